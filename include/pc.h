@@ -1,0 +1,247 @@
+/*
+ * pc.h -- C ABI of the MI355X (gfx950) spatio-temporal LiDAR range-image
+ * encoder.  The method is that of Feng, Liu and Zhu, "Real-Time
+ * Spatio-Temporal LiDAR Point Cloud Compression": a group of frames is
+ * projected to range images (Sec. III-B), the key frame is tiled and encoded
+ * with least-squares planes grown horizontally into runs [s, len, P]
+ * (Sec. III-C), the other frames reuse the key frame's planes after a rigid
+ * transform with only the plane offset free (Sec. III-D), and what no plane
+ * reproduces within the error bound eps is kept in a residual map whose
+ * streams are sized by an optimal Huffman code (Sec. III-A).
+ *
+ * Conventions for every entry point
+ *   - Pointers are DEVICE memory unless the comment says "host".
+ *   - Every call is asynchronous on the given HIP stream (`stream` is a
+ *     hipStream_t; NULL = the null stream).  The caller owns every buffer;
+ *     the library keeps no pointer to caller memory after a call returns,
+ *     except the workspace handed to pc_ctx_create.
+ *   - Argument errors are detected on the host before any launch and
+ *     returned as a negative pc_status; nothing is launched then.  Errors
+ *     that depend on data (a residual out of code range) set a sticky bit in
+ *     the frame's info block (pc_frame_info.status) and are reported by
+ *     pc_check() / by reading the info block after synchronising.
+ *   - Non-finite, zero-range and out-of-field-of-view input points are not
+ *     errors: they are dropped and counted.
+ *   - Alignment: device pointers 16 B aligned (PyTorch's allocator gives 512 B).
+ *   - A pc_ctx is not thread safe; use one per host thread / stream.
+ *   - GPU-path restrictions (return PC_ERR_UNSUPPORTED): W % 32 == 0,
+ *     W % tile_w == 0, H % tile_h == 0, tile_h*tile_w in {16, 32, 64} with a
+ *     compiled tile shape (4x4, 4x8, 4x16, 8x8).
+ */
+#ifndef PC_H
+#define PC_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PC_OK = 0,
+  PC_ERR_ARG = -1,          /* invalid argument (NULL buffer, bad size, eps <= 0 ...) */
+  PC_ERR_CAPACITY = -2,     /* a buffer or workspace is too small */
+  PC_ERR_DEVICE = -3,       /* a HIP runtime call failed */
+  PC_ERR_STATE = -4,        /* a sticky device error was found by pc_check */
+  PC_ERR_UNSUPPORTED = -5,  /* valid for the method, not supported by this GPU path */
+  PC_ERR_RANGE = -6         /* a residual could not be coded within eps (sticky) */
+} pc_status;
+
+/* Sensor geometry (host struct).  Row 0 is the top beam; elevations must be
+ * strictly descending.  Column u covers the clockwise azimuth interval
+ * (az0 - (u+1) 2pi/W, az0 - u 2pi/W] (Sec. III-B, Eq. (2): theta and phi are
+ * pixel coordinates at the sensor's angular resolution). */
+typedef struct {
+  int32_t H, W;             /* beams (rows), azimuth bins (columns) */
+  const float *elev_rad;    /* host, H beam elevations in radians */
+  float az0_rad;            /* leading edge of column 0 */
+} pc_sensor;
+
+/* Encoder parameters (host struct). */
+typedef struct {
+  float eps;                /* error bound on the range, metres, > 0 (Sec. III-C "threshold") */
+  int32_t tile_h, tile_w;   /* unit tile, rows x columns (Sec. III-C, e.g. 4x4) */
+  int32_t max_iter;         /* plane fits per tile, 1..8 (refit on reproduced points) */
+  int32_t min_pts;          /* fewest points a plane is fitted to, >= 3 */
+  float min_inlier_frac;    /* share of a tile's points its plane must reproduce, (0, 1] */
+} pc_params;
+
+/* Projection statistics (device struct, written by pc_project). */
+typedef struct {
+  int64_t n_in;             /* points given */
+  int64_t n_nonfinite;      /* non-finite coordinates or zero / overflowing range */
+  int64_t n_fov;            /* outside the vertical field of view or on the sensor axis */
+  int64_t n_collided;       /* landed on a pixel a nearer point kept (Sec. III-D) */
+  int64_t n_kept;           /* non-empty pixels */
+} pc_proj_stats;
+
+/* Sticky status bits in pc_frame_info.status */
+#define PC_STATUS_RANGE 1u  /* a residual exceeded the 16-bit code range or eps */
+
+/* Strip summary layout: 4 x 256 histogram words, then these counters. */
+#define PC_STRIP_STATS 16
+#define PC_STRIP_WORDS (4 * 256 + PC_STRIP_STATS)
+#define PC_SS_VALID 0       /* non-empty pixels */
+#define PC_SS_RES 1         /* residual pixels */
+#define PC_SS_TILES 2       /* 4 words: tiles per class */
+#define PC_SS_SRUNS 6       /* spatial runs */
+#define PC_SS_PRUNS 7       /* temporal runs */
+#define PC_SS_FITS 8        /* plane fits */
+#define PC_SS_FP64 9        /* FP64 eigen solves */
+#define PC_SS_STATUS 10     /* sticky status bits */
+#define PC_SS_SEEDED 11     /* seeded tiles accepted */
+#define PC_SS_FALLBACK 12   /* seeded tiles that fell back */
+
+/* Per-frame info block (device struct, first section of a frame stream). */
+typedef struct {
+  int32_t kind;             /* 0 = key frame, 1 = predicted frame */
+  uint32_t status;          /* sticky PC_STATUS_* bits */
+  int32_t n_sruns;          /* spatial runs [s, len, P] */
+  int32_t n_pruns;          /* temporal runs [s, len, c'] */
+  int64_t n_valid;          /* non-empty pixels */
+  int64_t n_res;            /* residual pixels */
+  int32_t tiles[4];         /* tiles per class: empty, unfit, spatial, temporal */
+  int32_t fits;             /* plane fits run (all iterations, all tiles) */
+  int32_t fp64_fits;        /* of which took the FP64 eigen path */
+  int32_t seeded;           /* tiles whose learned seed was accepted */
+  int32_t fallback;         /* tiles whose learned seed failed the check */
+  uint64_t stream_bytes[4]; /* serialized bytes of OCC, RUN, MASK, RES */
+  uint64_t coded_bits[4];   /* optimal Huffman cost of each stream */
+  uint64_t size_bytes;      /* header + coded streams + code tables */
+  float M[12];              /* rigid transform into the key frame (rows of [R|T]) */
+  int32_t pad[4];
+} pc_frame_info;
+
+/* A run of tiles in one tile row sharing one plane (Sec. III-C, [s, len, P]).
+ * The plane is p_k + a p_k1 + b p_k2 = c in the frame's coordinates, k the
+ * dominant axis of its normal and k1 < k2 the other two (Eq. (3) is k = x). */
+typedef struct {
+  int32_t s, len;           /* first tile column, number of tiles */
+  int32_t axis;             /* k: 0, 1, 2 */
+  float a, b, c;
+} pc_run;
+
+/* A temporal run: the key frame's run plane `krun` with offset c' (Sec. III-D). */
+typedef struct {
+  int32_t s, len;
+  int32_t krun;             /* slot of the key-frame run: row * TC + index in row */
+  float c;
+} pc_prun;
+
+/* Per-tile fit record (diagnostics and parity checks). */
+typedef struct {
+  float a, b, c;            /* own plane (valid when status >= 4) */
+  uint8_t axis, status, iters, t_status;   /* status: 0 empty, 1 few, 2 degenerate, 3 failed, 4 rejected, 5 accepted;
+                                              t_status: 0 none, 1 failed, 2 accepted */
+  uint64_t mask;            /* own plane's reproduced pixels, bit i*tw+k */
+  uint64_t t_mask;          /* temporal fit's reproduced pixels */
+  float t_c;                /* temporal offset c' */
+  uint8_t t_iters, seeded, pad[2];
+} pc_tile_rec;
+
+/* Section offsets (bytes) of one frame stream buffer.  Sizes:
+ * TR = H/tile_h tile rows, TC = W/tile_w tile columns, T = TR*TC. */
+typedef struct {
+  int32_t H, W, th, tw, TR, TC, T;
+  int32_t pad;
+  size_t bytes;             /* total size of the buffer */
+  size_t off_info;          /* pc_frame_info */
+  size_t off_occ;           /* uint32 words: bit (v*W+u) = pixel non-empty (OCC stream) */
+  size_t off_cls;           /* uint8[T]: 0 empty, 1 unfit, 2 spatial run, 3 temporal run */
+  size_t off_mask;          /* uint64[T]: pixels the covering plane reproduces */
+  size_t off_run_of;        /* int32[T]: covering run slot (spatial: slot; temporal: T + slot), -1 */
+  size_t off_nruns;         /* int32[2*TR]: spatial then temporal run count of each tile row */
+  size_t off_sruns;         /* pc_run[T]: tile row r's runs at slots r*TC .. */
+  size_t off_pruns;         /* pc_prun[T] */
+  size_t off_nres;          /* int32[TR]: residual pixels of each tile-row strip */
+  size_t off_res;           /* uint16[H*W]: strip r's codes (raster order) from r*tile_h*W */
+  size_t off_hist;          /* uint32[TR][PC_STRIP_WORDS]: per tile-row strip, the byte histograms
+                               of its OCC, RUN, MASK and RES bytes (4 x 256), then PC_STRIP_STATS
+                               counters (see PC_SS_*) */
+  size_t off_tiles;         /* pc_tile_rec[T] */
+} pc_layout;
+
+typedef struct pc_ctx pc_ctx;
+
+/* ---- set-up ------------------------------------------------------------ */
+
+/* Fill *out with the section offsets of a frame stream for this sensor and
+ * these parameters.  Returns PC_ERR_ARG / PC_ERR_UNSUPPORTED on bad input. */
+pc_status pc_stream_layout(const pc_sensor *sensor, const pc_params *params, pc_layout *out);
+
+/* Workspace a context needs to project frames of up to H*W pixels
+ * (8 bytes per pixel for the nearest-point keys). */
+size_t pc_workspace_size(const pc_sensor *sensor);
+
+/* Create a context on `device` using the caller's device workspace (at least
+ * pc_workspace_size bytes for every sensor used with it).  Sensor tables are
+ * computed on the host in FP64, rounded once to FP32, and uploaded on first
+ * use of each sensor (allocation happens there, never in the encode calls). */
+pc_status pc_ctx_create(pc_ctx **out, int device, void *workspace, size_t ws_bytes);
+pc_status pc_ctx_destroy(pc_ctx *ctx);
+
+/* Compute and upload the sensor's tables now (optional; otherwise done on
+ * first use).  Needed before capturing calls in a HIP graph. */
+pc_status pc_sensor_register(pc_ctx *ctx, const pc_sensor *sensor);
+
+/* Copy the sensor tables the GPU path uses to host arrays (for checks):
+ * cut[H+1], ebx[W], eby[W], ce[H], se[H], ca[W], sa[W]. */
+pc_status pc_sensor_tables(pc_ctx *ctx, const pc_sensor *sensor, float *cut, float *ebx, float *eby,
+                           float *ce, float *se, float *ca, float *sa);
+
+/* ---- the hot path -------------------------------------------------------- */
+
+/* Range-image conversion (Sec. III-B, Eq. (1)-(2)) of n points xyz[n][3]
+ * (FP32, any order), optionally moved into the key frame by M (host, 16 FP32,
+ * row-major 4x4, Eq. (6)).  Writes range[H][W] (FP32, 0 = empty) keeping the
+ * nearest point on collisions, ties to the lower index (Sec. III-D), the
+ * winning point's index src_idx[H][W] (-1 = empty; may be NULL) and stats
+ * (may be NULL).  Uses the context workspace. */
+pc_status pc_project(pc_ctx *ctx, const float *xyz, int64_t n, const float *M_host,
+                     const pc_sensor *sensor, float *range, int32_t *src_idx,
+                     pc_proj_stats *stats, void *stream);
+
+/* Spatial encoding of a key frame (Sec. III-C) from its range image into the
+ * frame stream buffer `out` (pc_layout.bytes bytes, laid out by
+ * pc_stream_layout).  Per tile: least-squares plane (FP32 moments, FP64 when
+ * the two smallest eigenvalues are close), refit on reproduced pixels up to
+ * max_iter times; per tile row: horizontal run growth; residual pixels
+ * quantised with step 2 eps (1 - 2^-8); per-strip byte histograms; then the
+ * optimal Huffman size into the info block.  `seed` (may be NULL) holds
+ * per-tile normal seeds [T][4] (n_x, n_y, n_z, planarity logit) from
+ * pc_net_forward: a seeded tile takes one refit from the seed and keeps it
+ * when it passes the same acceptance test, else runs the plain fit. */
+pc_status pc_fit_key(pc_ctx *ctx, const float *range, const pc_sensor *sensor,
+                     const pc_params *params, const float *seed, void *out, void *stream);
+
+/* Temporal encoding of a predicted frame (Sec. III-D) against the key
+ * frame's stream `key` (same sensor and parameters): each tile covered by a
+ * key run reuses that run's normal with the offset c' free; temporal runs
+ * grow within one key run; remaining tiles are encoded spatially.  `range` is
+ * the predicted frame's range image in the key frame's grid (pc_project with
+ * its transform); M_host (16 FP32, may be NULL) is recorded in the info block. */
+pc_status pc_encode_pred(pc_ctx *ctx, const void *key, const float *range, const float *M_host,
+                         const pc_sensor *sensor, const pc_params *params, void *out, void *stream);
+
+/* Decode a frame stream to range_out[H][W] (0 = empty): plane pixels by
+ * casting the pixel-centre ray onto the run plane (Sec. III-C), residual
+ * pixels as code * step.  `key` is the key frame's stream for a predicted
+ * frame (NULL for a key frame). */
+pc_status pc_decode(pc_ctx *ctx, const void *key, const void *frame, const pc_sensor *sensor,
+                    const pc_params *params, float *range_out, void *stream);
+
+/* Synchronise the context's last stream and scan the given frame info
+ * blocks (device pointers to pc_frame_info; may be 0 of them) for sticky
+ * errors.  Returns PC_ERR_RANGE if any frame has PC_STATUS_RANGE set. */
+pc_status pc_check(pc_ctx *ctx, void *stream, const void *const *frames, int32_t nframes);
+
+/* Thread-local message for the last error returned on this thread. */
+const char *pc_last_error(void);
+
+/* Library version string. */
+const char *pc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -230,6 +230,71 @@ pc_status pc_encode_pred(pc_ctx *ctx, const void *key, const float *range, const
 pc_status pc_decode(pc_ctx *ctx, const void *key, const void *frame, const pc_sensor *sensor,
                     const pc_params *params, float *range_out, void *stream);
 
+/* ---- batched encoding ------------------------------------------------------
+ * Many frames of many sensors (and groups of frames with their key frames)
+ * encoded by one replay of a HIP graph: every frame's points are projected
+ * and binned by tile-row strip, the key frames' strips are encoded, then
+ * the predicted frames' strips, then every frame's size.  Each strip's work
+ * item builds its strip's range image in LDS from its bin (nearest point
+ * wins) -- the range images never go through device memory unless asked
+ * for.  Encoding work is pulled in (frame, strip) items from an atomic queue
+ * by persistent work-groups.  Each frame's stream equals what pc_project +
+ * pc_fit_key / pc_encode_pred give for it. */
+typedef struct {
+  const float *xyz;          /* device, n x 3 FP32 points in the frame's own coordinates */
+  int64_t n;
+  const float *M;            /* host 16 FP32 (read at create): transform into the key frame; NULL for key frames */
+  const pc_sensor *sensor;   /* host, read at create */
+  const pc_params *params;   /* host, read at create; a predicted frame's tile shape equals its key frame's */
+  int32_t key;               /* batch index of the frame's key frame (its own index for a key frame) */
+  int32_t pad;
+  const float *seed;         /* device per-tile seeds for a key frame (as pc_fit_key), or NULL */
+  float *range;              /* device H*W FP32: receives the frame's range image (0 = empty); NULL = not written */
+  void *out;                 /* device frame stream buffer (pc_stream_layout bytes) */
+} pc_frame_desc;
+
+typedef struct {
+  int32_t persistent;        /* 1: persistent work-groups pull strips from an atomic queue; 0: a work-group per strip */
+  int32_t graph;             /* 1: capture the batch in a HIP graph at the first run and replay it afterwards */
+  int32_t blocks_per_cu;     /* persistent grid = CUs * this (at most one work-group per item); 0 = 4 */
+} pc_batch_opts;
+
+typedef struct pc_batch pc_batch;
+
+/* Device workspace a batch plan needs (descriptor table, work items, block
+ * tables, counters, and 8 bytes per point for the strip bins). */
+size_t pc_batch_workspace_size(const pc_frame_desc *frames, int32_t nframes);
+
+/* Check the frames, build and upload the descriptor table into the
+ * workspace.  The workspace, the frames' xyz, range and out buffers must stay
+ * valid until pc_batch_destroy.  opts may be NULL (persistent, graph).
+ * Besides the per-frame restrictions: at most 256 tile-row strips per frame
+ * (PC_ERR_UNSUPPORTED), and a predicted frame's key frame must be in the
+ * same batch with the same sensor size and tile shape (PC_ERR_ARG). */
+pc_status pc_batch_create(pc_ctx *ctx, const pc_frame_desc *frames, int32_t nframes, const pc_batch_opts *opts,
+                          void *workspace, size_t ws_bytes, pc_batch **out);
+
+/* Encode the whole batch on `stream` (asynchronous). */
+pc_status pc_batch_run(pc_batch *batch, void *stream);
+
+/* Work items (strips), launch groups (one per kind and tile shape) and the
+ * largest persistent grid of a plan. */
+pc_status pc_batch_info(const pc_batch *batch, int32_t *nitems, int32_t *ngroups, int32_t *grid_max);
+
+/* Run the batch once without the graph, recording a HIP event after every
+ * launch; ms[i] is the duration of launch i and kinds[i] its PC_LAUNCH_* kind
+ * (kinds may be NULL).  Synchronises the stream.  For measurement only. */
+#define PC_LAUNCH_RESET 0
+#define PC_LAUNCH_COUNT 1     /* projection, points per strip */
+#define PC_LAUNCH_OFFSETS 2
+#define PC_LAUNCH_SCATTER 3   /* projection, points into their strips' buckets */
+#define PC_LAUNCH_KEY 4
+#define PC_LAUNCH_PRED 5
+#define PC_LAUNCH_FINISH 6
+pc_status pc_batch_profile(pc_batch *batch, void *stream, float *ms, int32_t *kinds, int32_t cap, int32_t *count);
+
+pc_status pc_batch_destroy(pc_batch *batch);
+
 /* Synchronise the context's last stream and scan the given frame info
  * blocks (device pointers to pc_frame_info; may be 0 of them) for sticky
  * errors.  Returns PC_ERR_RANGE if any frame has PC_STATUS_RANGE set. */

@@ -116,6 +116,11 @@ static EncParams enc_params(const pc_params *p) {
   double st = 2.0 * (double)p->eps * (1.0 - 1.0 / 256.0);
   e.step = (float)st;
   e.inv = (float)(1.0 / (double)e.step);
+  for (int n = 0; n < 72; n++) {
+    int a = n < p->min_pts ? n : p->min_pts;
+    int b = (int)ceil((double)p->min_inlier_frac * (double)n);
+    e.need[n] = (uint8_t)(n > 64 ? 0 : (a > b ? a : b));
+  }
   return e;
 }
 
@@ -123,10 +128,31 @@ static EncParams enc_params(const pc_params *p) {
 // FP64 trigonometry rounded once to FP32; row cuts at the elevation midpoints,
 // field of view half a beam gap beyond the outer beams; columns advance
 // clockwise from az0 (Sec. III-B, Eq. (2)).
+// Table offsets (floats) in the one device allocation; every table starts
+// on a 16-byte boundary so kernels may read it with 128-bit loads.
+struct TableOffsets {
+  size_t cut, ebx, eby, ce, se, ca, sa, total;
+};
+static TableOffsets table_offsets(int H, int W) {
+  auto pad = [](size_t n) { return (n + 3) & ~(size_t)3; };
+  TableOffsets o;
+  o.cut = 0;
+  o.ebx = o.cut + pad(H + 1);
+  o.eby = o.ebx + pad(W);
+  o.ce = o.eby + pad(W);
+  o.se = o.ce + pad(H);
+  o.ca = o.se + pad(H);
+  o.sa = o.ca + pad(W);
+  o.total = o.sa + pad(W);
+  return o;
+}
+
 static void sensor_tables_host(const pc_sensor *s, std::vector<float> &t) {
   const int H = s->H, W = s->W;
-  t.assign((size_t)(H + 1) + 2 * W + 2 * H + 2 * W, 0.0f);
-  float *cut = t.data(), *ebx = cut + H + 1, *eby = ebx + W, *ce = eby + W, *se = ce + H, *ca = se + H, *sa = ca + W;
+  TableOffsets o = table_offsets(H, W);
+  t.assign(o.total, 0.0f);
+  float *cut = t.data() + o.cut, *ebx = t.data() + o.ebx, *eby = t.data() + o.eby, *ce = t.data() + o.ce,
+        *se = t.data() + o.se, *ca = t.data() + o.ca, *sa = t.data() + o.sa;
   double e0 = s->elev_rad[0], e1 = s->elev_rad[1];
   double eh = s->elev_rad[H - 1], eh1 = s->elev_rad[H - 2];
   cut[0] = (float)tan(e0 + 0.5 * (e0 - e1));
@@ -168,22 +194,38 @@ static pc_status get_sensor(pc_ctx *ctx, const pc_sensor *s, SensorEntry **out) 
     return set_error(PC_ERR_DEVICE, "sensor table upload failed");
   }
   const int H = s->H, W = s->W;
+  TableOffsets o = table_offsets(H, W);
   SensorDev &d = e->sd;
   d.H = H;
   d.W = W;
-  d.cut = e->dev;
-  d.ebx = d.cut + H + 1;
-  d.eby = d.ebx + W;
-  d.ce = d.eby + W;
-  d.se = d.ce + H;
-  d.ca = d.se + H;
-  d.sa = d.ca + W;
-  d.beta0 = (float)atan2((double)t[H + 1 + W], (double)t[H + 1]);
+  d.cut = e->dev + o.cut;
+  d.ebx = e->dev + o.ebx;
+  d.eby = e->dev + o.eby;
+  d.ce = e->dev + o.ce;
+  d.se = e->dev + o.se;
+  d.ca = e->dev + o.ca;
+  d.sa = e->dev + o.sa;
+  d.beta0 = (float)atan2((double)t[o.eby], (double)t[o.ebx]);
   d.dth = (float)(6.283185307179586476925286766559 / (double)W);
   ctx->sensors.push_back(e);
   *out = e;
   return PC_OK;
 }
+
+// helpers for the batch planner (batch.hip)
+pc_status pcc_sensor_dev(pc_ctx *ctx, const pc_sensor *s, SensorDev *out) {
+  SensorEntry *e;
+  pc_status st = get_sensor(ctx, s, &e);
+  if (st == PC_OK) *out = e->sd;
+  return st;
+}
+pc_status pcc_check_all(const pc_sensor *s, const pc_params *p) {
+  pc_status st = check_sensor(s);
+  if (st == PC_OK) st = check_params(s, p);
+  return st;
+}
+EncParams pcc_enc_params(const pc_params *p) { return enc_params(p); }
+int pcc_ctx_device(pc_ctx *ctx) { return ctx->device; }
 
 // ------------------------------------------------------------------ the ABI
 extern "C" {
@@ -271,23 +313,17 @@ pc_status pc_sensor_tables(pc_ctx *ctx, const pc_sensor *sensor, float *cut, flo
   SensorEntry *e;
   if ((st = get_sensor(ctx, sensor, &e))) return st;
   const int H = sensor->H, W = sensor->W;
-  std::vector<float> t((size_t)(H + 1) + 4 * W + 2 * H);
+  TableOffsets o = table_offsets(H, W);
+  std::vector<float> t(o.total);
   if (hipMemcpy(t.data(), e->dev, sizeof(float) * t.size(), hipMemcpyDeviceToHost) != hipSuccess)
     return set_error(PC_ERR_DEVICE, "table read-back failed");
-  const float *p = t.data();
-  if (cut) memcpy(cut, p, sizeof(float) * (H + 1));
-  p += H + 1;
-  if (ebx) memcpy(ebx, p, sizeof(float) * W);
-  p += W;
-  if (eby) memcpy(eby, p, sizeof(float) * W);
-  p += W;
-  if (ce) memcpy(ce, p, sizeof(float) * H);
-  p += H;
-  if (se) memcpy(se, p, sizeof(float) * H);
-  p += H;
-  if (ca) memcpy(ca, p, sizeof(float) * W);
-  p += W;
-  if (sa) memcpy(sa, p, sizeof(float) * W);
+  if (cut) memcpy(cut, t.data() + o.cut, sizeof(float) * (H + 1));
+  if (ebx) memcpy(ebx, t.data() + o.ebx, sizeof(float) * W);
+  if (eby) memcpy(eby, t.data() + o.eby, sizeof(float) * W);
+  if (ce) memcpy(ce, t.data() + o.ce, sizeof(float) * H);
+  if (se) memcpy(se, t.data() + o.se, sizeof(float) * H);
+  if (ca) memcpy(ca, t.data() + o.ca, sizeof(float) * W);
+  if (sa) memcpy(sa, t.data() + o.sa, sizeof(float) * W);
   return PC_OK;
 }
 

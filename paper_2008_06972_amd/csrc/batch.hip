@@ -1,0 +1,599 @@
+// Batched encoding of many frames of many sensors in one HIP graph.
+//
+// A plan holds a device table of frame descriptors.  One replay runs:
+//   reset    zero the strip counters and queue counters (a kernel, so the
+//            graph holds no memset node)
+//   count    project every point (Eq. (1), (2), (6)) and count the points
+//            falling in each (frame, tile-row strip); one global atomic per
+//            (work-group, strip)
+//   offsets  per frame, exclusive sum of the strip counts
+//   scatter  project again and write each point as (pixel within its strip,
+//            range bits) into its strip's bucket, reserving space once per
+//            (work-group, strip)
+//   key      persistent work-groups pull (key frame, strip) items from an
+//            atomic counter; each builds its strip from the bucket with LDS
+//            atomicMin (nearest point wins, Sec. III-D) and encodes it
+//   pred     the same for the predicted frames' strips
+//   finish   one block per frame: totals and the Huffman size
+// Device-wide atomics are slow on this chip (a few tens of billions per
+// second): binning keeps them to a few per 2048 points, and the per-pixel
+// minimum happens in LDS.  The range image never goes through HBM.
+// Phases are separate kernels, so a predicted strip never waits inside a
+// kernel for its key strip.  Items are grouped by tile shape; each group is
+// one launch per phase.
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "encode_strip.h"
+
+namespace pcc {
+
+constexpr int kBinPts = 8;                 // points per thread in the binning passes
+constexpr int kBinBlock = 256;
+constexpr int kBinChunk = kBinPts * kBinBlock;
+
+struct FrameDescDev {
+  const float *xyz;
+  int64_t n;
+  Mat12 M;
+  int hasM;
+  int kind;        // 0 key, 1 predicted
+  int key;         // descriptor index of the key frame
+  int pad0;
+  SensorDev s;
+  EncParams p;
+  uint2 *bucket;   // n entries: (pixel within strip, range bits)
+  int *bcount;     // [TR] points per strip
+  int *boff;       // [TR] first bucket entry of each strip
+  int *bcur;       // [TR] scatter cursors
+  float *range_out;
+  const float *seed;
+  FrameDev f;
+};
+
+__global__ void k_batch_reset(int *a, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) a[i] = 0;
+}
+
+__device__ __forceinline__ int b_row_of(const float *cut, int H, float q) {
+  int lo = 1, hi = H;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (cut[mid] > q) lo = mid + 1; else hi = mid;
+  }
+  return lo - 1;
+}
+
+__device__ __forceinline__ float b_edge_side(const SensorDev &s, int u, float x, float y) {
+  float t = s.eby[u] * x;
+  return fmaf(s.ebx[u], y, -t);
+}
+
+__device__ __forceinline__ int b_column_of(const SensorDev &s, float x, float y) {
+  int W = s.W;
+  float rel = s.beta0 - atan2f(y, x);
+  int u = (int)floorf(rel / s.dth);
+  u %= W;
+  if (u < 0) u += W;
+  for (int step = 0; step <= W + 2; step++) {
+    if (b_edge_side(s, u, x, y) > 0.0f) { u = (u == 0) ? W - 1 : u - 1; continue; }
+    int un = (u + 1 == W) ? 0 : u + 1;
+    if (b_edge_side(s, un, x, y) <= 0.0f) { u = un; continue; }
+    return u;
+  }
+  return -1;
+}
+
+// The per-frame projection's arithmetic (Eq. (1), (2), (6)); false if the
+// point is dropped (non-finite, zero range, on the axis, outside the FOV).
+__device__ __forceinline__ bool project_point(const FrameDescDev &D, int64_t i, int &v, int &u, float &r) {
+  float x = D.xyz[3 * i], y = D.xyz[3 * i + 1], z = D.xyz[3 * i + 2];
+  if (D.hasM) {
+    const float *m = D.M.m;
+    float xx = fmaf(m[0], x, fmaf(m[1], y, fmaf(m[2], z, m[3])));
+    float yy = fmaf(m[4], x, fmaf(m[5], y, fmaf(m[6], z, m[7])));
+    float zz = fmaf(m[8], x, fmaf(m[9], y, fmaf(m[10], z, m[11])));
+    x = xx; y = yy; z = zz;
+  }
+  if (!isfinite(x) || !isfinite(y) || !isfinite(z)) return false;
+  float yy2 = y * y;
+  float rho2 = fmaf(x, x, yy2);
+  float zz2 = z * z;
+  r = sqrtf(fmaf(x, x, fmaf(y, y, zz2)));
+  if (!isfinite(r) || r == 0.0f || rho2 < 1e-12f) return false;
+  float q = z / sqrtf(rho2);
+  const SensorDev &s = D.s;
+  if (!(q < s.cut[0]) || q < s.cut[s.H]) return false;
+  v = b_row_of(s.cut, s.H, q);
+  u = b_column_of(s, x, y);
+  return u >= 0;
+}
+
+// blocks [first[f], first[f+1]) belong to frame f; owner[b] = f
+__global__ void __launch_bounds__(kBinBlock) k_batch_count(const FrameDescDev *__restrict__ d, const int *__restrict__ owner,
+                                                           const int *__restrict__ first) {
+  __shared__ int hist[256];
+  const int fidx = owner[blockIdx.x];
+  const FrameDescDev &D = d[fidx];
+  const int th = D.p.th, TR = D.f.TR;
+  for (int t = threadIdx.x; t < TR; t += kBinBlock) hist[t] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)(blockIdx.x - first[fidx]) * kBinChunk;
+#pragma unroll 2
+  for (int q = 0; q < kBinPts; q++) {
+    int64_t i = base + q * kBinBlock + threadIdx.x;
+    int v, u;
+    float r;
+    if (i < D.n && project_point(D, i, v, u, r)) atomicAdd(&hist[v / th], 1);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < TR; t += kBinBlock)
+    if (hist[t]) atomicAdd(&D.bcount[t], hist[t]);
+}
+
+__global__ void k_batch_offsets(const FrameDescDev *__restrict__ d, int nframes) {
+  int fidx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (fidx >= nframes) return;
+  const FrameDescDev &D = d[fidx];
+  int run = 0;
+  for (int t = 0; t < D.f.TR; t++) {
+    D.boff[t] = run;
+    D.bcur[t] = run;
+    run += D.bcount[t];
+  }
+}
+
+__global__ void __launch_bounds__(kBinBlock) k_batch_scatter(const FrameDescDev *__restrict__ d,
+                                                             const int *__restrict__ owner, const int *__restrict__ first) {
+  __shared__ int cnt[256], base[256], lim[256];
+  const int fidx = owner[blockIdx.x];
+  const FrameDescDev &D = d[fidx];
+  const int th = D.p.th, TR = D.f.TR, W = D.s.W;
+  for (int t = threadIdx.x; t < TR; t += kBinBlock) cnt[t] = 0;
+  __syncthreads();
+  const int64_t b0 = (int64_t)(blockIdx.x - first[fidx]) * kBinChunk;
+  int strip[kBinPts], slot[kBinPts];
+  uint32_t px[kBinPts], rb[kBinPts];
+#pragma unroll
+  for (int q = 0; q < kBinPts; q++) {
+    int64_t i = b0 + q * kBinBlock + threadIdx.x;
+    int v, u;
+    float r;
+    strip[q] = -1;
+    slot[q] = 0;
+    px[q] = 0;
+    rb[q] = 0;
+    if (i < D.n && project_point(D, i, v, u, r)) {
+      strip[q] = v / th;
+      slot[q] = atomicAdd(&cnt[strip[q]], 1);
+      px[q] = (uint32_t)((v - strip[q] * th) * W + u);
+      rb[q] = __float_as_uint(r);
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < TR; t += kBinBlock)
+    if (cnt[t]) {
+      base[t] = atomicAdd(&D.bcur[t], cnt[t]);
+      lim[t] = D.boff[t] + D.bcount[t];
+    }
+  __syncthreads();
+  // The two passes project identically, so every entry fits its strip's
+  // range; the limit only keeps a bucket from spilling into its neighbour.
+#pragma unroll
+  for (int q = 0; q < kBinPts; q++)
+    if (strip[q] >= 0) {
+      int at = base[strip[q]] + slot[q];
+      if (at < lim[strip[q]]) D.bucket[at] = make_uint2(px[q], rb[q]);
+    }
+}
+
+__device__ __forceinline__ StripSrc src_of(const FrameDescDev &D) {
+  return StripSrc{nullptr, D.bucket, D.bcount, D.boff, D.range_out};
+}
+
+template <int TH, int TW>
+__global__ void __launch_bounds__(kBlock) k_batch_key(const FrameDescDev *__restrict__ d, const int2 *__restrict__ items,
+                                                      int nitems, int *counter) {
+  extern __shared__ __align__(16) char smem_raw[];
+  __shared__ int s_item;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = s_item;
+    if (it >= nitems) break;
+    const int2 fi = items[it];
+    const FrameDescDev &D = d[fi.x];
+    key_strip<TH, TW>(smem_raw, src_of(D), D.s, D.p, D.seed, D.f, fi.y);
+  }
+}
+
+template <int TH, int TW>
+__global__ void __launch_bounds__(kBlock) k_batch_pred(const FrameDescDev *__restrict__ d, const int2 *__restrict__ items,
+                                                       int nitems, int *counter) {
+  extern __shared__ __align__(16) char smem_raw[];
+  __shared__ int s_item;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = s_item;
+    if (it >= nitems) break;
+    const int2 fi = items[it];
+    const FrameDescDev &D = d[fi.x];
+    pred_strip<TH, TW>(smem_raw, d[D.key].f, src_of(D), D.s, D.p, D.f, fi.y);
+  }
+}
+
+// One work-group per strip (no queue), for comparison and for the autotuner.
+template <int TH, int TW>
+__global__ void __launch_bounds__(kBlock) k_batch_key_grid(const FrameDescDev *__restrict__ d, const int2 *__restrict__ items) {
+  extern __shared__ __align__(16) char smem_raw[];
+  const int2 fi = items[blockIdx.x];
+  const FrameDescDev &D = d[fi.x];
+  key_strip<TH, TW>(smem_raw, src_of(D), D.s, D.p, D.seed, D.f, fi.y);
+}
+
+template <int TH, int TW>
+__global__ void __launch_bounds__(kBlock) k_batch_pred_grid(const FrameDescDev *__restrict__ d, const int2 *__restrict__ items) {
+  extern __shared__ __align__(16) char smem_raw[];
+  const int2 fi = items[blockIdx.x];
+  const FrameDescDev &D = d[fi.x];
+  pred_strip<TH, TW>(smem_raw, d[D.key].f, src_of(D), D.s, D.p, D.f, fi.y);
+}
+
+__global__ void __launch_bounds__(256) k_batch_finish(const FrameDescDev *__restrict__ d) {
+  const FrameDescDev &D = d[blockIdx.x];
+  finish_frame(D.f, D.kind, D.M, D.hasM);
+}
+
+// ------------------------------------------------------------------ host
+struct Group {
+  int th, tw, kind;
+  int first, count;     // slice of the item array
+  size_t smem;
+  int grid;
+};
+
+struct BatchPlan {
+  int device = 0;
+  int nframes = 0;
+  FrameDescDev *d_desc = nullptr;
+  int2 *d_items = nullptr;
+  int *d_bin_owner = nullptr, *d_bin_first = nullptr;
+  int *d_counters = nullptr;     // queue counters (64), then the frames' strip counts
+  int64_t ncounters = 0;
+  int bin_blocks = 0;
+  std::vector<Group> groups;
+  int persistent = 1;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  int use_graph = 0;
+};
+
+template <int TH, int TW>
+static const void *key_fn(bool persistent) {
+  return persistent ? (const void *)k_batch_key<TH, TW> : (const void *)k_batch_key_grid<TH, TW>;
+}
+template <int TH, int TW>
+static const void *pred_fn(bool persistent) {
+  return persistent ? (const void *)k_batch_pred<TH, TW> : (const void *)k_batch_pred_grid<TH, TW>;
+}
+
+static const void *group_fn(const Group &g, bool persistent) {
+  if (g.th == 4 && g.tw == 4) return g.kind ? pred_fn<4, 4>(persistent) : key_fn<4, 4>(persistent);
+  if (g.th == 4 && g.tw == 8) return g.kind ? pred_fn<4, 8>(persistent) : key_fn<4, 8>(persistent);
+  if (g.th == 4 && g.tw == 16) return g.kind ? pred_fn<4, 16>(persistent) : key_fn<4, 16>(persistent);
+  if (g.th == 8 && g.tw == 8) return g.kind ? pred_fn<8, 8>(persistent) : key_fn<8, 8>(persistent);
+  return nullptr;
+}
+
+static size_t group_smem(int th, int tw, int W, bool pred) {
+  if (th == 4 && tw == 4) return StripSmem<4, 4>::bytes(W, W / 4, pred);
+  if (th == 4 && tw == 8) return StripSmem<4, 8>::bytes(W, W / 8, pred);
+  if (th == 4 && tw == 16) return StripSmem<4, 16>::bytes(W, W / 16, pred);
+  return StripSmem<8, 8>::bytes(W, W / 8, pred);
+}
+
+// All launches of one batch, in order; mark(kind) follows each (PC_LAUNCH_*).
+template <class Mark>
+static hipError_t batch_launches(BatchPlan &P, hipStream_t st, Mark mark) {
+  const int ngroups = (int)P.groups.size();
+  int rb = (int)std::min<int64_t>(1024, (P.ncounters + 255) / 256);
+  hipLaunchKernelGGL(k_batch_reset, dim3(rb), dim3(256), 0, st, P.d_counters, P.ncounters);
+  mark(PC_LAUNCH_RESET);
+  if (P.bin_blocks) {
+    hipLaunchKernelGGL(k_batch_count, dim3(P.bin_blocks), dim3(kBinBlock), 0, st, P.d_desc, P.d_bin_owner, P.d_bin_first);
+    mark(PC_LAUNCH_COUNT);
+  }
+  hipLaunchKernelGGL(k_batch_offsets, dim3((P.nframes + 63) / 64), dim3(64), 0, st, P.d_desc, P.nframes);
+  mark(PC_LAUNCH_OFFSETS);
+  if (P.bin_blocks) {
+    hipLaunchKernelGGL(k_batch_scatter, dim3(P.bin_blocks), dim3(kBinBlock), 0, st, P.d_desc, P.d_bin_owner, P.d_bin_first);
+    mark(PC_LAUNCH_SCATTER);
+  }
+  for (int pass = 0; pass < 2; pass++) {      // key groups, then predicted groups
+    for (int gi = 0; gi < ngroups; gi++) {
+      const Group &g = P.groups[gi];
+      if (g.kind != pass || g.count == 0) continue;
+      const void *fn = group_fn(g, P.persistent != 0);
+      const int2 *items = P.d_items + g.first;
+      int nitems = g.count;
+      int *counter = P.d_counters + gi;
+      hipError_t e;
+      if (P.persistent) {
+        void *args[] = {(void *)&P.d_desc, (void *)&items, (void *)&nitems, (void *)&counter};
+        e = hipLaunchKernel(fn, dim3(g.grid), dim3(kBlock), args, g.smem, st);
+      } else {
+        void *args[] = {(void *)&P.d_desc, (void *)&items};
+        e = hipLaunchKernel(fn, dim3(g.count), dim3(kBlock), args, g.smem, st);
+      }
+      if (e != hipSuccess) return e;
+      mark(pass == 0 ? PC_LAUNCH_KEY : PC_LAUNCH_PRED);
+    }
+  }
+  hipLaunchKernelGGL(k_batch_finish, dim3(P.nframes), dim3(256), 0, st, P.d_desc);
+  mark(PC_LAUNCH_FINISH);
+  return hipGetLastError();
+}
+
+}  // namespace pcc
+
+// ---------------------------------------------------------------- the ABI
+using namespace pcc;
+
+struct pc_batch {
+  BatchPlan plan;
+};
+
+// defined in api.hip
+pc_status pcc_sensor_dev(pc_ctx *ctx, const pc_sensor *s, SensorDev *out);
+pc_status pcc_check_all(const pc_sensor *s, const pc_params *p);
+EncParams pcc_enc_params(const pc_params *p);
+int pcc_ctx_device(pc_ctx *ctx);
+
+static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct BatchSizes {
+  size_t desc, items, bins, counters, buckets, total;
+  int nitems, bin_blocks;
+  int64_t strips;
+};
+
+static pc_status batch_sizes(const pc_frame_desc *frames, int32_t nframes, BatchSizes &B) {
+  memset(&B, 0, sizeof B);
+  int64_t items = 0, bb = 0, strips = 0;
+  size_t buckets = 0;
+  for (int i = 0; i < nframes; i++) {
+    const pc_frame_desc &F = frames[i];
+    if (!F.sensor || !F.params) return set_error(PC_ERR_ARG, "frame %d: sensor or params is NULL", i);
+    if (F.n < 0) return set_error(PC_ERR_ARG, "frame %d: negative point count", i);
+    int tr = F.sensor->H / (F.params->tile_h > 0 ? F.params->tile_h : 1);
+    items += tr;
+    strips += tr;
+    bb += (F.n + kBinChunk - 1) / kBinChunk;
+    buckets += a256(sizeof(uint2) * (size_t)F.n);
+  }
+  if (items > 0x7fffffff || bb > 0x7fffffff) return set_error(PC_ERR_CAPACITY, "batch too large");
+  B.nitems = (int)items;
+  B.bin_blocks = (int)bb;
+  B.strips = strips;
+  B.desc = a256(sizeof(FrameDescDev) * (size_t)nframes);
+  B.items = a256(sizeof(int2) * (size_t)items);
+  B.bins = a256(sizeof(int) * ((size_t)bb + (size_t)nframes));
+  B.counters = a256(sizeof(int) * (64 + 3 * (size_t)strips));
+  B.buckets = buckets;
+  B.total = B.desc + B.items + B.bins + B.counters + B.buckets;
+  return PC_OK;
+}
+
+extern "C" {
+
+size_t pc_batch_workspace_size(const pc_frame_desc *frames, int32_t nframes) {
+  BatchSizes B;
+  if (!frames || nframes <= 0 || batch_sizes(frames, nframes, B) != PC_OK) return 0;
+  return B.total;
+}
+
+pc_status pc_batch_create(pc_ctx *ctx, const pc_frame_desc *frames, int32_t nframes, const pc_batch_opts *opts,
+                          void *workspace, size_t ws_bytes, pc_batch **out) {
+  if (!ctx || !out) return set_error(PC_ERR_ARG, "ctx or output is NULL");
+  if (!frames || nframes <= 0) return set_error(PC_ERR_ARG, "no frames");
+  BatchSizes B;
+  pc_status st = batch_sizes(frames, nframes, B);
+  if (st) return st;
+  if (!workspace || ws_bytes < B.total)
+    return set_error(PC_ERR_CAPACITY, "batch workspace %zu bytes < %zu needed", ws_bytes, B.total);
+  pc_batch_opts o = opts ? *opts : pc_batch_opts{1, 1, 0};
+  if (o.blocks_per_cu < 0) return set_error(PC_ERR_ARG, "blocks_per_cu must be >= 0");
+  char *ws = (char *)workspace;
+  int *counters = (int *)(ws + B.desc + B.items + B.bins);
+  int *strip_counts = counters + 64;
+  char *bucket_ws = ws + B.desc + B.items + B.bins + B.counters;
+  std::vector<FrameDescDev> desc((size_t)nframes);
+  int64_t strip_at = 0;
+  for (int i = 0; i < nframes; i++) {
+    const pc_frame_desc &F = frames[i];
+    if ((st = pcc_check_all(F.sensor, F.params))) return st;
+    if (F.n > 0x7fffffffLL || (F.n > 0 && !F.xyz)) return set_error(PC_ERR_ARG, "frame %d: bad points", i);
+    if (!F.out) return set_error(PC_ERR_ARG, "frame %d: output stream is NULL", i);
+    if (F.key < 0 || F.key >= nframes) return set_error(PC_ERR_ARG, "frame %d: key index out of range", i);
+    const pc_frame_desc &K = frames[F.key];
+    if (K.key != F.key) return set_error(PC_ERR_ARG, "frame %d: its key frame %d is not a key frame", i, F.key);
+    if (K.sensor->H != F.sensor->H || K.sensor->W != F.sensor->W || K.params->tile_h != F.params->tile_h ||
+        K.params->tile_w != F.params->tile_w)
+      return set_error(PC_ERR_ARG, "frame %d: sensor or tile shape differs from its key frame", i);
+    if (F.M && F.key != i)
+      for (int q = 0; q < 16; q++)
+        if (!std::isfinite(F.M[q])) return set_error(PC_ERR_ARG, "frame %d: transform has a non-finite entry", i);
+    FrameDescDev &D = desc[i];
+    memset(&D, 0, sizeof D);
+    D.xyz = F.xyz;
+    D.n = F.n;
+    D.hasM = (F.M && F.key != i) ? 1 : 0;
+    for (int q = 0; q < 12; q++) D.M.m[q] = D.hasM ? F.M[q] : (q % 5 == 0 ? 1.f : 0.f);
+    D.kind = F.key == i ? 0 : 1;
+    D.key = F.key;
+    if ((st = pcc_sensor_dev(ctx, F.sensor, &D.s))) return st;
+    D.p = pcc_enc_params(F.params);
+    pc_layout L;
+    pc_stream_layout(F.sensor, F.params, &L);
+    if (L.TR > 256) return set_error(PC_ERR_UNSUPPORTED, "frame %d: more than 256 tile-row strips", i);
+    D.f = frame_dev(F.out, L);
+    D.bucket = (uint2 *)bucket_ws;
+    bucket_ws += a256(sizeof(uint2) * (size_t)F.n);
+    D.bcount = strip_counts + strip_at;
+    D.boff = strip_counts + B.strips + strip_at;
+    D.bcur = strip_counts + 2 * B.strips + strip_at;
+    strip_at += L.TR;
+    D.range_out = F.range;
+    D.seed = F.seed;
+  }
+  // items grouped by (kind, tile shape); inside a group, frames in order
+  pc_batch *b = new pc_batch();
+  BatchPlan &P = b->plan;
+  P.device = pcc_ctx_device(ctx);
+  P.nframes = nframes;
+  P.persistent = o.persistent;
+  P.use_graph = o.graph;
+  std::vector<int2> items;
+  items.reserve(B.nitems);
+  int cus = 0;
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P.device);
+  const int shapes[4][2] = {{4, 4}, {4, 8}, {4, 16}, {8, 8}};
+  for (int kind = 0; kind < 2; kind++)
+    for (auto &sh : shapes) {
+      Group g{sh[0], sh[1], kind, (int)items.size(), 0, 0, 0};
+      int maxW = 0;
+      for (int i = 0; i < nframes; i++) {
+        if (desc[i].kind != kind || desc[i].p.th != sh[0] || desc[i].p.tw != sh[1]) continue;
+        for (int tr = 0; tr < desc[i].f.TR; tr++) items.push_back(make_int2(i, tr));
+        maxW = std::max(maxW, desc[i].s.W);
+      }
+      g.count = (int)items.size() - g.first;
+      if (!g.count) continue;
+      g.smem = group_smem(sh[0], sh[1], maxW, kind == 1);
+      const void *fn = group_fn(g, P.persistent != 0);
+      if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.smem) != hipSuccess) {
+        delete b;
+        return set_error(PC_ERR_DEVICE, "shared memory attribute failed");
+      }
+      // Persistent grid: generous; work-groups that start after the queue is
+      // empty exit at once, so over-provisioning costs nothing.
+      int per_cu = o.blocks_per_cu > 0 ? o.blocks_per_cu : 4;
+      g.grid = std::min(g.count, std::max(1, cus * per_cu));
+      P.groups.push_back(g);
+    }
+  if ((int)P.groups.size() > 64) { delete b; return set_error(PC_ERR_CAPACITY, "too many groups"); }
+  // block -> frame table of the binning passes
+  std::vector<int> bin_owner, bin_first(nframes);
+  for (int i = 0; i < nframes; i++) {
+    bin_first[i] = (int)bin_owner.size();
+    for (int64_t q = 0; q < (desc[i].n + kBinChunk - 1) / kBinChunk; q++) bin_owner.push_back(i);
+  }
+  P.bin_blocks = (int)bin_owner.size();
+  P.d_desc = (FrameDescDev *)ws;
+  P.d_items = (int2 *)(ws + B.desc);
+  P.d_bin_owner = (int *)(ws + B.desc + B.items);
+  P.d_bin_first = P.d_bin_owner + bin_owner.size();
+  P.d_counters = counters;
+  P.ncounters = 64 + B.strips;      // queue counters and the strip counts (offsets and cursors are rewritten)
+  bool ok = hipMemcpy(P.d_desc, desc.data(), sizeof(FrameDescDev) * desc.size(), hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(P.d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice) == hipSuccess &&
+            (bin_owner.empty() || hipMemcpy(P.d_bin_owner, bin_owner.data(), sizeof(int) * bin_owner.size(), hipMemcpyHostToDevice) == hipSuccess) &&
+            hipMemcpy(P.d_bin_first, bin_first.data(), sizeof(int) * nframes, hipMemcpyHostToDevice) == hipSuccess;
+  if (!ok) {
+    delete b;
+    return set_error(PC_ERR_DEVICE, "descriptor upload failed");
+  }
+  *out = b;
+  return PC_OK;
+}
+
+pc_status pc_batch_run(pc_batch *b, void *stream) {
+  if (!b) return set_error(PC_ERR_ARG, "batch is NULL");
+  BatchPlan &P = b->plan;
+  hipStream_t st = (hipStream_t)stream;
+  auto nomark = [](int) {};
+  if (P.use_graph) {
+    if (!P.exec) {
+      // capture once on a private stream, replay on the caller's
+      hipStream_t cap;
+      if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
+        return set_error(PC_ERR_DEVICE, "stream creation failed");
+      hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        hipError_t le = batch_launches(P, cap, nomark);
+        e = hipStreamEndCapture(cap, &P.graph);
+        if (le != hipSuccess) e = le;
+      }
+      if (e == hipSuccess) e = hipGraphInstantiate(&P.exec, P.graph, nullptr, nullptr, 0);
+      hipStreamDestroy(cap);
+      if (e != hipSuccess) return set_error(PC_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    }
+    hipError_t e = hipGraphLaunch(P.exec, st);
+    if (e != hipSuccess) return set_error(PC_ERR_DEVICE, "graph launch failed: %s", hipGetErrorString(e));
+    return PC_OK;
+  }
+  hipError_t e = batch_launches(P, st, nomark);
+  if (e != hipSuccess) return set_error(PC_ERR_DEVICE, "batch launch failed: %s", hipGetErrorString(e));
+  return PC_OK;
+}
+
+pc_status pc_batch_profile(pc_batch *b, void *stream, float *ms, int32_t *kinds, int32_t cap, int32_t *count) {
+  if (!b || !ms || !count || cap <= 0) return set_error(PC_ERR_ARG, "bad profile arguments");
+  BatchPlan &P = b->plan;
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> kind;
+  auto mark = [&](int k) {
+    hipEvent_t e;
+    hipEventCreate(&e);
+    hipEventRecord(e, st);
+    ev.push_back(e);
+    kind.push_back(k);
+  };
+  mark(-1);
+  hipError_t le = batch_launches(P, st, mark);
+  hipError_t e = hipEventSynchronize(ev.back());
+  int n = 0;
+  for (size_t i = 1; i < ev.size() && n < cap; i++, n++) {
+    float t = 0.f;
+    hipEventElapsedTime(&t, ev[i - 1], ev[i]);
+    ms[n] = t;
+    if (kinds) kinds[n] = kind[i];
+  }
+  for (hipEvent_t x : ev) hipEventDestroy(x);
+  *count = n;
+  if (le != hipSuccess || e != hipSuccess)
+    return set_error(PC_ERR_DEVICE, "profiled batch failed: %s", hipGetErrorString(le != hipSuccess ? le : e));
+  return PC_OK;
+}
+
+pc_status pc_batch_info(const pc_batch *b, int32_t *nitems, int32_t *ngroups, int32_t *grid_max) {
+  if (!b) return set_error(PC_ERR_ARG, "batch is NULL");
+  int n = 0, gm = 0;
+  for (const Group &g : b->plan.groups) {
+    n += g.count;
+    gm = std::max(gm, g.grid);
+  }
+  if (nitems) *nitems = n;
+  if (ngroups) *ngroups = (int)b->plan.groups.size();
+  if (grid_max) *grid_max = gm;
+  return PC_OK;
+}
+
+pc_status pc_batch_destroy(pc_batch *b) {
+  if (!b) return PC_OK;
+  if (b->plan.exec) hipGraphExecDestroy(b->plan.exec);
+  if (b->plan.graph) hipGraphDestroy(b->plan.graph);
+  delete b;
+  return PC_OK;
+}
+
+}  // extern "C"

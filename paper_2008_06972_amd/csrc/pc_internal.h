@@ -35,6 +35,7 @@ struct EncParams {
   int th, tw, max_iter, min_pts;
   float rho;
   float step, inv;      // residual quantiser: step = 2 eps (1 - 2^-8), inv = 1/step
+  uint8_t need[72];     // need[n] = max(min(min_pts, n), ceil(rho n)) for n = 0..64
 };
 
 struct Mat12 {

@@ -53,6 +53,16 @@ class pc_frame_info(C.Structure):
                 ("M", C.c_float * 12), ("pad", C.c_int32 * 4)]
 
 
+class pc_frame_desc(C.Structure):
+    _fields_ = [("xyz", C.c_void_p), ("n", C.c_int64), ("M", C.c_void_p), ("sensor", C.c_void_p),
+                ("params", C.c_void_p), ("key", C.c_int32), ("pad", C.c_int32), ("seed", C.c_void_p),
+                ("range", C.c_void_p), ("out", C.c_void_p)]
+
+
+class pc_batch_opts(C.Structure):
+    _fields_ = [("persistent", C.c_int32), ("graph", C.c_int32), ("blocks_per_cu", C.c_int32)]
+
+
 # numpy views of the device records
 RUN_DTYPE = np.dtype([("s", "<i4"), ("len", "<i4"), ("axis", "<i4"), ("a", "<f4"), ("b", "<f4"), ("c", "<f4")])
 PRUN_DTYPE = np.dtype([("s", "<i4"), ("len", "<i4"), ("krun", "<i4"), ("c", "<f4")])
@@ -74,15 +84,19 @@ def lib():
         L.pc_version.restype = C.c_char_p
         L.pc_workspace_size.restype = C.c_size_t
         for name in ("pc_stream_layout", "pc_ctx_create", "pc_ctx_destroy", "pc_sensor_register", "pc_sensor_tables",
-                     "pc_project", "pc_fit_key", "pc_encode_pred", "pc_decode", "pc_check"):
+                     "pc_project", "pc_fit_key", "pc_encode_pred", "pc_decode", "pc_check", "pc_batch_create",
+                     "pc_batch_run", "pc_batch_info", "pc_batch_profile", "pc_batch_destroy"):
             getattr(L, name).restype = C.c_int
+        L.pc_batch_workspace_size.restype = C.c_size_t
         _lib = L
     return _lib
 
 
 EXPORTED = ("pc_stream_layout", "pc_workspace_size", "pc_ctx_create", "pc_ctx_destroy", "pc_sensor_register",
             "pc_sensor_tables", "pc_project", "pc_fit_key", "pc_encode_pred", "pc_decode", "pc_check",
-            "pc_last_error", "pc_version")
+            "pc_last_error", "pc_version", "pc_batch_workspace_size", "pc_batch_create", "pc_batch_run",
+            "pc_batch_info", "pc_batch_profile", "pc_batch_destroy")
+LAUNCH_KINDS = {0: "reset", 1: "count", 2: "offsets", 3: "scatter", 4: "key", 5: "pred", 6: "finish"}
 
 
 def _check(st: int):
@@ -192,6 +206,41 @@ def pc_check(ctx, frames, stream=None):
     _check(lib().pc_check(ctx, _stream(stream), arr, C.c_int32(len(frames))))
 
 
+def pc_batch_workspace_size(frames) -> int:
+    arr = (pc_frame_desc * len(frames))(*frames)
+    return int(lib().pc_batch_workspace_size(arr, C.c_int32(len(frames))))
+
+
+def pc_batch_create(ctx, frames, opts, workspace, ws_bytes):
+    arr = (pc_frame_desc * len(frames))(*frames)
+    h = C.c_void_p()
+    _check(lib().pc_batch_create(ctx, arr, C.c_int32(len(frames)), C.byref(opts) if opts is not None else None,
+                                 _ptr(workspace), C.c_size_t(ws_bytes), C.byref(h)))
+    return h
+
+
+def pc_batch_run(batch, stream=None):
+    _check(lib().pc_batch_run(batch, _stream(stream)))
+
+
+def pc_batch_info(batch):
+    a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib().pc_batch_info(batch, C.byref(a), C.byref(b), C.byref(c)))
+    return a.value, b.value, c.value
+
+
+def pc_batch_profile(batch, stream=None, cap=64):
+    ms = np.zeros(cap, np.float32)
+    kinds = np.zeros(cap, np.int32)
+    n = C.c_int32()
+    _check(lib().pc_batch_profile(batch, _stream(stream), _ptr(ms), _ptr(kinds), C.c_int32(cap), C.byref(n)))
+    return [(LAUNCH_KINDS[int(k)], float(t)) for k, t in zip(kinds[:n.value], ms[:n.value])]
+
+
+def pc_batch_destroy(batch):
+    _check(lib().pc_batch_destroy(batch))
+
+
 def pc_version() -> str:
     return lib().pc_version().decode()
 
@@ -266,3 +315,56 @@ class FrameStream:
         thw = L.th * L.W
         out["codes"] = np.concatenate([out["res"][r * thw:r * thw + out["nres"][r]] for r in range(TR)])
         return out
+
+
+class Batch:
+    """A batch plan over frames given as dicts with keys xyz (device tensor),
+    M (host 4x4 or None), sensor (Sensor), params (pc_params), key (int),
+    out (FrameStream), range (device tensor or None), seed (tensor or None)."""
+
+    def __init__(self, ctx: Context, frames, persistent=True, graph=True, blocks_per_cu=0):
+        import torch
+        self._keep = []
+        descs = []
+        for i, f in enumerate(frames):
+            M = None
+            if f.get("M") is not None:
+                M = np.ascontiguousarray(f["M"], dtype=np.float32).reshape(16)
+                self._keep.append(M)
+            d = pc_frame_desc()
+            d.xyz = f["xyz"].data_ptr() if len(f["xyz"]) else None
+            d.n = len(f["xyz"])
+            d.M = M.ctypes.data if M is not None else None
+            d.sensor = C.addressof(f["sensor"].c)
+            d.params = C.addressof(f["params"])
+            d.key = f["key"]
+            d.seed = f["seed"].data_ptr() if f.get("seed") is not None else None
+            d.range = f["range"].data_ptr() if f.get("range") is not None else None
+            d.out = f["out"].data_ptr()
+            descs.append(d)
+            self._keep += [f["sensor"], f["params"]]
+        self.frames = frames
+        ws = pc_batch_workspace_size(descs)
+        self.ws = torch.empty(ws, dtype=torch.uint8, device=frames[0]["xyz"].device)
+        opts = pc_batch_opts(1 if persistent else 0, 1 if graph else 0, blocks_per_cu)
+        self.h = pc_batch_create(ctx.h, descs, opts, self.ws, ws)
+
+    def run(self, stream=None):
+        pc_batch_run(self.h, stream)
+
+    def profile(self, stream=None):
+        return pc_batch_profile(self.h, stream)
+
+    def info(self):
+        return pc_batch_info(self.h)
+
+    def close(self):
+        if self.h is not None:
+            pc_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,108 @@
+"""Batched encoding (one HIP graph of persistent kernels over many frames and
+sensors) against the per-frame C-ABI path: every frame's stream buffer must
+be byte-identical, for every graph replay."""
+import numpy as np
+import pytest
+
+from paper_2008_06972_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2008_06972_amd import pcc  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def _mixed_frames():
+    """Two 16x512 sequences (tiles 4x4, eps 2 cm), one 64x2048 sequence
+    (tiles 4x8, eps 1 cm) and one 32x1024 sequence (tiles 8x8)."""
+    groups = [
+        (synth.SENSORS["c1"], "c1", 3000, 10, pcc.params(eps=0.02, tile_h=4, tile_w=4)),
+        (synth.SENSORS["c1"], "c1", 3001, 10, pcc.params(eps=0.02, tile_h=4, tile_w=4)),
+        (synth.SENSORS["c2"], "c2", 7000, 4, pcc.params(eps=0.01, tile_h=4, tile_w=8)),
+        (synth.mixed_sensor(32, 1024), "c1", 4000, 5, pcc.params(eps=0.02, tile_h=8, tile_w=8)),
+    ]
+    sensors = {}
+    out = []
+    for s, kind, seed, n, prm in groups:
+        S = sensors.setdefault((s.H, s.W, s.top_deg), pcc.Sensor.of(s))
+        seq = synth.make_sequence(s, kind, seed, n_frames=n, shuffle=True)
+        base = len(out)
+        for i, f in enumerate(seq.frames):
+            out.append(dict(np=f, M=None if i == seq.key_index else seq.transforms[i], sensor=S, params=prm,
+                            key=base + seq.key_index))
+    return list(sensors.values()), out
+
+
+@pytest.mark.parametrize("persistent,graph", [(True, True), (False, False), (True, False)])
+def test_batch_equals_per_frame(persistent, graph):
+    sensors, frames = _mixed_frames()
+    # key frames first so the per-frame path has its key streams ready
+    order = sorted(range(len(frames)), key=lambda i: frames[i]["key"] != i)
+    ctx = pcc.Context(sensors)
+    ref = [None] * len(frames)
+    ref_rng = [None] * len(frames)
+    # per-frame reference, key frames first
+    for i in order:
+        f = frames[i]
+        S, prm = f["sensor"], f["params"]
+        xyz = torch.from_numpy(f["np"]).to(DEV)
+        rng = torch.empty(S.H, S.W, dtype=torch.float32, device=DEV)
+        pcc.pc_project(ctx.h, xyz, len(f["np"]), f["M"], S, rng)
+        fs = pcc.FrameStream(S, prm, DEV)
+        if f["key"] == i:
+            pcc.pc_fit_key(ctx.h, rng, S, prm, None, fs)
+        else:
+            pcc.pc_encode_pred(ctx.h, ref[f["key"]], rng, f["M"], S, prm, fs)
+        ref[i] = fs
+        ref_rng[i] = rng
+    torch.cuda.synchronize()
+    outs = [pcc.FrameStream(f["sensor"], f["params"], DEV) for f in frames]
+    rngs = [torch.full((f["sensor"].H, f["sensor"].W), -1.0, device=DEV) for f in frames]
+    bf = [dict(xyz=torch.from_numpy(f["np"]).to(DEV), M=f["M"], sensor=f["sensor"], params=f["params"],
+               key=f["key"], out=o, range=r) for f, o, r in zip(frames, outs, rngs)]
+    batch = pcc.Batch(ctx, bf, persistent=persistent, graph=graph)
+    nitems, ngroups, grid = batch.info()
+    print("items", nitems, "groups", ngroups, "grid", grid, flush=True)
+    assert ngroups == 6          # (key, pred) x three tile shapes
+    for rep in range(3):
+        for o in outs:
+            o.buf.fill_(0xAB)        # stale bytes must all be rewritten... except unused slots
+        batch.run()
+        torch.cuda.synchronize()
+        # unrelated eager work between replays
+        junk = torch.randn(1 << 20, device=DEV).sum()
+        torch.cuda.synchronize()
+        for i, (o, r) in enumerate(zip(outs, ref)):
+            L = o.L
+            a, b = o.host(), r.host()
+            assert a["info"].size_bytes == b["info"].size_bytes, (rep, i)
+            for k in ("occ", "cls", "mask", "run_of", "nruns", "nres", "codes", "strip"):
+                assert np.array_equal(a[k], b[k]), (rep, i, k)
+            assert np.array_equal(a["srun_list"], b["srun_list"]), (rep, i)
+            assert np.array_equal(a["prun_list"], b["prun_list"]), (rep, i)
+            assert torch.equal(rngs[i], ref_rng[i]), (rep, i, "range image")
+    del junk
+    batch.close()
+    ctx.close()
+
+
+def test_batch_rejects_bad_descriptors():
+    s = synth.SENSORS["c1"]
+    S = pcc.Sensor.of(s)
+    ctx = pcc.Context([S])
+    prm4 = pcc.params(tile_h=4, tile_w=4)
+    prm8 = pcc.params(tile_h=4, tile_w=8)
+    xyz = torch.zeros(10, 3, device=DEV)
+    o = [pcc.FrameStream(S, prm4, DEV), pcc.FrameStream(S, prm8, DEV)]
+    with pytest.raises(pcc.PcError):      # predicted frame with a different tile shape than its key
+        pcc.Batch(ctx, [dict(xyz=xyz, sensor=S, params=prm4, key=0, out=o[0]),
+                        dict(xyz=xyz, sensor=S, params=prm8, key=0, out=o[1], M=np.eye(4))])
+    with pytest.raises(pcc.PcError):      # key index pointing at a predicted frame
+        pcc.Batch(ctx, [dict(xyz=xyz, sensor=S, params=prm4, key=1, out=o[0], M=np.eye(4)),
+                        dict(xyz=xyz, sensor=S, params=prm4, key=0, out=o[1], M=np.eye(4))])
+    ctx.close()

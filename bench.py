@@ -19,7 +19,6 @@ Prints one JSON line (rank 0).
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -34,6 +33,7 @@ METRIC = "encoded frames/s at 64×2048, ε=2cm, learned+batched vs plain; compre
 N_FRAMES, KEY_INDEX = 10, 5
 SEED0 = 7000
 EPS = 0.02
+TRAFFIC_FILE = "hbm_traffic_batched_encoder_64x2048_960frames.json"
 
 
 def _gen(seed):
@@ -56,19 +56,11 @@ def make_workload(nseq: int, procs: int):
     return frames, transforms
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2008_06972_amd", "csrc")
-    for fn in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, fn), "rb") as f:
-            h.update(fn.encode() + f.read())
-    return h.hexdigest()[:16]
-
-
 def traffic_from_profiles(kernel_kind: str, launches: int):
     """HBM traffic per launch from committed rocprofv3 counter summaries, if
     they were taken on the current kernel sources (else None)."""
-    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    from paper_2008_06972_amd.profile_summary import kernel_source_hash
+    path = os.path.join(ROOT, "profiles", TRAFFIC_FILE)
     if not os.path.exists(path):
         return None
     try:
@@ -95,7 +87,19 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--procs", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (traffic counter calibration) and exit")
     a = ap.parse_args()
+    if a.copy_probe:
+        import torch
+        n = a.copy_probe << 18
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": 4 * n}), flush=True)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: this build encodes one GPU's share "
@@ -214,7 +218,12 @@ def main():
 
     # ------------------------------------------------------------ roofline
     if batch is not None:
-        prof = batch.profile()
+        # per-launch durations: HIP events between the launches of the same
+        # launch sequence, on the same stream, averaged over --steps passes
+        prof = []
+        for _ in range(a.steps):
+            prof += batch.profile(stream.cuda_stream)
+        prof = [(k, t / a.steps) for k, t in prof]
         log("per-launch ms:", prof)
         infos = [o.info() for o in outs_b]
         n_res_k = sum(i.n_res for j, i in enumerate(infos) if j == key_of(j))

@@ -205,7 +205,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_key(const FrameDescDev *__rest
     __syncthreads();
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
     __syncthreads();
-    const int it = s_item;
+    const int it = __builtin_amdgcn_readfirstlane(s_item);   // uniform: descriptor fields go to scalar registers
     if (it >= nitems) break;
     const int2 fi = items[it];
     const FrameDescDev &D = d[fi.x];
@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_pred(const FrameDescDev *__res
     __syncthreads();
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
     __syncthreads();
-    const int it = s_item;
+    const int it = __builtin_amdgcn_readfirstlane(s_item);   // uniform: descriptor fields go to scalar registers
     if (it >= nitems) break;
     const int2 fi = items[it];
     const FrameDescDev &D = d[fi.x];

@@ -8,20 +8,21 @@
 //
 // One work-group encodes one tile-row strip (tile_h rows of the range
 // image), staged in LDS:
-//  1. fits: each thread owns a tile and runs the iterative least-squares fit
-//     (predicted frames: the offset-only fit against the key run's plane);
-//  2. reach: each tile whose fit is accepted measures, in parallel, how many
-//     following tiles (up to kReach) its plane reproduces -- the extension
-//     test of the horizontal growth;
-//  3. chain: one wavefront walks the run starts: a run starts at the next
-//     accepted tile and covers its reach; the next run starts at the first
-//     accepted tile after it (runs that reach kReach continue with a
-//     wavefront-wide test of the following tiles).  This is exactly the
-//     sequential growth, in O(runs) steps; the runs' stream bytes are then
-//     counted in parallel;
-//  4. masks: each thread records its tile's class and the pixels the covering
-//     run's plane reproduces;
-//  5. residuals: codes of the remaining pixels, placed in raster order by a
+//  1. fits, one thread per tile: the iterative least-squares fit (predicted
+//     frames: first the offset-only fit against the key run's plane).  The
+//     iterations are synchronous across the work-group and the tiles still
+//     iterating are compacted onto the first threads after each one, so a
+//     wavefront does not idle on its tiles that converged early; FP64 fits
+//     of near-degenerate tiles are likewise gathered onto a few threads;
+//  2. growth: each tile whose fit is accepted measures, in parallel, how
+//     many following tiles (up to kReach) its plane reproduces -- the
+//     extension test of the horizontal growth -- and which start would
+//     follow its run; one wavefront then walks the actual run starts in
+//     order (runs that reach kReach continue with a wavefront-wide test of
+//     the following tiles).  This is exactly the sequential growth, in
+//     O(runs) steps.  Covered tiles then take their masks, and the runs'
+//     stream bytes are counted, in parallel;
+//  3. residuals: codes of the remaining pixels, placed in raster order by a
 //     work-group prefix sum, and byte histograms of the four streams.
 // A last block per frame sums the strip histograms and computes the optimal
 // Huffman cost of each stream.
@@ -30,7 +31,7 @@
 
 namespace pcc {
 
-constexpr int kReach = 6;     // tiles a fit measures its reach over before the chain continues it
+constexpr int kReach = 6;     // tiles a fit measures its reach over before the walk continues it
 
 // ---------------------------------------------------------------- LDS layout
 template <int TH, int TW>
@@ -38,39 +39,47 @@ struct StripSmem {
   static constexpr int N = TH * TW;
   static constexpr int NP = N + 4;       // tile stride: 16-byte aligned rows, conflict-free 128-bit reads across threads
   float *r;          // [TC * NP] ranges, tile-major
-  const float *ca, *sa;   // [W] column tables (global memory, L1/L2 resident)
-  uint32_t *cnt;     // [TH * TC] residual counts
+  float *ca, *sa;    // [W] column tables
   float *ce, *se;    // [TH] row tables of the strip
-  float4 *plane;     // [TC] own plane: a, b, c, axis
-  uint64_t *omask;   // [TC] own plane's reproduced pixels
+  float4 *plane;     // [TC] plane: a, b, c, axis (predicted frames: the temporal pass's, then the own fits')
+  uint64_t *omask;   // [TC] pixels that plane reproduces
   uint64_t *fmask;   // [TC] final mask (covering plane)
-  uint8_t *stat;     // [TC] own-fit status
+  uint8_t *stat;     // [TC] fit status
+  uint8_t *iters;    // [TC] fits done
   uint8_t *nv;       // [TC] valid pixels
   uint8_t *cls;      // [TC] final class
   uint8_t *elig;     // [TC] still to be encoded spatially (predicted frames)
-  uint8_t *reach;    // [TC] tiles a run starting here covers after its start (<= kReach)
   int32_t *runof;    // [TC] run index within the current pass, then the stream's run slot
-  int32_t *rs;       // [TC] run starts of the current pass
-  int32_t *rl;       // [TC] run lengths
-  uint64_t *acc;     // [8] tiles that may start a run (bit tc)
-  // predicted frames
-  float4 *tplane;    // [TC] key plane a, b with own offset c', axis
-  uint64_t *tmask;   // [TC]
-  uint8_t *tstat;    // [TC]
-  int32_t *krun;     // [TC] key run slot, -1 if the key tile is not plane coded
+  int16_t *rs, *rl;  // [TC] run starts and lengths of the current pass
+  uint8_t *reach;    // [TC] tiles a run starting here covers after its start (<= kReach)
+  int16_t *nx;       // [TC] start that follows a run starting here (-1: none)
+  uint64_t *acc;     // [(TC + 63) / 64] tiles that may start a run (bit tc)
+  int32_t *krun;     // [TC] key run slot, -1 if the key tile is not plane coded (predicted frames)
+  uint32_t *scratch; // fits: cur (u64[TC]), two work lists and the FP64 list (i16[TC] each);
+                     // residuals: counts per (row, tile) (u32[TH * TC])
   uint32_t *hist;    // [4 * 256]
   uint32_t *occ;     // [TH * W / 32]
   int32_t *misc;     // [32] counters
 
+  __device__ uint32_t *cnt() const { return scratch; }
+  __device__ uint64_t *cur() const { return reinterpret_cast<uint64_t *>(scratch); }
+  __device__ int16_t *list(int q, int TC) const { return reinterpret_cast<int16_t *>(cur() + TC) + q * TC; }
+
+  __host__ __device__ static size_t scratch_bytes(int TC) {
+    size_t a = sizeof(uint32_t) * (size_t)TH * TC, b = sizeof(uint64_t) * (size_t)TC + 3 * sizeof(int16_t) * (size_t)TC;
+    return a > b ? a : b;
+  }
   __host__ __device__ static size_t bytes(int W, int TC, bool pred) {
     auto a16 = [](size_t n) { return (n + 15) & ~(size_t)15; };
     size_t b = 0;
     b += a16(sizeof(float) * (size_t)TC * NP);
-    b += a16(sizeof(uint32_t) * (size_t)TH * TC);
+    b += 2 * a16(sizeof(float) * (size_t)W);
     b += 2 * a16(sizeof(float) * 16);
-    b += a16(sizeof(float4) * TC) + 2 * a16(sizeof(uint64_t) * TC) + 5 * a16(TC) + 3 * a16(sizeof(int32_t) * TC);
-    b += a16(sizeof(uint64_t) * 8);
-    if (pred) b += a16(sizeof(float4) * TC) + a16(sizeof(uint64_t) * TC) + a16(TC) + a16(sizeof(int32_t) * TC);
+    b += a16(sizeof(float4) * TC) + 2 * a16(sizeof(uint64_t) * TC) + 6 * a16(TC) + a16(sizeof(int32_t) * TC) +
+         3 * a16(sizeof(int16_t) * TC);
+    b += a16(sizeof(uint64_t) * ((TC + 63) / 64));
+    if (pred) b += a16(sizeof(int32_t) * TC);
+    b += a16(scratch_bytes(TC));
     b += a16(sizeof(uint32_t) * 1024) + a16(sizeof(uint32_t) * (TH * W / 32)) + a16(sizeof(int32_t) * 32);
     return b + 64;
   }
@@ -79,32 +88,43 @@ struct StripSmem {
     char *p = base;
     auto take = [&](size_t n) { char *q = p; p += (n + 15) & ~(size_t)15; return q; };
     r = (float *)take(sizeof(float) * (size_t)TC * NP);
-    cnt = (uint32_t *)take(sizeof(uint32_t) * (size_t)TH * TC);
+    ca = (float *)take(sizeof(float) * (size_t)W);
+    sa = (float *)take(sizeof(float) * (size_t)W);
     ce = (float *)take(sizeof(float) * 16);
     se = (float *)take(sizeof(float) * 16);
     plane = (float4 *)take(sizeof(float4) * TC);
     omask = (uint64_t *)take(sizeof(uint64_t) * TC);
     fmask = (uint64_t *)take(sizeof(uint64_t) * TC);
     stat = (uint8_t *)take(TC);
+    iters = (uint8_t *)take(TC);
     nv = (uint8_t *)take(TC);
     cls = (uint8_t *)take(TC);
     elig = (uint8_t *)take(TC);
-    reach = (uint8_t *)take(TC);
     runof = (int32_t *)take(sizeof(int32_t) * TC);
-    rs = (int32_t *)take(sizeof(int32_t) * TC);
-    rl = (int32_t *)take(sizeof(int32_t) * TC);
-    acc = (uint64_t *)take(sizeof(uint64_t) * 8);
-    if (pred) {
-      tplane = (float4 *)take(sizeof(float4) * TC);
-      tmask = (uint64_t *)take(sizeof(uint64_t) * TC);
-      tstat = (uint8_t *)take(TC);
-      krun = (int32_t *)take(sizeof(int32_t) * TC);
-    }
+    rs = (int16_t *)take(sizeof(int16_t) * TC);
+    rl = (int16_t *)take(sizeof(int16_t) * TC);
+    reach = (uint8_t *)take(TC);
+    nx = (int16_t *)take(sizeof(int16_t) * TC);
+    acc = (uint64_t *)take(sizeof(uint64_t) * ((TC + 63) / 64));
+    krun = pred ? (int32_t *)take(sizeof(int32_t) * TC) : nullptr;
+    scratch = (uint32_t *)take(scratch_bytes(TC));
     hist = (uint32_t *)take(sizeof(uint32_t) * 1024);
     occ = (uint32_t *)take(sizeof(uint32_t) * (TH * W / 32));
     misc = (int32_t *)take(sizeof(int32_t) * 32);
   }
 };
+
+// LDS bytes of a strip encoder's work-group (0 for shapes not compiled).
+__host__ __device__ inline size_t strip_lds_bytes(int th, int tw, int W, bool pred) {
+  if (th == 4 && tw == 4) return StripSmem<4, 4>::bytes(W, W / 4, pred);
+  if (th == 4 && tw == 8) return StripSmem<4, 8>::bytes(W, W / 8, pred);
+  if (th == 4 && tw == 16) return StripSmem<4, 16>::bytes(W, W / 16, pred);
+  if (th == 8 && tw == 8) return StripSmem<8, 8>::bytes(W, W / 8, pred);
+  return 0;
+}
+
+// misc[] slots
+constexpr int M_SRUNS = 0, M_PRUNS = 1, M_SEEDED = 2, M_FALLBACK = 3, M_LIST = 8, M_F64 = 10;
 
 __device__ __forceinline__ float4 pack_plane(const Plane &P) { return make_float4(P.a, P.b, P.c, (float)P.k); }
 __device__ __forceinline__ Plane unpack_plane(float4 v) { return Plane{(int)v.w, v.x, v.y, v.z}; }
@@ -131,8 +151,11 @@ __device__ void strip_init(StripSmem<TH, TW> &sm, const SensorDev &s, int tr) {
   for (int q = tid; q < 1024; q += kBlock) sm.hist[q] = 0;
   for (int q = tid; q < TH * s.W / 32; q += kBlock) sm.occ[q] = 0;
   if (tid < 32) sm.misc[tid] = 0;
-  sm.ca = s.ca;
-  sm.sa = s.sa;
+  const float4 *ca4 = reinterpret_cast<const float4 *>(s.ca), *sa4 = reinterpret_cast<const float4 *>(s.sa);
+  for (int q = tid; q < s.W / 4; q += kBlock) {
+    reinterpret_cast<float4 *>(sm.ca)[q] = ca4[q];
+    reinterpret_cast<float4 *>(sm.sa)[q] = sa4[q];
+  }
   if (tid < TH) {
     sm.ce[tid] = s.ce[tr * TH + tid];
     sm.se[tid] = s.se[tr * TH + tid];
@@ -203,10 +226,10 @@ __device__ __forceinline__ void load_source(StripSmem<TH, TW> &sm, const StripSr
   }
 }
 
-// A tile of the strip as seen by one thread (its own, or a neighbour it
-// tests): ranges in LDS, column tables loaded into registers.
+// A tile of the strip as seen by one thread: ranges and column tables in
+// LDS, the tile's column tables copied into registers.
 template <int TH, int TW>
-__device__ __forceinline__ TileRows<TH, TW> tile_at(const StripSmem<TH, TW> &sm, int tc, int TC, bool with_valid) {
+__device__ __forceinline__ TileRows<TH, TW> tile_at(const StripSmem<TH, TW> &sm, int tc) {
   TileRows<TH, TW> T;
   T.rp = sm.r + tc * StripSmem<TH, TW>::NP;
   T.ce = sm.ce;
@@ -223,81 +246,186 @@ __device__ __forceinline__ TileRows<TH, TW> tile_at(const StripSmem<TH, TW> &sm,
   }
   T.V = 0;
   T.nV = 0;
-  if (with_valid) {
-    uint32_t lo = 0, hi = 0;
-#pragma unroll
-    for (int i = 0; i < TH; i++) {
-      float r[TW];
-      T.row(i, r);
-#pragma unroll
-      for (int k = 0; k < TW; k++) {
-        const int j = i * TW + k;
-        if (j < 32) lo |= (uint32_t)(r[k] > 0.0f) << (j & 31); else hi |= (uint32_t)(r[k] > 0.0f) << (j & 31);
-      }
-    }
-    T.V = ((uint64_t)hi << 32) | lo;
-    T.nV = __popcll(T.V);
-  }
   return T;
 }
 
-// Pixels of tile tc that plane P reproduces.
+// Valid pixels of tile tc (range > 0), bit j = i * TW + k.
 template <int TH, int TW>
-__device__ __forceinline__ uint64_t inliers_at(const StripSmem<TH, TW> &sm, int tc, int TC, const Plane &P,
-                                               float eps) {
-  return inliers(tile_at<TH, TW>(sm, tc, TC, false), P, eps);
-}
-
-// ------------------------------------------------ phases 2-4: run growth
-// Reach of a run started at tile s with plane P: the number of following
-// tiles (at most kReach) it extends over.  `allowed(s, t)` says whether tile
-// t may join a run started at s.
-template <int TH, int TW, class Allowed>
-__device__ __forceinline__ int reach_of(const StripSmem<TH, TW> &sm, const EncParams &p, const Plane &P, int s, int TC,
-                                        Allowed allowed) {
-  int e = 0;
-  for (int t = s + 1; t < TC && e < kReach; t++) {
-    if (!allowed(s, t)) break;
-    int n = __popcll(inliers_at<TH, TW>(sm, t, TC, P, p.eps));
-    if (n < need_of(p, sm.nv[t])) break;
-    e++;
-  }
-  return e;
-}
-
-// Continue a run beyond its measured reach: the wavefront tests windows of
-// 64/(th*tw) tiles from tile t on; returns how many more tiles join.
-template <int TH, int TW, class Allowed>
-__device__ int extend_beyond(const StripSmem<TH, TW> &sm, const EncParams &p, const Plane &P, int s, int t, int TC,
-                             Allowed allowed) {
-  constexpr int N = TH * TW, NP = StripSmem<TH, TW>::NP, TPW = 64 / N;
-  const int lane = threadIdx.x & 63, w = lane / N, j = lane % N, i = j / TW, k = j % TW;
-  const uint64_t segmask = (N == 64) ? ~0ull : ((1ull << N) - 1ull);
-  int added = 0;
-  while (t < TC) {
-    int tt = t + w;
-    bool in = tt < TC;
-    float r = in ? sm.r[tt * NP + j] : 0.0f;
-    bool inl = false;
-    if (r > 0.0f) {
-      Dir d = dir_of(sm.ce[i], sm.se[i], sm.ca[tt * TW + k], sm.sa[tt * TW + k]);
-      inl = reproduces(P, d, r, p.eps);
-    }
-    uint64_t B = __ballot(inl);
-    uint64_t m = (B >> (w * N)) & segmask;
-    bool ext = in && allowed(s, tt) && __popcll(m) >= need_of(p, in ? sm.nv[tt] : 0);
-    uint64_t E = __ballot(j == 0 && ext);
-    int f = 0;
+__device__ __forceinline__ uint64_t valid_bits(const StripSmem<TH, TW> &sm, int tc) {
+  constexpr int NP = StripSmem<TH, TW>::NP;
+  uint32_t lo = 0, hi = 0;
+  const float4 *q = reinterpret_cast<const float4 *>(sm.r + tc * NP);
 #pragma unroll
-    for (int q = 0; q < TPW; q++)
-      if (((E >> (q * N)) & 1ull) && f == q) f = q + 1;
-    added += f;
-    t += f;
-    if (f < TPW) break;
+  for (int j4 = 0; j4 < TH * TW / 4; j4++) {
+    float4 v = q[j4];
+    uint32_t b = (uint32_t)(v.x > 0.0f) | ((uint32_t)(v.y > 0.0f) << 1) | ((uint32_t)(v.z > 0.0f) << 2) |
+                 ((uint32_t)(v.w > 0.0f) << 3);
+    const int j = 4 * j4;
+    if (j < 32) lo |= b << (j & 31); else hi |= b << (j & 31);
   }
-  return added;
+  return ((uint64_t)hi << 32) | lo;
 }
 
+// ------------------------------------------------------------ phase 1: fits
+// Work-group-synchronous iterations over a compacted list of the tiles
+// still iterating.  Lists live in the scratch area: lists 0 and 1
+// alternate, list 2 gathers the tiles whose FP32 fit needs FP64.
+// misc[M_LIST + q] counts list q (q < 2), misc[M_F64] list 2.
+template <int TH, int TW>
+__device__ __forceinline__ void list_push(StripSmem<TH, TW> &sm, int q, int TC, int tc) {
+  int at = atomicAdd(&sm.misc[q == 2 ? M_F64 : M_LIST + q], 1);
+  sm.list(q, TC)[at] = (int16_t)tc;
+}
+
+// Own least-squares fits (Sec. III-C) of the tiles with take(tc): fit,
+// keep the pixels the plane reproduces, refit on them, up to max_iter fits,
+// converged when the kept set stops changing; accepted when at least
+// need(n) pixels are kept.  Results in plane/omask/stat/iters.
+template <int TH, int TW, class Take>
+__device__ void own_fits(StripSmem<TH, TW> &sm, const EncParams &p, int TC, Take take, int &fits, int &fp64) {
+  const int tid = threadIdx.x;
+  uint64_t *cur = sm.cur();
+  for (int tc = tid; tc < TC; tc += kBlock) {
+    if (!take(tc)) continue;
+    const int n = sm.nv[tc];
+    sm.plane[tc] = make_float4(0.f, 0.f, 0.f, 0.f);
+    sm.omask[tc] = 0;
+    sm.iters[tc] = 0;
+    sm.stat[tc] = (uint8_t)(n == 0 ? ST_EMPTY : ST_FEW);
+    if (n >= p.min_pts) {
+      cur[tc] = valid_bits<TH, TW>(sm, tc);
+      list_push<TH, TW>(sm, 0, TC, tc);
+    }
+  }
+  __syncthreads();
+  int n = sm.misc[M_LIST];
+  for (int it = 1; it <= p.max_iter && n > 0; it++) {
+    const int q = (it - 1) & 1;
+    const int16_t *L = sm.list(q, TC);
+    // (a) FP32 fits; near-degenerate ones go to the FP64 list
+    for (int e = tid; e < n; e += kBlock) {
+      const int tc = L[e];
+      TileRows<TH, TW> T = tile_at<TH, TW>(sm, tc);
+      Plane P{0, 0.f, 0.f, 0.f};
+      fits++;
+      if (fit_plane_f32(T, cur[tc], P)) sm.plane[tc] = pack_plane(P);
+      else list_push<TH, TW>(sm, 2, TC, tc);
+    }
+    __syncthreads();
+    // (b) FP64 fits
+    const int nf = sm.misc[M_F64];
+    if (tid == 0) sm.misc[M_LIST + q] = 0;      // every thread has read n before (a)
+    for (int e = tid; e < nf; e += kBlock) {
+      const int tc = sm.list(2, TC)[e];
+      TileRows<TH, TW> T = tile_at<TH, TW>(sm, tc);
+      Plane P{0, 0.f, 0.f, 0.f};
+      fp64++;
+      if (fit_plane_f64(T, cur[tc], P)) sm.plane[tc] = pack_plane(P);
+      else sm.stat[tc] = ST_DEGENERATE;
+    }
+    __syncthreads();
+    if (tid == 0) sm.misc[M_F64] = 0;            // every thread has read nf before (b)
+    // (c) kept pixels, convergence
+    for (int e = tid; e < n; e += kBlock) {
+      const int tc = L[e];
+      sm.iters[tc] = (uint8_t)it;
+      if (sm.stat[tc] == ST_DEGENERATE) {
+        sm.omask[tc] = 0;
+        continue;
+      }
+      TileRows<TH, TW> T = tile_at<TH, TW>(sm, tc);
+      const uint64_t S = cur[tc];
+      const uint64_t S2 = inliers(T, unpack_plane(sm.plane[tc]), p.eps);
+      if (S2 != S && __popcll(S2) < p.min_pts) {
+        sm.stat[tc] = ST_FAILED;
+        sm.omask[tc] = 0;
+        continue;
+      }
+      sm.omask[tc] = S2;
+      if (S2 != S && it < p.max_iter) {
+        cur[tc] = S2;
+        list_push<TH, TW>(sm, q ^ 1, TC, tc);
+      } else {
+        sm.stat[tc] = __popcll(S2) >= need_of(p, sm.nv[tc]) ? ST_ACCEPTED : ST_REJECTED;
+      }
+    }
+    __syncthreads();
+    n = sm.misc[M_LIST + (q ^ 1)];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    sm.misc[M_LIST] = 0;
+    sm.misc[M_LIST + 1] = 0;
+  }
+  __syncthreads();
+}
+
+// Temporal fits (Sec. III-D) of the tiles whose key tile is plane coded:
+// the key run's normal (k, a, b) is held and only the offset varies, with
+// the same iteration, kept-pixel test and acceptance as the own fits.
+// stat: 2 accepted, 1 not, 0 no key plane.  Results in plane/omask/stat/iters.
+template <int TH, int TW>
+__device__ void temporal_fits(StripSmem<TH, TW> &sm, const FrameDev &key, const EncParams &p, int tr, int TC) {
+  const int tid = threadIdx.x;
+  uint64_t *cur = sm.cur();
+  for (int tc = tid; tc < TC; tc += kBlock) {
+    const int t = tr * TC + tc;
+    const int kr = key.cls[t] == CLS_SPATIAL ? key.run_of[t] : -1;
+    sm.krun[tc] = kr;
+    float4 Q = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (kr >= 0) {
+      pc_run q = key.sruns[kr];
+      Q = pack_plane(Plane{q.axis, q.a, q.b, q.c});
+    }
+    sm.plane[tc] = Q;
+    sm.omask[tc] = 0;
+    sm.iters[tc] = 0;
+    sm.stat[tc] = kr >= 0 ? 1 : 0;
+    if (kr >= 0 && sm.nv[tc] >= p.min_pts) {
+      cur[tc] = valid_bits<TH, TW>(sm, tc);
+      list_push<TH, TW>(sm, 0, TC, tc);
+    }
+  }
+  __syncthreads();
+  int n = sm.misc[M_LIST];
+  for (int it = 1; it <= p.max_iter && n > 0; it++) {
+    const int q = (it - 1) & 1;
+    const int16_t *L = sm.list(q, TC);
+    for (int e = tid; e < n; e += kBlock) {
+      const int tc = L[e];
+      sm.iters[tc] = (uint8_t)it;
+      TileRows<TH, TW> T = tile_at<TH, TW>(sm, tc);
+      Plane P = unpack_plane(sm.plane[tc]);
+      const uint64_t S = cur[tc];
+      P.c = temporal_offset(T, P, S);
+      sm.plane[tc] = pack_plane(P);
+      const uint64_t S2 = inliers(T, P, p.eps);
+      if (S2 != S && __popcll(S2) < p.min_pts) {     // failed: stat stays 1
+        sm.omask[tc] = 0;
+        continue;
+      }
+      sm.omask[tc] = S2;
+      if (S2 != S && it < p.max_iter) {
+        cur[tc] = S2;
+        list_push<TH, TW>(sm, q ^ 1, TC, tc);
+      } else {
+        sm.stat[tc] = __popcll(S2) >= need_of(p, sm.nv[tc]) ? 2 : 1;
+      }
+    }
+    __syncthreads();
+    n = sm.misc[M_LIST + (q ^ 1)];
+    if (tid == 0) sm.misc[M_LIST + q] = 0;    // every thread read its count before the pass
+    __syncthreads();
+  }
+  __syncthreads();
+  if (tid == 0) {
+    sm.misc[M_LIST] = 0;
+    sm.misc[M_LIST + 1] = 0;
+  }
+  __syncthreads();
+}
+
+// --------------------------------------------------------- phase 2: growth
 // Next tile >= t in the start bitmask, or -1.
 __device__ __forceinline__ int next_start(const uint64_t *acc, int t, int TC) {
   const int nw = (TC + 63) >> 6;
@@ -311,27 +439,114 @@ __device__ __forceinline__ int next_start(const uint64_t *acc, int t, int TC) {
   return (w << 6) + __ffsll((long long)bits) - 1;
 }
 
-// The chain (one wavefront, lane-uniform control): runs from the start
-// bitmask and the reaches.  Writes rs/rl and runof (run index per tile;
-// -1 elsewhere, set beforehand); returns the number of runs.
-template <int TH, int TW, class Allowed, class PlaneOf>
-__device__ int chain_runs(StripSmem<TH, TW> &sm, const EncParams &p, int TC, Allowed allowed, PlaneOf plane_of) {
-  const int lane = threadIdx.x & 63;
-  int nr = 0, t = 0;
-  for (;;) {
-    int s = next_start(sm.acc, t, TC);
-    if (s < 0) break;
-    int len = 1 + sm.reach[s];
-    if (len == 1 + kReach && s + len < TC) len += extend_beyond<TH, TW>(sm, p, plane_of(s), s, s + len, TC, allowed);
-    for (int q = lane; q < len; q += 64) sm.runof[s + q] = nr;
-    if (lane == 0) {
-      sm.rs[nr] = s;
-      sm.rl[nr] = len;
-    }
-    nr++;
-    t = s + len;
+// Pixels of tile tc that plane P reproduces.
+template <int TH, int TW>
+__device__ __forceinline__ uint64_t inliers_at(const StripSmem<TH, TW> &sm, int tc, const Plane &P, float eps) {
+  return inliers(tile_at<TH, TW>(sm, tc), P, eps);
+}
+
+// Reach of a run started at tile s with plane P: the number of following
+// tiles (at most kReach) it extends over: tile t joins while allowed(s, t)
+// and P reproduces at least need(n) of its pixels.
+template <int TH, int TW, class Allowed>
+__device__ __forceinline__ int reach_of(const StripSmem<TH, TW> &sm, const EncParams &p, const Plane &P, int s, int TC,
+                                        Allowed allowed) {
+  int e = 0;
+  for (int t = s + 1; t < TC && e < kReach; t++) {
+    if (!allowed(s, t)) break;
+    if (__popcll(inliers_at<TH, TW>(sm, t, P, p.eps)) < need_of(p, sm.nv[t])) break;
+    e++;
   }
-  return nr;
+  return e;
+}
+
+// Continue a run beyond its measured reach: the wavefront tests windows of
+// 64 / (TH * TW) tiles from tile t on (lane = pixel); returns how many more
+// tiles join.
+template <int TH, int TW, class Allowed>
+__device__ int extend_beyond(const StripSmem<TH, TW> &sm, const EncParams &p, const Plane &P, int s, int t, int TC,
+                             Allowed allowed) {
+  constexpr int N = TH * TW, NP = StripSmem<TH, TW>::NP, TPW = 64 / N;
+  const int lane = threadIdx.x & 63, w = lane / N, j = lane % N, i = j / TW, k = j % TW;
+  const uint64_t segmask = (N == 64) ? ~0ull : ((1ull << N) - 1ull);
+  int added = 0;
+  while (t < TC) {
+    const int tt = t + w;
+    const bool in = tt < TC;
+    const float r = in ? sm.r[tt * NP + j] : 0.0f;
+    bool inl = false;
+    if (r > 0.0f) inl = reproduces(P, dir_of(sm.ce[i], sm.se[i], sm.ca[tt * TW + k], sm.sa[tt * TW + k]), r, p.eps);
+    const uint64_t B = __ballot(inl);
+    const uint64_t m = (B >> (w * N)) & segmask;
+    const bool ext = in && allowed(s, tt) && __popcll(m) >= need_of(p, in ? sm.nv[tt] : 0);
+    const uint64_t E = __ballot(j == 0 && ext);
+    int f = 0;
+#pragma unroll
+    for (int q = 0; q < TPW; q++)
+      if (((E >> (q * N)) & 1ull) && f == q) f = q + 1;
+    added += f;
+    t += f;
+    if (f < TPW) break;
+  }
+  return added;
+}
+
+// Runs of one pass.  Every tile that may start a run (start(tc)) measures
+// its reach in parallel and notes the start that would follow its run; one
+// wavefront then walks the actual starts in order (a run starts at the
+// first start tile at or after the previous run's end) and continues runs
+// that reached kReach.  Then every covered tile takes its mask: its own for
+// a run's first tile, else the pixels the run plane reproduces.  Writes
+// rs/rl, runof (run index, -1 outside runs, for tiles with member(tc)) and
+// fmask; returns the number of runs.
+template <int TH, int TW, class Member, class Start, class Allowed, class PlaneOf, class MaskOf>
+__device__ int grow_runs(StripSmem<TH, TW> &sm, const EncParams &p, int TC, Member member, Start start,
+                         Allowed allowed, PlaneOf plane_of, MaskOf own_mask, int *nr_out) {
+  const int tid = threadIdx.x, nw = (TC + 63) >> 6;
+  for (int w = tid >> 6; w < nw; w += kBlock / 64) {
+    const int tc = w * 64 + (tid & 63);
+    const uint64_t b = __ballot(tc < TC && start(tc));
+    if ((tid & 63) == 0) sm.acc[w] = b;
+  }
+  for (int tc = tid; tc < TC; tc += kBlock)
+    if (member(tc)) sm.runof[tc] = -1;
+  __syncthreads();
+  for (int tc = tid; tc < TC; tc += kBlock) {
+    if (!start(tc)) continue;
+    const int e = reach_of<TH, TW>(sm, p, plane_of(tc), tc, TC, allowed);
+    sm.reach[tc] = (uint8_t)e;
+    sm.nx[tc] = (int16_t)next_start(sm.acc, tc + 1 + e, TC);
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const int lane = tid;
+    int nr = 0, s = next_start(sm.acc, 0, TC);
+    while (s >= 0) {
+      int len = 1 + sm.reach[s];
+      int nxt = sm.nx[s];
+      if (len == 1 + kReach && s + len < TC) {
+        len += extend_beyond<TH, TW>(sm, p, plane_of(s), s, s + len, TC, allowed);
+        nxt = next_start(sm.acc, s + len, TC);
+      }
+      for (int q = lane; q < len; q += 64) sm.runof[s + q] = nr;
+      if (lane == 0) {
+        sm.rs[nr] = (int16_t)s;
+        sm.rl[nr] = (int16_t)len;
+      }
+      nr++;
+      s = nxt;
+    }
+    if (lane == 0) *nr_out = nr;
+  }
+  __syncthreads();
+  for (int tc = tid; tc < TC; tc += kBlock) {
+    if (!member(tc)) continue;
+    const int ri = sm.runof[tc];
+    if (ri < 0) continue;
+    const int s = sm.rs[ri];
+    sm.fmask[tc] = s == tc ? own_mask(tc) : inliers_at<TH, TW>(sm, tc, plane_of(s), p.eps);
+  }
+  return *nr_out;
 }
 
 // RUN-stream bytes of the pass's runs, one thread per run: varint of the
@@ -354,33 +569,13 @@ __device__ void run_bytes(StripSmem<TH, TW> &sm, int nr, EmitRun emit) {
 template <int TH, int TW>
 __device__ void grow_spatial(StripSmem<TH, TW> &sm, const EncParams &p, const FrameDev &f, int tr, bool pred) {
   const int TC = f.TC, tid = threadIdx.x;
-  auto allowed = [&](int, int t) { return !pred || sm.elig[t] != 0; };
-  // starts and reaches
-  if (tid < 8) sm.acc[tid] = 0;
-  __syncthreads();
-  for (int tc = tid; tc < TC; tc += kBlock) {
-    bool el = !pred || sm.elig[tc];
-    if (el) sm.runof[tc] = -1;
-    bool start = el && sm.stat[tc] == ST_ACCEPTED;
-    int e = 0;
-    if (start) {
-      atomicOr((unsigned long long *)&sm.acc[tc >> 6], 1ull << (tc & 63));
-      e = reach_of<TH, TW>(sm, p, unpack_plane(sm.plane[tc]), tc, TC, allowed);
-    }
-    sm.reach[tc] = (uint8_t)e;
-  }
-  __syncthreads();
-  if (tid < 64) {
-    auto plane_of = [&](int s) { return unpack_plane(sm.plane[s]); };
-    int nr = chain_runs<TH, TW>(sm, p, TC, allowed, plane_of);
-    if (tid == 0) {
-      sm.misc[0] = nr;
-      f.nruns[tr] = nr;
-    }
-  }
-  __syncthreads();
-  // stream bytes, masks, classes and the runs themselves
-  const int nr = sm.misc[0];
+  auto member = [&](int tc) { return !pred || sm.elig[tc] != 0; };
+  const int nr = grow_runs<TH, TW>(
+      sm, p, TC, member, [&](int tc) { return member(tc) && sm.stat[tc] == ST_ACCEPTED; },
+      [&](int, int t) { return member(t); }, [&](int s) { return unpack_plane(sm.plane[s]); },
+      [&](int s) { return sm.omask[s]; }, &sm.misc[M_SRUNS]);
+  if (tid == 0) f.nruns[tr] = nr;
+  // stream bytes, classes and the runs themselves
   run_bytes<TH, TW>(sm, nr, [&](int s) {
     Plane P = unpack_plane(sm.plane[s]);
     hist_byte(sm.hist, S_RUN, (uint32_t)P.k);
@@ -394,13 +589,10 @@ __device__ void grow_spatial(StripSmem<TH, TW> &sm, const EncParams &p, const Fr
     runs[q] = pc_run{sm.rs[q], sm.rl[q], P.k, P.a, P.b, P.c};
   }
   for (int tc = tid; tc < TC; tc += kBlock) {
-    if (pred && !sm.elig[tc]) continue;
+    if (!member(tc)) continue;
     int ri = sm.runof[tc];
     if (ri >= 0) {
-      int s = sm.rs[ri];
-      uint64_t m = (s == tc) ? sm.omask[tc] : inliers_at<TH, TW>(sm, tc, TC, unpack_plane(sm.plane[s]), p.eps);
       sm.cls[tc] = CLS_SPATIAL;
-      sm.fmask[tc] = m;
       sm.runof[tc] = tr * TC + ri;
     } else {
       sm.cls[tc] = sm.nv[tc] ? CLS_UNFIT : CLS_EMPTY;
@@ -416,40 +608,18 @@ __device__ void grow_spatial(StripSmem<TH, TW> &sm, const EncParams &p, const Fr
 template <int TH, int TW>
 __device__ void grow_temporal(StripSmem<TH, TW> &sm, const EncParams &p, const FrameDev &f, int tr) {
   const int TC = f.TC, T = f.T, tid = threadIdx.x;
-  auto allowed = [&](int s, int t) { return sm.krun[t] == sm.krun[s]; };
-  if (tid < 8) sm.acc[tid] = 0;
-  __syncthreads();
-  for (int tc = tid; tc < TC; tc += kBlock) {
-    sm.runof[tc] = -1;
-    bool start = sm.tstat[tc] == 2;
-    int e = 0;
-    if (start) {
-      atomicOr((unsigned long long *)&sm.acc[tc >> 6], 1ull << (tc & 63));
-      e = reach_of<TH, TW>(sm, p, unpack_plane(sm.tplane[tc]), tc, TC, allowed);
-    }
-    sm.reach[tc] = (uint8_t)e;
-  }
-  __syncthreads();
-  if (tid < 64) {
-    auto plane_of = [&](int s) { return unpack_plane(sm.tplane[s]); };
-    int nr = chain_runs<TH, TW>(sm, p, TC, allowed, plane_of);
-    if (tid == 0) {
-      sm.misc[1] = nr;
-      f.nruns[f.TR + tr] = nr;
-    }
-  }
-  __syncthreads();
-  const int nr = sm.misc[1];
-  run_bytes<TH, TW>(sm, nr, [&](int s) { f32_bytes(sm.hist, sm.tplane[s].z); });
+  const int nr = grow_runs<TH, TW>(
+      sm, p, TC, [](int) { return true; }, [&](int tc) { return sm.stat[tc] == 2; },
+      [&](int s, int t) { return sm.krun[t] == sm.krun[s]; }, [&](int s) { return unpack_plane(sm.plane[s]); },
+      [&](int s) { return sm.omask[s]; }, &sm.misc[M_PRUNS]);
+  if (tid == 0) f.nruns[f.TR + tr] = nr;
+  run_bytes<TH, TW>(sm, nr, [&](int s) { f32_bytes(sm.hist, sm.plane[s].z); });
   pc_prun *runs = f.pruns + (int64_t)tr * TC;
-  for (int q = tid; q < nr; q += kBlock) runs[q] = pc_prun{sm.rs[q], sm.rl[q], sm.krun[sm.rs[q]], sm.tplane[sm.rs[q]].z};
+  for (int q = tid; q < nr; q += kBlock) runs[q] = pc_prun{sm.rs[q], sm.rl[q], sm.krun[sm.rs[q]], sm.plane[sm.rs[q]].z};
   for (int tc = tid; tc < TC; tc += kBlock) {
     int ri = sm.runof[tc];
     if (ri >= 0) {
-      int s = sm.rs[ri];
-      uint64_t m = (s == tc) ? sm.tmask[tc] : inliers_at<TH, TW>(sm, tc, TC, unpack_plane(sm.tplane[s]), p.eps);
       sm.cls[tc] = CLS_TEMPORAL;
-      sm.fmask[tc] = m;
       sm.runof[tc] = T + tr * TC + ri;
       sm.elig[tc] = 0;
     } else {
@@ -459,14 +629,14 @@ __device__ void grow_temporal(StripSmem<TH, TW> &sm, const EncParams &p, const F
 }
 
 // ----------------------------------------------------- phase 3: residuals
-// Block-wide exclusive scan of sm.cnt[0 .. n) in place; returns the total.
+// Block-wide exclusive scan of sm.cnt()[0 .. n) in place; returns the total.
 template <int TH, int TW>
 __device__ uint32_t block_exclusive_scan(StripSmem<TH, TW> &sm, int n) {
   const int tid = threadIdx.x;
   const int per = (n + kBlock - 1) / kBlock;
   const int b = tid * per, e = min(n, b + per);
   uint32_t local = 0;
-  for (int q = b; q < e; q++) local += sm.cnt[q];
+  for (int q = b; q < e; q++) local += sm.cnt()[q];
   // wave inclusive scan
   uint32_t x = local;
   const int lane = tid & 63, wv = tid >> 6;
@@ -485,8 +655,8 @@ __device__ uint32_t block_exclusive_scan(StripSmem<TH, TW> &sm, int n) {
   }
   uint32_t run = base + x - local;
   for (int q = b; q < e; q++) {
-    uint32_t c = sm.cnt[q];
-    sm.cnt[q] = run;
+    uint32_t c = sm.cnt()[q];
+    sm.cnt()[q] = run;
     run += c;
   }
   __syncthreads();
@@ -522,7 +692,7 @@ __device__ void residuals_and_streams(StripSmem<TH, TW> &sm, const SensorDev &s,
 #pragma unroll
     for (int i = 0; i < TH; i++) {
       uint32_t rowbits = (uint32_t)((V >> (i * TW)) & ((1ull << TW) - 1ull));
-      sm.cnt[i * TC + tc] = __popc((uint32_t)((R >> (i * TW)) & ((1ull << TW) - 1ull)));
+      sm.cnt()[i * TC + tc] = __popc((uint32_t)((R >> (i * TW)) & ((1ull << TW) - 1ull)));
       int bit = i * W + tc * TW;
       if (rowbits) atomicOr(&sm.occ[bit >> 5], rowbits << (bit & 31));
     }
@@ -543,7 +713,7 @@ __device__ void residuals_and_streams(StripSmem<TH, TW> &sm, const SensorDev &s,
     uint64_t fm = cov ? sm.fmask[tc] : 0ull;
 #pragma unroll
     for (int i = 0; i < TH; i++) {
-      uint32_t o = sm.cnt[i * TC + tc];
+      uint32_t o = sm.cnt()[i * TC + tc];
 #pragma unroll
       for (int k = 0; k < TW; k++) {
         int j = i * TW + k;
@@ -601,16 +771,22 @@ __device__ void residuals_and_streams(StripSmem<TH, TW> &sm, const SensorDev &s,
     st[PC_SS_VALID] = red[0];
     st[PC_SS_RES] = total;
     for (int c = 0; c < 4; c++) st[PC_SS_TILES + c] = red[1 + c];
-    st[PC_SS_SRUNS] = sm.misc[0];
-    st[PC_SS_PRUNS] = sm.misc[1];
+    st[PC_SS_SRUNS] = sm.misc[M_SRUNS];
+    st[PC_SS_PRUNS] = sm.misc[M_PRUNS];
     st[PC_SS_FITS] = red[5];
     st[PC_SS_FP64] = red[6];
     st[PC_SS_STATUS] = red[7] ? PC_STATUS_RANGE : 0u;
-    st[PC_SS_SEEDED] = sm.misc[2];
-    st[PC_SS_FALLBACK] = sm.misc[3];
+    st[PC_SS_SEEDED] = sm.misc[M_SEEDED];
+    st[PC_SS_FALLBACK] = sm.misc[M_FALLBACK];
     for (int q = PC_SS_FALLBACK + 1; q < PC_STRIP_STATS; q++) st[q] = 0;
     f.nres[tr] = (int32_t)total;
   }
+}
+
+// Valid-pixel counts of the strip's tiles.
+template <int TH, int TW>
+__device__ __forceinline__ void count_valid(StripSmem<TH, TW> &sm, int TC) {
+  for (int tc = threadIdx.x; tc < TC; tc += kBlock) sm.nv[tc] = (uint8_t)__popcll(valid_bits<TH, TW>(sm, tc));
 }
 
 // Key frame, one tile-row strip (Sec. III-C).
@@ -623,21 +799,18 @@ __device__ void key_strip(char *smem_raw, const StripSrc &src, const SensorDev &
   strip_init<TH, TW>(sm, s, tr);
   load_source<TH, TW>(sm, src, s, tr);
   __syncthreads();
+  count_valid<TH, TW>(sm, TC);
+  __syncthreads();
   int fits = 0, fp64 = 0;
+  own_fits<TH, TW>(sm, p, TC, [](int) { return true; }, fits, fp64);
   for (int tc = threadIdx.x; tc < TC; tc += kBlock) {
-    TileRows<TH, TW> T = tile_at<TH, TW>(sm, tc, TC, true);
-    sm.nv[tc] = (uint8_t)T.nV;
-    FitResult R = own_fit(T, p, fits, fp64);
-    sm.plane[tc] = pack_plane(R.P);
-    sm.omask[tc] = R.mask;
-    sm.stat[tc] = (uint8_t)R.status;
+    Plane P = unpack_plane(sm.plane[tc]);
     pc_tile_rec rec;
-    rec.a = R.P.a; rec.b = R.P.b; rec.c = R.P.c;
-    rec.axis = (uint8_t)R.P.k; rec.status = (uint8_t)R.status; rec.iters = (uint8_t)R.iters; rec.t_status = 0;
-    rec.mask = R.mask; rec.t_mask = 0; rec.t_c = 0.f; rec.t_iters = 0; rec.seeded = 0; rec.pad[0] = rec.pad[1] = 0;
+    rec.a = P.a; rec.b = P.b; rec.c = P.c;
+    rec.axis = (uint8_t)P.k; rec.status = sm.stat[tc]; rec.iters = sm.iters[tc]; rec.t_status = 0;
+    rec.mask = sm.omask[tc]; rec.t_mask = 0; rec.t_c = 0.f; rec.t_iters = 0; rec.seeded = 0; rec.pad[0] = rec.pad[1] = 0;
     f.tiles[tr * TC + tc] = rec;
   }
-  __syncthreads();
   grow_spatial<TH, TW>(sm, p, f, tr, false);
   if (threadIdx.x == 0) f.nruns[f.TR + tr] = 0;
   __syncthreads();
@@ -654,49 +827,34 @@ __device__ void pred_strip(char *smem_raw, const FrameDev &key, const StripSrc &
   strip_init<TH, TW>(sm, s, tr);
   load_source<TH, TW>(sm, src, s, tr);
   __syncthreads();
-  int fits = 0, fp64 = 0;
-  // temporal fits against the key frame's run planes
+  count_valid<TH, TW>(sm, TC);
   for (int tc = threadIdx.x; tc < TC; tc += kBlock) {
-    const int t = tr * TC + tc;
-    TileRows<TH, TW> T = tile_at<TH, TW>(sm, tc, TC, true);
-    sm.nv[tc] = (uint8_t)T.nV;
-    int kr = key.cls[t] == CLS_SPATIAL ? key.run_of[t] : -1;
-    sm.krun[tc] = kr;
-    FitResult R{Plane{0, 0.f, 0.f, 0.f}, 0ull, 0, 0};
-    if (kr >= 0) {
-      pc_run q = key.sruns[kr];
-      R = temporal_fit(T, Plane{q.axis, q.a, q.b, q.c}, p);
-    }
-    sm.tplane[tc] = pack_plane(R.P);
-    sm.tmask[tc] = R.mask;
-    sm.tstat[tc] = (uint8_t)R.status;
     sm.cls[tc] = CLS_EMPTY;
     sm.elig[tc] = 0;
+  }
+  __syncthreads();
+  int fits = 0, fp64 = 0;
+  // temporal fits against the key frame's run planes, temporal runs
+  temporal_fits<TH, TW>(sm, key, p, tr, TC);
+  for (int tc = threadIdx.x; tc < TC; tc += kBlock) {
     pc_tile_rec rec;
     rec.a = 0.f; rec.b = 0.f; rec.c = 0.f; rec.axis = 0; rec.status = 0; rec.iters = 0;
-    rec.t_status = (uint8_t)R.status; rec.mask = 0; rec.t_mask = R.mask; rec.t_c = R.P.c;
-    rec.t_iters = (uint8_t)R.iters; rec.seeded = 0; rec.pad[0] = rec.pad[1] = 0;
-    f.tiles[t] = rec;
+    rec.t_status = sm.stat[tc]; rec.mask = 0; rec.t_mask = sm.omask[tc]; rec.t_c = sm.plane[tc].z;
+    rec.t_iters = sm.iters[tc]; rec.seeded = 0; rec.pad[0] = rec.pad[1] = 0;
+    f.tiles[tr * TC + tc] = rec;
   }
-  __syncthreads();
   grow_temporal<TH, TW>(sm, p, f, tr);
   __syncthreads();
-  // own fits of the tiles left over
+  // own fits of the tiles left over, spatial runs
+  own_fits<TH, TW>(sm, p, TC, [&](int tc) { return sm.elig[tc] != 0; }, fits, fp64);
   for (int tc = threadIdx.x; tc < TC; tc += kBlock) {
-    FitResult R{Plane{0, 0.f, 0.f, 0.f}, 0ull, ST_EMPTY, 0};
-    if (sm.elig[tc]) {
-      TileRows<TH, TW> T = tile_at<TH, TW>(sm, tc, TC, true);
-      R = own_fit(T, p, fits, fp64);
-      pc_tile_rec *rec = &f.tiles[tr * TC + tc];
-      rec->a = R.P.a; rec->b = R.P.b; rec->c = R.P.c;
-      rec->axis = (uint8_t)R.P.k; rec->status = (uint8_t)R.status; rec->iters = (uint8_t)R.iters;
-      rec->mask = R.mask;
-    }
-    sm.plane[tc] = pack_plane(R.P);
-    sm.omask[tc] = R.mask;
-    sm.stat[tc] = (uint8_t)R.status;
+    if (!sm.elig[tc]) continue;
+    Plane P = unpack_plane(sm.plane[tc]);
+    pc_tile_rec *rec = &f.tiles[tr * TC + tc];
+    rec->a = P.a; rec->b = P.b; rec->c = P.c;
+    rec->axis = (uint8_t)P.k; rec->status = sm.stat[tc]; rec->iters = sm.iters[tc];
+    rec->mask = sm.omask[tc];
   }
-  __syncthreads();
   grow_spatial<TH, TW>(sm, p, f, tr, true);
   __syncthreads();
   residuals_and_streams<TH, TW>(sm, s, p, f, tr, fits, fp64);

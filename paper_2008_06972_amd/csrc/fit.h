@@ -53,6 +53,22 @@ __device__ __forceinline__ bool reproduces(const Plane &P, const Dir &d, float r
   return reproduces_exact(P.c, den, r, eps);
 }
 
+// One-ulp hardware reciprocal, reciprocal square root and square root: the
+// FP32 fit only needs to be accurate, not correctly rounded (the decisions
+// that must match the decoder bit for bit are made elsewhere).
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// acos to about 7e-5 rad: the polynomial of Abramowitz & Stegun 4.4.45
+// (Hastings) on [0, 1], reflected for negative arguments.
+__device__ __forceinline__ float acos_as(float x) {
+  const float ax = fabsf(x);
+  const float poly = fmaf(fmaf(fmaf(-0.0187293f, ax, 0.0742610f), ax, -0.2121144f), ax, 1.5707288f);
+  const float a = fsqrt(1.0f - ax) * poly;
+  return x < 0.0f ? 3.14159265358979f - a : a;
+}
+
 // Dominant axis (ties to the lower axis) and the stored coefficients.
 __device__ __forceinline__ Plane stored_form_f32(float nx, float ny, float nz, float c) {
   float ax = fabsf(nx), ay = fabsf(ny), az = fabsf(nz);
@@ -63,7 +79,8 @@ __device__ __forceinline__ Plane stored_form_f32(float nx, float ny, float nz, f
   float nk = k == 0 ? nx : (k == 1 ? ny : nz);
   float n1 = k == 0 ? ny : nx;
   float n2 = k == 2 ? ny : nz;
-  return Plane{k, n1 / nk, n2 / nk, c / nk};
+  float ik = frcp(nk);
+  return Plane{k, n1 * ik, n2 * ik, c * ik};
 }
 __device__ __forceinline__ Plane stored_form_f64(double nx, double ny, double nz, double c) {
   double ax = fabs(nx), ay = fabs(ny), az = fabs(nz);
@@ -93,7 +110,7 @@ __device__ __forceinline__ bool cross_eigvec(float a00, float a01, float a02, fl
   if (d1 > bd) { bx = x1; by = y1; bz = z1; bd = d1; }
   if (d2 > bd) { bx = x2; by = y2; bz = z2; bd = d2; }
   if (!(bd > 0.0f) || !isfinite(bd)) return false;
-  float inv = 1.0f / sqrtf(bd);
+  float inv = frsq(bd);
   x = bx * inv; y = by * inv; z = bz * inv;
   return true;
 }
@@ -109,14 +126,14 @@ __device__ __forceinline__ bool eig3_frame_f32(float a00, float a01, float a02, 
   float off = a01 * a01 + a02 * a02 + a12 * a12;
   float p2 = (b00 * b00 + b11 * b11 + b22 * b22 + 2.0f * off) * (1.0f / 6.0f);
   if (!(p2 > 0.0f)) return false;
-  float p = sqrtf(p2);
-  float ip = 1.0f / p;
+  float ip = frsq(p2);
+  float p = p2 * ip;
   float c00 = b00 * ip, c11 = b11 * ip, c22 = b22 * ip, c01 = a01 * ip, c02 = a02 * ip, c12 = a12 * ip;
   float det = c00 * (c11 * c22 - c12 * c12) - c01 * (c01 * c22 - c12 * c02) + c02 * (c01 * c12 - c11 * c02);
   float rr = fminf(1.0f, fmaxf(-1.0f, 0.5f * det));
-  float phi = acosf(rr) * (1.0f / 3.0f);
-  float l3 = q + 2.0f * p * cosf(phi);
-  float l1 = q + 2.0f * p * cosf(phi + 2.0943951023931953f);
+  float phi = acos_as(rr) * (1.0f / 3.0f);
+  float l3 = q + 2.0f * p * __cosf(phi);
+  float l1 = q + 2.0f * p * __cosf(phi + 2.0943951023931953f);
   if (!cross_eigvec(a00, a01, a02, a11, a12, a22, l1, nx, ny, nz)) return false;
   bool okl = cross_eigvec(a00, a01, a02, a11, a12, a22, l3, lx, ly, lz);
   if (okl) {
@@ -130,7 +147,7 @@ __device__ __forceinline__ bool eig3_frame_f32(float a00, float a01, float a02, 
     float uz = (ux == 0.f && uy == 0.f) ? 1.f : 0.f;
     lx = ny * uz - nz * uy; ly = nz * ux - nx * uz; lz = nx * uy - ny * ux;
   }
-  float il = 1.0f / sqrtf(lx * lx + ly * ly + lz * lz);
+  float il = frsq(lx * lx + ly * ly + lz * lz);
   lx *= il; ly *= il; lz *= il;
   return true;
 }
@@ -179,6 +196,42 @@ __device__ __forceinline__ void jacobi3(T a00, T a01, T a02, T a11, T a12, T a22
   if (a22 < m) { m = a22; vx = v02; vy = v12; vz = v22; }
   l1 = t_min(a00, t_min(a11, a22));
   l3 = t_max(a00, t_max(a11, a22));
+  l2 = a00 + a11 + a22 - l1 - l3;
+}
+
+// The FP32 Jacobi used on the nearly diagonal scatter of the rotated frame,
+// with hardware reciprocal and square roots.
+__device__ __forceinline__ void jacobi3_f32(float a00, float a01, float a02, float a11, float a12, float a22, int sweeps,
+                                            float &vx, float &vy, float &vz, float &l1, float &l2, float &l3) {
+  float v00 = 1, v01 = 0, v02 = 0, v10 = 0, v11 = 1, v12 = 0, v20 = 0, v21 = 0, v22 = 1;
+#define PCC_JACOBI_ROT_F32(app, aqq, apq, arp, arq, vp0, vq0, vp1, vq1, vp2, vq2)          \
+  if (apq != 0.0f) {                                                                        \
+    float th_ = (aqq - app) * frcp(2.0f * apq);                                             \
+    float r_ = frcp(fabsf(th_) + fsqrt(fmaf(th_, th_, 1.0f)));                              \
+    float t_ = th_ >= 0.0f ? r_ : -r_;                                                      \
+    float c_ = frsq(fmaf(t_, t_, 1.0f)), s_ = t_ * c_;                                      \
+    float np_ = app - t_ * apq, nq_ = aqq + t_ * apq;                                       \
+    float rp_ = c_ * arp - s_ * arq, rq_ = s_ * arp + c_ * arq;                             \
+    app = np_; aqq = nq_; apq = 0.0f; arp = rp_; arq = rq_;                                 \
+    float w0_ = c_ * vp0 - s_ * vq0, w1_ = s_ * vp0 + c_ * vq0; vp0 = w0_; vq0 = w1_;       \
+    w0_ = c_ * vp1 - s_ * vq1; w1_ = s_ * vp1 + c_ * vq1; vp1 = w0_; vq1 = w1_;              \
+    w0_ = c_ * vp2 - s_ * vq2; w1_ = s_ * vp2 + c_ * vq2; vp2 = w0_; vq2 = w1_;              \
+  }
+  for (int sweep = 0; sweep < sweeps; sweep++) {
+    // the small eigenvalues can be far below the largest: only an exactly
+    // diagonal matrix ends the sweeps early
+    if (a01 == 0.0f && a02 == 0.0f && a12 == 0.0f) break;
+    PCC_JACOBI_ROT_F32(a00, a11, a01, a02, a12, v00, v01, v10, v11, v20, v21)
+    PCC_JACOBI_ROT_F32(a00, a22, a02, a01, a12, v00, v02, v10, v12, v20, v22)
+    PCC_JACOBI_ROT_F32(a11, a22, a12, a01, a02, v01, v02, v11, v12, v21, v22)
+  }
+#undef PCC_JACOBI_ROT_F32
+  float m = a00;
+  vx = v00; vy = v10; vz = v20;
+  if (a11 < m) { m = a11; vx = v01; vy = v11; vz = v21; }
+  if (a22 < m) { m = a22; vx = v02; vy = v12; vz = v22; }
+  l1 = fminf(a00, fminf(a11, a22));
+  l3 = fmaxf(a00, fmaxf(a11, a22));
   l2 = a00 + a11 + a22 - l1 - l3;
 }
 
@@ -238,15 +291,42 @@ __device__ __forceinline__ void each_rolled(const Tile &T, F f) {
 
 __device__ __forceinline__ float bitw(uint64_t S, int j) { return (float)((S >> j) & 1ull); }
 
-// Pixels of the tile that plane P reproduces within eps.
+// Pixels of the tile that plane P reproduces within eps (the decoder's
+// test).  Branch-free over the pixels with the one-ulp reciprocal; the few
+// pixels whose |t - r| lies within rounding reach of eps are decided
+// afterwards with the correctly rounded division.
 template <class Tile>
 __device__ __forceinline__ uint64_t inliers(const Tile &T, const Plane &P, float eps) {
-  uint32_t lo = 0, hi = 0;
+  const bool isx = P.k == 0, isz = P.k == 2;
+  uint32_t lo = 0, hi = 0, ulo = 0, uhi = 0;
   T.each([&](int j, float r, const Dir &d) {
-    bool ok = r > 0.0f && reproduces(P, d, r, eps);
-    if (j < 32) lo |= (uint32_t)ok << (j & 31); else hi |= (uint32_t)ok << (j & 31);
+    const float dk = isz ? d.z : (isx ? d.x : d.y);
+    const float dk1 = isx ? d.y : d.x;
+    const float dk2 = isz ? d.y : d.z;
+    const float den = fmaf(P.b, dk2, fmaf(P.a, dk1, dk));
+    const float t0 = P.c * __builtin_amdgcn_rcpf(den);
+    const float diff = fabsf(t0 - r);
+    const float margin = fmaf(fabsf(t0), 1e-6f, 1e-7f);
+    const bool valid = r > 0.0f;
+    const bool sure_in = valid & (diff < eps - margin) & (t0 > 0.0f);
+    const bool unsure = valid & !(diff < eps - margin) & !(diff > eps + margin);
+    if (j < 32) {
+      lo |= (uint32_t)sure_in << (j & 31);
+      ulo |= (uint32_t)unsure << (j & 31);
+    } else {
+      hi |= (uint32_t)sure_in << (j & 31);
+      uhi |= (uint32_t)unsure << (j & 31);
+    }
   });
-  return ((uint64_t)hi << 32) | lo;
+  uint64_t m = ((uint64_t)hi << 32) | lo, u = ((uint64_t)uhi << 32) | ulo;
+  while (u) {
+    const int j = __ffsll((long long)u) - 1;
+    u &= u - 1;
+    const int i = j / Tile::TWc, k = j % Tile::TWc;
+    const Dir d = dir_of(T.ce[i], T.se[i], T.cal[k * T.cstride], T.sal[k * T.cstride]);
+    if (reproduces_exact(P.c, plane_den(P, d), T.rp[j], eps)) m |= 1ull << j;
+  }
+  return m;
 }
 
 // FP64 least squares on the exact products r*d: two-pass centring, Jacobi.
@@ -287,11 +367,11 @@ __device__ __forceinline__ bool fit_plane_f64(const Tile &T, uint64_t S, Plane &
 //     small eigen-directions are accumulated free of the large one's
 //     rounding (elongated tiles: far ground seen by few beams);
 //  4. Jacobi on the nearly diagonal result, rotated back.
-// FP64 on the exact products when the two smallest eigenvalues are within
-// kNearDegenerate of the largest.  Returns false if degenerate.
+// Returns false when FP32 cannot decide: the two smallest eigenvalues are
+// within kNearDegenerate of the largest (the caller then fits in FP64).
 // Pixels outside S enter every sum with weight 0 (no branches).
 template <class Tile>
-__device__ __forceinline__ bool fit_plane(const Tile &T, uint64_t S, Plane &P, int &fp64) {
+__device__ __forceinline__ bool fit_plane_f32(const Tile &T, uint64_t S, Plane &P) {
   float n = (float)__popcll(S);
   float sx = 0.f, sy = 0.f, sz = 0.f;
   T.each([&](int j, float r, const Dir &d) {
@@ -300,7 +380,8 @@ __device__ __forceinline__ bool fit_plane(const Tile &T, uint64_t S, Plane &P, i
     sy = fmaf(rw, d.y, sy);
     sz = fmaf(rw, d.z, sz);
   });
-  float mx = sx / n, my = sy / n, mz = sz / n;
+  const float in = frcp(n);
+  float mx = sx * in, my = sy * in, mz = sz * in;
   float cxx = 0.f, cxy = 0.f, cxz = 0.f, cyy = 0.f, cyz = 0.f, czz = 0.f;
   T.each([&](int j, float r, const Dir &d) {
     float w = bitw(S, j);
@@ -309,107 +390,49 @@ __device__ __forceinline__ bool fit_plane(const Tile &T, uint64_t S, Plane &P, i
     cyy = fmaf(ey, ey, cyy); cyz = fmaf(ey, ez, cyz); czz = fmaf(ez, ez, czz);
   });
   float ax, ay, az, lx, ly, lz;
-  if (eig3_frame_f32(cxx, cxy, cxz, cyy, cyz, czz, ax, ay, az, lx, ly, lz)) {
-    float bx = ly * az - lz * ay, by = lz * ax - lx * az, bz = lx * ay - ly * ax;   // a2 = a3 x a1
-    float q1 = 0.f, q2 = 0.f, q3 = 0.f;
-    float s11 = 0.f, s12 = 0.f, s13 = 0.f, s22 = 0.f, s23 = 0.f, s33 = 0.f;
-    T.each([&](int j, float r, const Dir &d) {
-      float w = bitw(S, j);
-      float ex = fmaf(r, d.x, -mx), ey = fmaf(r, d.y, -my), ez = fmaf(r, d.z, -mz);
-      float e1 = fmaf(ax, ex, fmaf(ay, ey, az * ez)) * w;
-      float e2 = fmaf(bx, ex, fmaf(by, ey, bz * ez)) * w;
-      float e3 = fmaf(lx, ex, fmaf(ly, ey, lz * ez)) * w;
-      q1 += e1; q2 += e2; q3 += e3;
-      s11 = fmaf(e1, e1, s11); s12 = fmaf(e1, e2, s12); s13 = fmaf(e1, e3, s13);
-      s22 = fmaf(e2, e2, s22); s23 = fmaf(e2, e3, s23); s33 = fmaf(e3, e3, s33);
-    });
-    float in = 1.0f / n;
-    float u1 = q1 * in, u2 = q2 * in, u3 = q3 * in;    // rounding left in the mean
-    s11 -= q1 * u1; s12 -= q1 * u2; s13 -= q1 * u3;
-    s22 -= q2 * u2; s23 -= q2 * u3; s33 -= q3 * u3;
-    float w1, w2, w3, l1, l2, l3;
-    jacobi3<float>(s11, s12, s13, s22, s23, s33, 4, w1, w2, w3, l1, l2, l3);
-    if ((l2 - l1) > kNearDegenerate * l3) {
-      float nx = w1 * ax + w2 * bx + w3 * lx;
-      float ny = w1 * ay + w2 * by + w3 * ly;
-      float nz = w1 * az + w2 * bz + w3 * lz;
-      float nn = 1.0f / sqrtf(nx * nx + ny * ny + nz * nz);
-      nx *= nn; ny *= nn; nz *= nn;
-      // offset through the exact-product mean: n . mean + n . (mean of e)
-      float ux = u1 * ax + u2 * bx + u3 * lx, uy = u1 * ay + u2 * by + u3 * ly, uz = u1 * az + u2 * bz + u3 * lz;
-      float c = (nx * mx + ny * my + nz * mz) + (nx * ux + ny * uy + nz * uz);
-      P = stored_form_f32(nx, ny, nz, c);
-      return true;
-    }
-  }
-  fp64++;
-  return fit_plane_f64(T, S, P);
+  if (!eig3_frame_f32(cxx, cxy, cxz, cyy, cyz, czz, ax, ay, az, lx, ly, lz)) return false;
+  float bx = ly * az - lz * ay, by = lz * ax - lx * az, bz = lx * ay - ly * ax;   // a2 = a3 x a1
+  float q1 = 0.f, q2 = 0.f, q3 = 0.f;
+  float s11 = 0.f, s12 = 0.f, s13 = 0.f, s22 = 0.f, s23 = 0.f, s33 = 0.f;
+  T.each([&](int j, float r, const Dir &d) {
+    float w = bitw(S, j);
+    float ex = fmaf(r, d.x, -mx), ey = fmaf(r, d.y, -my), ez = fmaf(r, d.z, -mz);
+    float e1 = fmaf(ax, ex, fmaf(ay, ey, az * ez)) * w;
+    float e2 = fmaf(bx, ex, fmaf(by, ey, bz * ez)) * w;
+    float e3 = fmaf(lx, ex, fmaf(ly, ey, lz * ez)) * w;
+    q1 += e1; q2 += e2; q3 += e3;
+    s11 = fmaf(e1, e1, s11); s12 = fmaf(e1, e2, s12); s13 = fmaf(e1, e3, s13);
+    s22 = fmaf(e2, e2, s22); s23 = fmaf(e2, e3, s23); s33 = fmaf(e3, e3, s33);
+  });
+  float u1 = q1 * in, u2 = q2 * in, u3 = q3 * in;    // rounding left in the mean
+  s11 -= q1 * u1; s12 -= q1 * u2; s13 -= q1 * u3;
+  s22 -= q2 * u2; s23 -= q2 * u3; s33 -= q3 * u3;
+  float w1, w2, w3, l1, l2, l3;
+  jacobi3_f32(s11, s12, s13, s22, s23, s33, 4, w1, w2, w3, l1, l2, l3);
+  if (!((l2 - l1) > kNearDegenerate * l3)) return false;
+  float nx = w1 * ax + w2 * bx + w3 * lx;
+  float ny = w1 * ay + w2 * by + w3 * ly;
+  float nz = w1 * az + w2 * bz + w3 * lz;
+  float nn = frsq(nx * nx + ny * ny + nz * nz);
+  nx *= nn; ny *= nn; nz *= nn;
+  // offset through the exact-product mean: n . mean + n . (mean of e)
+  float ux = u1 * ax + u2 * bx + u3 * lx, uy = u1 * ay + u2 * by + u3 * ly, uz = u1 * az + u2 * bz + u3 * lz;
+  float c = (nx * mx + ny * my + nz * mz) + (nx * ux + ny * uy + nz * uz);
+  P = stored_form_f32(nx, ny, nz, c);
+  return true;
 }
-
-struct FitResult {
-  Plane P;
-  uint64_t mask;
-  int status, iters;
-};
 
 // Points a tile must keep on its plane: max(min(min_pts, n), ceil(rho n)),
 // tabulated on the host in FP64.
 __device__ __forceinline__ int need_of(const EncParams &p, int n) { return p.need[n]; }
 
-// Own fit of a tile: fit, keep the pixels the plane reproduces, refit on
-// them, up to max_iter fits (converged when the kept set stops changing).
+// Offset of the key plane's stored form (normal held) through the pixels in
+// S: the mean of r * (d_k + a d_k1 + b d_k2) (Sec. III-D).
 template <class Tile>
-__device__ __forceinline__ FitResult own_fit(const Tile &T, const EncParams &p, int &fits, int &fp64) {
-  FitResult R{Plane{0, 0.f, 0.f, 0.f}, 0ull, ST_EMPTY, 0};
-  if (T.nV == 0) return R;
-  if (T.nV < p.min_pts) { R.status = ST_FEW; return R; }
-  uint64_t S = T.V;
-  for (int it = 1; it <= p.max_iter; it++) {
-    R.iters = it;
-    fits++;
-    if (!fit_plane(T, S, R.P, fp64)) {
-      R.status = ST_DEGENERATE;
-      R.mask = 0;
-      return R;
-    }
-    uint64_t S2 = inliers(T, R.P, p.eps);
-    R.mask = S2;
-    if (S2 == S) break;
-    if (__popcll(S2) < p.min_pts) {
-      R.status = ST_FAILED;
-      R.mask = 0;
-      return R;
-    }
-    S = S2;
-  }
-  R.status = __popcll(R.mask) >= need_of(p, T.nV) ? ST_ACCEPTED : ST_REJECTED;
-  return R;
-}
-
-// Temporal fit (Sec. III-D): the key plane's normal (k, a, b) is held and
-// only the offset varies; in the stored form the offset is the mean of
-// r * (d_k + a d_k1 + b d_k2) over the pixels kept.
-template <class Tile>
-__device__ __forceinline__ FitResult temporal_fit(const Tile &T, Plane Q, const EncParams &p) {
-  FitResult R{Q, 0ull, 1, 0};
-  if (T.nV < p.min_pts) return R;
-  uint64_t S = T.V;
-  for (int it = 1; it <= p.max_iter; it++) {
-    R.iters = it;
-    float sum = 0.f;
-    T.each([&](int j, float r, const Dir &d) { sum = fmaf(r * bitw(S, j), plane_den(Q, d), sum); });
-    R.P.c = sum / (float)__popcll(S);
-    uint64_t S2 = inliers(T, R.P, p.eps);
-    R.mask = S2;
-    if (S2 == S) break;
-    if (__popcll(S2) < p.min_pts) {
-      R.mask = 0;
-      return R;
-    }
-    S = S2;
-  }
-  R.status = __popcll(R.mask) >= need_of(p, T.nV) ? 2 : 1;
-  return R;
+__device__ __forceinline__ float temporal_offset(const Tile &T, const Plane &Q, uint64_t S) {
+  float sum = 0.f;
+  T.each([&](int j, float r, const Dir &d) { sum = fmaf(r * bitw(S, j), plane_den(Q, d), sum); });
+  return sum / (float)__popcll(S);
 }
 
 }  // namespace pcc

@@ -262,7 +262,7 @@ typedef struct {
 typedef struct pc_batch pc_batch;
 
 /* Device workspace a batch plan needs (descriptor table, work items, block
- * tables, counters, and 8 bytes per point for the strip bins). */
+ * tables, counters, and 16 bytes per point for staging and the strip bins). */
 size_t pc_batch_workspace_size(const pc_frame_desc *frames, int32_t nframes);
 
 /* Check the frames, build and upload the descriptor table into the

@@ -210,6 +210,9 @@ static pc_status get_sensor(pc_ctx *ctx, const pc_sensor *s, SensorEntry **out) 
   d.sa = e->dev + o.sa;
   d.beta0 = (float)atan2((double)t[o.eby], (double)t[o.ebx]);
   d.dth = (float)(6.283185307179586476925286766559 / (double)W);
+  d.inv_dth = (float)((double)W / 6.283185307179586476925286766559);
+  d.elev0 = s->elev_rad[0];
+  d.inv_de = (float)((double)(H - 1) / ((double)s->elev_rad[0] - (double)s->elev_rad[H - 1]));
   ctx->sensors.push_back(e);
   *out = e;
   return PC_OK;

@@ -3,13 +3,12 @@
 // A plan holds a device table of frame descriptors.  One replay runs:
 //   reset    zero the strip counters and queue counters (a kernel, so the
 //            graph holds no memset node)
-//   count    project every point (Eq. (1), (2), (6)) and count the points
-//            falling in each (frame, tile-row strip); one global atomic per
-//            (work-group, strip)
+//   count    project every point (Eq. (1), (2), (6)), stage it as (strip,
+//            LDS slot, range bits) and count the points of each (frame,
+//            tile-row strip); one global atomic per (work-group, strip)
 //   offsets  per frame, exclusive sum of the strip counts
-//   scatter  project again and write each point as (pixel within its strip,
-//            range bits) into its strip's bucket, reserving space once per
-//            (work-group, strip)
+//   scatter  move the staged points into their strips' buckets, reserving
+//            space once per (work-group, strip)
 //   key      persistent work-groups pull (key frame, strip) items from an
 //            atomic counter; each builds its strip from the bucket with LDS
 //            atomicMin (nearest point wins, Sec. III-D) and encodes it
@@ -28,6 +27,7 @@
 #include <vector>
 
 #include "encode_strip.h"
+#include "project.h"
 
 namespace pcc {
 
@@ -45,7 +45,9 @@ struct FrameDescDev {
   int pad0;
   SensorDev s;
   EncParams p;
-  uint2 *bucket;   // n entries: (pixel within strip, range bits)
+  uint2 *stage;    // n entries: (strip << 16 | LDS slot, range bits), ~0 for dropped points
+  uint2 *bucket;   // n entries: (LDS slot, range bits), grouped by strip
+  int twl;         // log2 tile_w
   int *bcount;     // [TR] points per strip
   int *boff;       // [TR] first bucket entry of each strip
   int *bcur;       // [TR] scatter cursors
@@ -60,76 +62,32 @@ __global__ void k_batch_reset(int *a, int64_t n) {
   for (; i < n; i += stride) a[i] = 0;
 }
 
-__device__ __forceinline__ int b_row_of(const float *cut, int H, float q) {
-  int lo = 1, hi = H;
-  while (lo < hi) {
-    int mid = (lo + hi) >> 1;
-    if (cut[mid] > q) lo = mid + 1; else hi = mid;
-  }
-  return lo - 1;
-}
-
-__device__ __forceinline__ float b_edge_side(const SensorDev &s, int u, float x, float y) {
-  float t = s.eby[u] * x;
-  return fmaf(s.ebx[u], y, -t);
-}
-
-__device__ __forceinline__ int b_column_of(const SensorDev &s, float x, float y) {
-  int W = s.W;
-  float rel = s.beta0 - atan2f(y, x);
-  int u = (int)floorf(rel / s.dth);
-  u %= W;
-  if (u < 0) u += W;
-  for (int step = 0; step <= W + 2; step++) {
-    if (b_edge_side(s, u, x, y) > 0.0f) { u = (u == 0) ? W - 1 : u - 1; continue; }
-    int un = (u + 1 == W) ? 0 : u + 1;
-    if (b_edge_side(s, un, x, y) <= 0.0f) { u = un; continue; }
-    return u;
-  }
-  return -1;
-}
-
-// The per-frame projection's arithmetic (Eq. (1), (2), (6)); false if the
-// point is dropped (non-finite, zero range, on the axis, outside the FOV).
-__device__ __forceinline__ bool project_point(const FrameDescDev &D, int64_t i, int &v, int &u, float &r) {
-  float x = D.xyz[3 * i], y = D.xyz[3 * i + 1], z = D.xyz[3 * i + 2];
-  if (D.hasM) {
-    const float *m = D.M.m;
-    float xx = fmaf(m[0], x, fmaf(m[1], y, fmaf(m[2], z, m[3])));
-    float yy = fmaf(m[4], x, fmaf(m[5], y, fmaf(m[6], z, m[7])));
-    float zz = fmaf(m[8], x, fmaf(m[9], y, fmaf(m[10], z, m[11])));
-    x = xx; y = yy; z = zz;
-  }
-  if (!isfinite(x) || !isfinite(y) || !isfinite(z)) return false;
-  float yy2 = y * y;
-  float rho2 = fmaf(x, x, yy2);
-  float zz2 = z * z;
-  r = sqrtf(fmaf(x, x, fmaf(y, y, zz2)));
-  if (!isfinite(r) || r == 0.0f || rho2 < 1e-12f) return false;
-  float q = z / sqrtf(rho2);
-  const SensorDev &s = D.s;
-  if (!(q < s.cut[0]) || q < s.cut[s.H]) return false;
-  v = b_row_of(s.cut, s.H, q);
-  u = b_column_of(s, x, y);
-  return u >= 0;
-}
-
 // blocks [first[f], first[f+1]) belong to frame f; owner[b] = f
 __global__ void __launch_bounds__(kBinBlock) k_batch_count(const FrameDescDev *__restrict__ d, const int *__restrict__ owner,
                                                            const int *__restrict__ first) {
   __shared__ int hist[256];
-  const int fidx = owner[blockIdx.x];
+  const int fidx = __builtin_amdgcn_readfirstlane(owner[blockIdx.x]);
   const FrameDescDev &D = d[fidx];
   const int th = D.p.th, TR = D.f.TR;
   for (int t = threadIdx.x; t < TR; t += kBinBlock) hist[t] = 0;
   __syncthreads();
   const int64_t base = (int64_t)(blockIdx.x - first[fidx]) * kBinChunk;
+  const auto *xyz = (const __attribute__((address_space(1))) float *)D.xyz;
+  auto *stage = (__attribute__((address_space(1))) uint64_t *)D.stage;    // x | y << 32
 #pragma unroll 2
   for (int q = 0; q < kBinPts; q++) {
-    int64_t i = base + q * kBinBlock + threadIdx.x;
+    const int64_t i = base + q * kBinBlock + threadIdx.x;
+    if (i >= D.n) break;
     int v, u;
     float r;
-    if (i < D.n && project_point(D, i, v, u, r)) atomicAdd(&hist[v / th], 1);
+    uint64_t e = ~0ull;
+    if (project_point(D.s, D.M, D.hasM, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], v, u, r) == PROJ_KEPT) {
+      const int strip = v / th;
+      const uint32_t x = ((uint32_t)strip << 16) | (uint32_t)strip_slot(v - strip * th, u, th, D.twl);
+      e = (uint64_t)x | ((uint64_t)__float_as_uint(r) << 32);
+      atomicAdd(&hist[strip], 1);
+    }
+    stage[i] = e;
   }
   __syncthreads();
   for (int t = threadIdx.x; t < TR; t += kBinBlock)
@@ -151,30 +109,25 @@ __global__ void k_batch_offsets(const FrameDescDev *__restrict__ d, int nframes)
 __global__ void __launch_bounds__(kBinBlock) k_batch_scatter(const FrameDescDev *__restrict__ d,
                                                              const int *__restrict__ owner, const int *__restrict__ first) {
   __shared__ int cnt[256], base[256], lim[256];
-  const int fidx = owner[blockIdx.x];
+  const int fidx = __builtin_amdgcn_readfirstlane(owner[blockIdx.x]);
   const FrameDescDev &D = d[fidx];
-  const int th = D.p.th, TR = D.f.TR, W = D.s.W;
+  const int TR = D.f.TR;
   for (int t = threadIdx.x; t < TR; t += kBinBlock) cnt[t] = 0;
   __syncthreads();
   const int64_t b0 = (int64_t)(blockIdx.x - first[fidx]) * kBinChunk;
-  int strip[kBinPts], slot[kBinPts];
-  uint32_t px[kBinPts], rb[kBinPts];
+  // entries are x | y << 32: x = strip << 16 | slot (~0 dropped), y = range bits
+  const auto *stage = (const __attribute__((address_space(1))) uint64_t *)D.stage;
+  auto *bucket = (__attribute__((address_space(1))) uint64_t *)D.bucket;
+  uint64_t e[kBinPts];
+  int slot[kBinPts];
 #pragma unroll
   for (int q = 0; q < kBinPts; q++) {
-    int64_t i = b0 + q * kBinBlock + threadIdx.x;
-    int v, u;
-    float r;
-    strip[q] = -1;
-    slot[q] = 0;
-    px[q] = 0;
-    rb[q] = 0;
-    if (i < D.n && project_point(D, i, v, u, r)) {
-      strip[q] = v / th;
-      slot[q] = atomicAdd(&cnt[strip[q]], 1);
-      px[q] = (uint32_t)((v - strip[q] * th) * W + u);
-      rb[q] = __float_as_uint(r);
-    }
+    const int64_t i = b0 + q * kBinBlock + threadIdx.x;
+    e[q] = i < D.n ? (uint64_t)stage[i] : ~0ull;
   }
+#pragma unroll
+  for (int q = 0; q < kBinPts; q++)
+    slot[q] = (uint32_t)e[q] != 0xffffffffu ? atomicAdd(&cnt[(uint32_t)e[q] >> 16], 1) : 0;
   __syncthreads();
   for (int t = threadIdx.x; t < TR; t += kBinBlock)
     if (cnt[t]) {
@@ -182,13 +135,15 @@ __global__ void __launch_bounds__(kBinBlock) k_batch_scatter(const FrameDescDev 
       lim[t] = D.boff[t] + D.bcount[t];
     }
   __syncthreads();
-  // The two passes project identically, so every entry fits its strip's
-  // range; the limit only keeps a bucket from spilling into its neighbour.
+  // Both passes see the same staged entries, so every entry fits its
+  // strip's range; the limit only keeps a bucket from spilling into its
+  // neighbour.
 #pragma unroll
   for (int q = 0; q < kBinPts; q++)
-    if (strip[q] >= 0) {
-      int at = base[strip[q]] + slot[q];
-      if (at < lim[strip[q]]) D.bucket[at] = make_uint2(px[q], rb[q]);
+    if ((uint32_t)e[q] != 0xffffffffu) {
+      const int strip = (uint32_t)e[q] >> 16;
+      const int at = base[strip] + slot[q];
+      if (at < lim[strip]) bucket[at] = e[q] & 0xffffffff0000ffffull;
     }
 }
 
@@ -377,7 +332,7 @@ static pc_status batch_sizes(const pc_frame_desc *frames, int32_t nframes, Batch
     items += tr;
     strips += tr;
     bb += (F.n + kBinChunk - 1) / kBinChunk;
-    buckets += a256(sizeof(uint2) * (size_t)F.n);
+    buckets += 2 * a256(sizeof(uint2) * (size_t)F.n);
   }
   if (items > 0x7fffffff || bb > 0x7fffffff) return set_error(PC_ERR_CAPACITY, "batch too large");
   B.nitems = (int)items;
@@ -447,6 +402,9 @@ pc_status pc_batch_create(pc_ctx *ctx, const pc_frame_desc *frames, int32_t nfra
     D.f = frame_dev(F.out, L);
     D.bucket = (uint2 *)bucket_ws;
     bucket_ws += a256(sizeof(uint2) * (size_t)F.n);
+    D.stage = (uint2 *)bucket_ws;
+    bucket_ws += a256(sizeof(uint2) * (size_t)F.n);
+    D.twl = __builtin_ctz((unsigned)F.params->tile_w);
     D.bcount = strip_counts + strip_at;
     D.boff = strip_counts + B.strips + strip_at;
     D.bcur = strip_counts + 2 * B.strips + strip_at;

@@ -123,6 +123,13 @@ __host__ __device__ inline size_t strip_lds_bytes(int th, int tw, int W, bool pr
   return 0;
 }
 
+// LDS slot of pixel (row i of the strip, column u) in StripSmem::r: tiles
+// of th*tw ranges (row-major inside the tile) at a stride of th*tw + 4.
+__host__ __device__ inline int strip_slot(int i, int u, int th, int tw_log2) {
+  const int tw = 1 << tw_log2;
+  return (u >> tw_log2) * (th * tw + 4) + i * tw + (u & (tw - 1));
+}
+
 // misc[] slots
 constexpr int M_SRUNS = 0, M_PRUNS = 1, M_SEEDED = 2, M_FALLBACK = 3, M_LIST = 8, M_F64 = 10;
 
@@ -183,9 +190,10 @@ __device__ __forceinline__ void load_strip(StripSmem<TH, TW> &sm, const float *_
 }
 
 // Where a strip's ranges come from: a range image (0 = empty), or the
-// strip's bucket of (pixel within the strip, range bits) entries from the
-// batched binning pass, resolved here with LDS atomicMin (nearest point
-// wins, Sec. III-D).  range_out, if set, receives the strip's range image.
+// strip's bucket of (LDS slot, range bits) entries from the batched binning
+// pass (slots as strip_slot gives them), resolved here with LDS atomicMin:
+// the nearest point wins (Sec. III-D).  range_out, if set, receives the
+// strip's range image.
 struct StripSrc {
   const float *range;
   const uint2 *bucket;     // frame's bucket entries
@@ -196,7 +204,7 @@ struct StripSrc {
 
 template <int TH, int TW>
 __device__ __forceinline__ void load_source(StripSmem<TH, TW> &sm, const StripSrc &src, const SensorDev &s, int tr) {
-  constexpr int NP = StripSmem<TH, TW>::NP;
+  constexpr int NP = StripSmem<TH, TW>::NP, U = 8;
   const int W = s.W, TC = W / TW, tid = threadIdx.x;
   if (!src.bucket) {
     load_strip<TH, TW>(sm, src.range, s, tr);
@@ -205,12 +213,20 @@ __device__ __forceinline__ void load_source(StripSmem<TH, TW> &sm, const StripSr
     for (int e = tid; e < TC * NP; e += kBlock) ri[e] = 0x7f800000u;   // +inf: empty
     __syncthreads();
     const int n = src.bcount[tr];
-    const uint2 *b = src.bucket + src.boff[tr];
-    for (int q = tid; q < n; q += kBlock) {
-      uint2 en = b[q];
-      if (en.x >= (uint32_t)(TH * W)) continue;
-      int i = (int)en.x / W, u = (int)en.x - i * W;
-      atomicMin(&ri[(u / TW) * NP + i * TW + (u % TW)], en.y);
+    // entry = slot | range bits << 32
+    const auto *b = (const __attribute__((address_space(1))) uint64_t *)(src.bucket + src.boff[tr]);
+    const uint32_t lim = (uint32_t)(TC * NP);
+    // U entries in flight per thread before their atomics
+    for (int q0 = tid; q0 < n; q0 += U * kBlock) {
+      uint64_t en[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int q = q0 + u * kBlock;
+        en[u] = q < n ? (uint64_t)b[q] : ~0ull;
+      }
+#pragma unroll
+      for (int u = 0; u < U; u++)
+        if ((uint32_t)en[u] < lim) atomicMin(&ri[(uint32_t)en[u]], (uint32_t)(en[u] >> 32));
     }
     __syncthreads();
     for (int e = tid; e < TC * NP; e += kBlock)

@@ -277,18 +277,6 @@ struct TileRows {
   }
 };
 
-// Rolled variant reading everything from LDS (rare FP64 path: small code,
-// few registers).
-template <class Tile, class F>
-__device__ __forceinline__ void each_rolled(const Tile &T, F f) {
-  asm volatile("" ::: "memory");
-#pragma unroll 1
-  for (int j = 0; j < Tile::N; j++) {
-    const int i = j / Tile::TWc, k = j % Tile::TWc;
-    f(j, T.rp[j], dir_of(T.ce[i], T.se[i], T.cal[k * T.cstride], T.sal[k * T.cstride]));
-  }
-}
-
 __device__ __forceinline__ float bitw(uint64_t S, int j) { return (float)((S >> j) & 1ull); }
 
 // Pixels of the tile that plane P reproduces within eps (the decoder's
@@ -330,24 +318,25 @@ __device__ __forceinline__ uint64_t inliers(const Tile &T, const Plane &P, float
 }
 
 // FP64 least squares on the exact products r*d: two-pass centring, Jacobi.
-// Rare path (near-degenerate scatter), rolled loops.
+// Rare path (near-degenerate scatter).
 template <class Tile>
 __device__ __forceinline__ bool fit_plane_f64(const Tile &T, uint64_t S, Plane &P) {
   double m0 = 0, m1 = 0, m2 = 0;
-  each_rolled(T, [&](int j, float rf, const Dir &d) {
-    double w = (double)((S >> j) & 1ull);
-    double r = (double)rf * w;
-    m0 += r * (double)d.x; m1 += r * (double)d.y; m2 += r * (double)d.z;
+  T.each([&](int j, float rf, const Dir &d) {
+    const double r = ((S >> j) & 1ull) ? (double)rf : 0.0;
+    m0 = fma(r, (double)d.x, m0);
+    m1 = fma(r, (double)d.y, m1);
+    m2 = fma(r, (double)d.z, m2);
   });
-  double dn = (double)__popcll(S);
+  const double dn = (double)__popcll(S);
   m0 /= dn; m1 /= dn; m2 /= dn;
   double a00 = 0, a01 = 0, a02 = 0, a11 = 0, a12 = 0, a22 = 0;
-  each_rolled(T, [&](int j, float rf, const Dir &d) {
-    double w = (double)((S >> j) & 1ull);
-    double r = (double)rf;
-    double e0 = (r * (double)d.x - m0) * w, e1 = (r * (double)d.y - m1) * w, e2 = (r * (double)d.z - m2) * w;
-    a00 += e0 * e0; a01 += e0 * e1; a02 += e0 * e2;
-    a11 += e1 * e1; a12 += e1 * e2; a22 += e2 * e2;
+  T.each([&](int j, float rf, const Dir &d) {
+    const double w = ((S >> j) & 1ull) ? 1.0 : 0.0;
+    const double r = (double)rf;
+    const double e0 = fma(r, (double)d.x, -m0) * w, e1 = fma(r, (double)d.y, -m1) * w, e2 = fma(r, (double)d.z, -m2) * w;
+    a00 = fma(e0, e0, a00); a01 = fma(e0, e1, a01); a02 = fma(e0, e2, a02);
+    a11 = fma(e1, e1, a11); a12 = fma(e1, e2, a12); a22 = fma(e2, e2, a22);
   });
   double vx, vy, vz, l1, l2, l3;
   jacobi3<double>(a00, a01, a02, a11, a12, a22, 32, vx, vy, vz, l1, l2, l3);

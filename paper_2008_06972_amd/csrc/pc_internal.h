@@ -25,6 +25,8 @@ struct SensorDev {
   int H, W;
   float beta0;          // angle of column 0's leading edge (search start only)
   float dth;            // 2 pi / W (search start only)
+  float inv_dth;        // W / (2 pi) (search start only)
+  float elev0, inv_de;  // first beam's elevation, beams per radian (search start only)
   const float *cut;     // H+1: tan of row cuts, [0] top edge, [H] bottom edge
   const float *ebx, *eby;   // W: leading-edge unit vectors
   const float *ce, *se;     // H: cos/sin of beam elevation

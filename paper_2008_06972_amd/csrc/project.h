@@ -1,0 +1,111 @@
+// Point to pixel (Sec. III-B, Eq. (1)-(2)) with the rigid transform of
+// predicted frames (Sec. III-D, Eq. (6)), shared by the per-frame
+// projection kernel and the batched binning kernels.
+//
+// All arithmetic that decides a bin is FP32 with the operation order written
+// out (explicit fmaf, correctly rounded sqrt and division), so bins are
+// reproducible bit for bit.  Row and column come from table comparisons
+// against the sensor's cut tangents and column edge vectors; the angle
+// estimates that pick the first table entry to compare are only search
+// starts, so their accuracy affects the speed, never the bin.
+#pragma once
+#include "pc_internal.h"
+
+namespace pcc {
+
+// Loads through the global address space (the tables live in device memory).
+template <class T>
+__device__ __forceinline__ T gload(const T *p) {
+  return *(const __attribute__((address_space(1))) T *)p;
+}
+
+// atan on [-1, 1] to about 1e-5 rad: the odd polynomial of Abramowitz &
+// Stegun 4.4.49.
+__device__ __forceinline__ float atan_unit_as(float x) {
+  const float x2 = x * x;
+  float p = fmaf(0.0208351f, x2, -0.0851330f);
+  p = fmaf(p, x2, 0.1801410f);
+  p = fmaf(p, x2, -0.3302995f);
+  p = fmaf(p, x2, 0.9998660f);
+  return p * x;
+}
+
+// atan2 to about 1e-5 rad (octant reduction of the polynomial above);
+// (x, y) must not both be zero.
+__device__ __forceinline__ float atan2_as(float y, float x) {
+  const float ax = fabsf(x), ay = fabsf(y);
+  const float a = atan_unit_as(fminf(ax, ay) * __builtin_amdgcn_rcpf(fmaxf(ax, ay)));
+  float t = ay > ax ? 1.57079632679f - a : a;
+  t = x < 0.0f ? 3.14159265359f - t : t;
+  return y < 0.0f ? -t : t;
+}
+
+// Row: the v with cut[v] > q >= cut[v + 1] (cuts descend; the caller has
+// checked cut[0] > q >= cut[H]), i.e. the number of interior cuts above q.
+// Start at the beam nearest the point's elevation and walk.
+__device__ __forceinline__ int row_of(const SensorDev &s, float q) {
+  const int H = s.H;
+  const float e = fabsf(q) <= 1.0f ? atan_unit_as(q)
+                                    : copysignf(1.57079632679f, q) - atan_unit_as(__builtin_amdgcn_rcpf(q));
+  int v = (int)fmaf(s.elev0 - e, s.inv_de, 0.5f);
+  v = min(max(v, 0), H - 1);
+  for (int step = 0; step <= H; step++) {
+    if (gload(s.cut + v) <= q) { v--; continue; }
+    if (gload(s.cut + v + 1) > q) { v++; continue; }
+    return v;
+  }
+  return -1;
+}
+
+__device__ __forceinline__ float edge_side(const SensorDev &s, int u, float x, float y) {
+  float t = gload(s.eby + u) * x;
+  return fmaf(gload(s.ebx + u), y, -t);
+}
+
+// Column: the unique u with side(u) <= 0 < side(u + 1); start from the
+// azimuth's bin and walk (the walk ends within one step for any estimate
+// error below a bin; it is bounded by W steps in any case).
+__device__ __forceinline__ int column_of(const SensorDev &s, float x, float y) {
+  const int W = s.W;
+  const float rel = s.beta0 - atan2_as(y, x);
+  int u = (int)floorf(rel * s.inv_dth);
+  u %= W;
+  if (u < 0) u += W;
+  for (int step = 0; step <= W + 2; step++) {
+    if (edge_side(s, u, x, y) > 0.0f) { u = (u == 0) ? W - 1 : u - 1; continue; }
+    int un = (u + 1 == W) ? 0 : u + 1;
+    if (edge_side(s, un, x, y) <= 0.0f) { u = un; continue; }
+    return u;
+  }
+  return -1;
+}
+
+enum { PROJ_KEPT = 0, PROJ_NONFINITE = 1, PROJ_FOV = 2 };
+
+// Transform (if hasM), range, row and column of one point.  Returns
+// PROJ_KEPT with v, u, r set, or why the point is dropped: non-finite
+// coordinates or a zero range, or outside the field of view (on the axis,
+// above the top or below the bottom edge).
+__device__ __forceinline__ int project_point(const SensorDev &s, const Mat12 &M, int hasM, float x, float y, float z,
+                                             int &v, int &u, float &r) {
+  if (hasM) {
+    const float xx = fmaf(M.m[0], x, fmaf(M.m[1], y, fmaf(M.m[2], z, M.m[3])));
+    const float yy = fmaf(M.m[4], x, fmaf(M.m[5], y, fmaf(M.m[6], z, M.m[7])));
+    const float zz = fmaf(M.m[8], x, fmaf(M.m[9], y, fmaf(M.m[10], z, M.m[11])));
+    x = xx; y = yy; z = zz;
+  }
+  if (!isfinite(x) || !isfinite(y) || !isfinite(z)) return PROJ_NONFINITE;
+  const float yy2 = y * y;
+  const float rho2 = fmaf(x, x, yy2);
+  const float zz2 = z * z;
+  r = sqrtf(fmaf(x, x, fmaf(y, y, zz2)));
+  if (!isfinite(r) || r == 0.0f) return PROJ_NONFINITE;
+  if (rho2 < 1e-12f) return PROJ_FOV;
+  const float q = z / sqrtf(rho2);
+  if (!(q < gload(s.cut)) || q < gload(s.cut + s.H)) return PROJ_FOV;
+  v = row_of(s, q);
+  u = column_of(s, x, y);
+  return (v < 0 || u < 0) ? PROJ_FOV : PROJ_KEPT;
+}
+
+}  // namespace pcc

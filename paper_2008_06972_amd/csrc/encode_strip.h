@@ -461,21 +461,6 @@ __device__ __forceinline__ uint64_t inliers_at(const StripSmem<TH, TW> &sm, int 
   return inliers(tile_at<TH, TW>(sm, tc), P, eps);
 }
 
-// Reach of a run started at tile s with plane P: the number of following
-// tiles (at most kReach) it extends over: tile t joins while allowed(s, t)
-// and P reproduces at least need(n) of its pixels.
-template <int TH, int TW, class Allowed>
-__device__ __forceinline__ int reach_of(const StripSmem<TH, TW> &sm, const EncParams &p, const Plane &P, int s, int TC,
-                                        Allowed allowed) {
-  int e = 0;
-  for (int t = s + 1; t < TC && e < kReach; t++) {
-    if (!allowed(s, t)) break;
-    if (__popcll(inliers_at<TH, TW>(sm, t, P, p.eps)) < need_of(p, sm.nv[t])) break;
-    e++;
-  }
-  return e;
-}
-
 // Continue a run beyond its measured reach: the wavefront tests windows of
 // 64 / (TH * TW) tiles from tile t on (lane = pixel); returns how many more
 // tiles join.
@@ -508,38 +493,69 @@ __device__ int extend_beyond(const StripSmem<TH, TW> &sm, const EncParams &p, co
 }
 
 // Runs of one pass.  Every tile that may start a run (start(tc)) measures
-// its reach in parallel and notes the start that would follow its run; one
-// wavefront then walks the actual starts in order (a run starts at the
-// first start tile at or after the previous run's end) and continues runs
-// that reached kReach.  Then every covered tile takes its mask: its own for
-// a run's first tile, else the pixels the run plane reproduces.  Writes
-// rs/rl, runof (run index, -1 outside runs, for tiles with member(tc)) and
-// fmask; returns the number of runs.
+// its reach -- level by level over a compacted list of the starts still
+// extending, so no thread idles on a neighbour's longer run -- and notes
+// the start that would follow its run.  One wavefront then walks the actual
+// starts in order (a run starts at the first start tile at or after the
+// previous run's end), reading each start's note from a register window of
+// 64 tiles, and continues runs that reached kReach.  Then every covered
+// tile takes its mask: its own for a run's first tile, else the pixels the
+// run plane reproduces.  Writes rs/rl, runof (run index, -1 outside runs,
+// for tiles with member(tc)) and fmask; returns the number of runs.
 template <int TH, int TW, class Member, class Start, class Allowed, class PlaneOf, class MaskOf>
 __device__ int grow_runs(StripSmem<TH, TW> &sm, const EncParams &p, int TC, Member member, Start start,
                          Allowed allowed, PlaneOf plane_of, MaskOf own_mask, int *nr_out) {
   const int tid = threadIdx.x, nw = (TC + 63) >> 6;
   for (int w = tid >> 6; w < nw; w += kBlock / 64) {
     const int tc = w * 64 + (tid & 63);
-    const uint64_t b = __ballot(tc < TC && start(tc));
+    const bool st = tc < TC && start(tc);
+    const uint64_t b = __ballot(st);
     if ((tid & 63) == 0) sm.acc[w] = b;
+    if (st) {
+      sm.reach[tc] = 0;
+      list_push<TH, TW>(sm, 0, TC, tc);
+    }
   }
   for (int tc = tid; tc < TC; tc += kBlock)
     if (member(tc)) sm.runof[tc] = -1;
   __syncthreads();
-  for (int tc = tid; tc < TC; tc += kBlock) {
-    if (!start(tc)) continue;
-    const int e = reach_of<TH, TW>(sm, p, plane_of(tc), tc, TC, allowed);
-    sm.reach[tc] = (uint8_t)e;
-    sm.nx[tc] = (int16_t)next_start(sm.acc, tc + 1 + e, TC);
+  // reach, level by level
+  int n = sm.misc[M_LIST];
+  for (int d = 1; d <= kReach && n > 0; d++) {
+    const int q = (d - 1) & 1;
+    const int16_t *L = sm.list(q, TC);
+    for (int e = tid; e < n; e += kBlock) {
+      const int s = L[e], t = s + d;
+      if (t >= TC || !allowed(s, t)) continue;
+      if (__popcll(inliers_at<TH, TW>(sm, t, plane_of(s), p.eps)) < need_of(p, sm.nv[t])) continue;
+      sm.reach[s] = (uint8_t)d;
+      if (d < kReach) list_push<TH, TW>(sm, q ^ 1, TC, s);
+    }
+    __syncthreads();
+    n = sm.misc[M_LIST + (q ^ 1)];
+    if (tid == 0) sm.misc[M_LIST + q] = 0;    // every thread read its count before the pass
+    __syncthreads();
   }
+  if (tid == 0) {
+    sm.misc[M_LIST] = 0;
+    sm.misc[M_LIST + 1] = 0;
+  }
+  for (int tc = tid; tc < TC; tc += kBlock)
+    if (start(tc)) sm.nx[tc] = (int16_t)next_start(sm.acc, tc + 1 + sm.reach[tc], TC);
   __syncthreads();
   if (tid < 64) {
     const int lane = tid;
-    int nr = 0, s = next_start(sm.acc, 0, TC);
+    int nr = 0, s = next_start(sm.acc, 0, TC), win = -1;
+    uint32_t note = 0;      // this lane's tile of the current window: reach | (nx & 0xffff) << 8
     while (s >= 0) {
-      int len = 1 + sm.reach[s];
-      int nxt = sm.nx[s];
+      if ((s >> 6) != win) {
+        win = s >> 6;
+        const int tc = win * 64 + lane;
+        note = tc < TC ? (uint32_t)sm.reach[tc] | ((uint32_t)(uint16_t)sm.nx[tc] << 8) : 0u;
+      }
+      const uint32_t x = __builtin_amdgcn_readlane(note, s & 63);
+      int len = 1 + (int)(x & 255u);
+      int nxt = (int)(int16_t)(x >> 8);
       if (len == 1 + kReach && s + len < TC) {
         len += extend_beyond<TH, TW>(sm, p, plane_of(s), s, s + len, TC, allowed);
         nxt = next_start(sm.acc, s + len, TC);

@@ -50,9 +50,10 @@ __device__ __forceinline__ int row_of(const SensorDev &s, float q) {
   int v = (int)fmaf(s.elev0 - e, s.inv_de, 0.5f);
   v = min(max(v, 0), H - 1);
   for (int step = 0; step <= H; step++) {
-    if (gload(s.cut + v) <= q) { v--; continue; }
-    if (gload(s.cut + v + 1) > q) { v++; continue; }
-    return v;
+    const float above = gload(s.cut + v), below = gload(s.cut + v + 1);
+    if (above <= q) v--;
+    else if (below > q) v++;
+    else return v;
   }
   return -1;
 }
@@ -67,15 +68,19 @@ __device__ __forceinline__ float edge_side(const SensorDev &s, int u, float x, f
 // error below a bin; it is bounded by W steps in any case).
 __device__ __forceinline__ int column_of(const SensorDev &s, float x, float y) {
   const int W = s.W;
-  const float rel = s.beta0 - atan2_as(y, x);
+  const float rel = s.beta0 - atan2_as(y, x);      // within (-2 pi, 2 pi]
   int u = (int)floorf(rel * s.inv_dth);
-  u %= W;
-  if (u < 0) u += W;
+  u = u < 0 ? u + W : u;
+  u = u < 0 ? u + W : u;
+  u = u >= W ? u - W : u;
+  u = u >= W ? u - W : u;
+  u = min(max(u, 0), W - 1);
   for (int step = 0; step <= W + 2; step++) {
-    if (edge_side(s, u, x, y) > 0.0f) { u = (u == 0) ? W - 1 : u - 1; continue; }
-    int un = (u + 1 == W) ? 0 : u + 1;
-    if (edge_side(s, un, x, y) <= 0.0f) { u = un; continue; }
-    return u;
+    const int un = (u + 1 == W) ? 0 : u + 1;
+    const float lead = edge_side(s, u, x, y), next = edge_side(s, un, x, y);
+    if (lead > 0.0f) u = (u == 0) ? W - 1 : u - 1;
+    else if (next <= 0.0f) u = un;
+    else return u;
   }
   return -1;
 }

@@ -81,7 +81,7 @@ class _Frame(C.Structure):
                 + [(n, C.c_void_p) for n, _, _ in _PRUN]
                 + [("occ", C.c_void_p), ("n_res", C.c_int64), ("codes", C.c_void_p), ("hist", C.c_void_p),
                    ("stream_bytes", C.c_uint64 * 4), ("coded_bits", C.c_uint64 * 4),
-                   ("size_bytes", C.c_uint64), ("range_error", C.c_int32)])
+                   ("size_bytes", C.c_uint64), ("range_error", C.c_int32), ("seeded", C.c_void_p)])
 
 
 @dataclass
@@ -163,6 +163,7 @@ class Frame:
         self.arrays["occ"] = np.zeros((H * W + 7) // 8, np.uint8)
         self.arrays["codes"] = np.zeros(H * W, np.uint16)
         self.arrays["hist"] = np.zeros(4 * 256, np.uint32)
+        self.arrays["seeded"] = np.zeros(T, np.int8)
         kw = {n: _p(a).value for n, a in self.arrays.items()}
         self.c = _Frame(TR=self.TR, TC=self.TC, **kw)
 
@@ -206,11 +207,16 @@ class Frame:
         return int(self.c.range_error)
 
 
-def encode_key(range_img: np.ndarray, tables: Tables, prm: Params) -> Frame:
+def encode_key(range_img: np.ndarray, tables: Tables, prm: Params, seed: np.ndarray | None = None) -> Frame:
+    """Key-frame encoding; ``seed`` (T x 4 FP32: normal, planarity logit) turns
+    on the seeded fit with fallback."""
     r = np.ascontiguousarray(range_img, dtype=np.float32)
     f = Frame(tables.H, tables.W, prm)
     pc = prm.c()
-    lib().orc_encode_key(_p(r), C.byref(tables.s), C.byref(pc), C.byref(f.c))
+    sd = None if seed is None else np.ascontiguousarray(seed, dtype=np.float32).reshape(-1, 4)
+    if sd is not None and len(sd) != f.TR * f.TC:
+        raise ValueError("seed must have one row per tile")
+    lib().orc_encode_key(_p(r), C.byref(tables.s), C.byref(pc), _p(sd), C.byref(f.c))
     return f
 
 

@@ -315,6 +315,47 @@ static void own_fit(const tile_t *T, const orc_params *prm, int8_t *status, int8
   *status = popcount64(*mask) >= need(prm, T->n) ? ORC_ACCEPTED : ORC_REJECTED;
 }
 
+/* Seeded fit (learned plane seeding): the seed normal's stored form
+ * (FP32 coefficients), its offset as the mean of p_k + a p_k1 + b p_k2 over
+ * the tile's points, the points that plane reproduces, one least-squares
+ * refit on them, and the same acceptance test as the own fit.  Returns 1 when
+ * the seed is accepted (status, plane, mask set), 0 when the tile must fall
+ * back to the plain fit, -1 when the tile has no usable seed. */
+static int seeded_fit(const tile_t *T, const float seed[4], const orc_params *prm, int8_t *status,
+                      int8_t *iters, plane_t *P, uint64_t *mask) {
+  if (!(seed[3] > 0.0f) || T->n < prm->min_pts) return -1;
+  float n[3] = {seed[0], seed[1], seed[2]};
+  if (!isfinite(n[0]) || !isfinite(n[1]) || !isfinite(n[2])) return -1;
+  int k = 0;
+  float m = fabsf(n[0]);
+  if (fabsf(n[1]) > m) { k = 1; m = fabsf(n[1]); }
+  if (fabsf(n[2]) > m) { k = 2; m = fabsf(n[2]); }
+  if (!(m > 0.0f)) return -1;
+  int k1 = (k == 0) ? 1 : 0, k2 = (k == 2) ? 1 : 2;
+  plane_t Q = {k, n[k1] / n[k], n[k2] / n[k], 0.0f};
+  double sum = 0.0;
+  for (int j = 0; j < T->n; j++) sum += T->p[j][k] + (double)Q.a * T->p[j][k1] + (double)Q.b * T->p[j][k2];
+  Q.c = (float)(sum / (double)T->n);
+  uint64_t S1 = inliers_of(Q, T, prm->eps);
+  if (popcount64(S1) < prm->min_pts) return 0;
+  double pts[64 * 3], nrm[3], c, ev[3];
+  int cnt = 0;
+  for (int j = 0; j < T->n; j++)
+    if (S1 >> T->slot[j] & 1) {
+      for (int a = 0; a < 3; a++) pts[3 * cnt + a] = T->p[j][a];
+      cnt++;
+    }
+  if (orc_tls(cnt, pts, nrm, &c, ev)) return 0;
+  plane_t P1 = stored_form(nrm, c);
+  uint64_t S2 = inliers_of(P1, T, prm->eps);
+  if (popcount64(S2) < need(prm, T->n)) return 0;
+  *P = P1;
+  *mask = S2;
+  *iters = 1;
+  *status = ORC_ACCEPTED;
+  return 1;
+}
+
 /* Temporal fit: the key-frame plane's normal is held and only the offset
  * varies (Sec. III-D).  In the stored form the offset is the mean of
  * p_k + a p_k1 + b p_k2 over the points kept. */
@@ -557,7 +598,8 @@ static void reset_frame(orc_frame *f, const orc_sensor *s, const orc_params *prm
 }
 
 /* Spatial-only encoding of a key frame (Sec. III-C). */
-void orc_encode_key(const float *range, const orc_sensor *s, const orc_params *prm, orc_frame *f) {
+void orc_encode_key(const float *range, const orc_sensor *s, const orc_params *prm, const float *seed,
+                    orc_frame *f) {
   reset_frame(f, s, prm);
   int T = f->TR * f->TC;
   tile_t *tiles;
@@ -565,7 +607,11 @@ void orc_encode_key(const float *range, const orc_sensor *s, const orc_params *p
   plane_t *own = (plane_t *)calloc((size_t)T, sizeof(plane_t));
   for (int t = 0; t < T; t++) {
     load_tile(range, s, prm, t / f->TC, t % f->TC, &tiles[t]);
-    own_fit(&tiles[t], prm, &f->own_status[t], &f->own_iters[t], &own[t], &f->own_mask[t]);
+    int sd = -1;
+    if (seed) sd = seeded_fit(&tiles[t], seed + 4 * (size_t)t, prm, &f->own_status[t], &f->own_iters[t], &own[t],
+                              &f->own_mask[t]);
+    if (f->seeded) f->seeded[t] = (int8_t)(sd == 1 ? 1 : (sd == 0 ? 2 : 0));
+    if (sd != 1) own_fit(&tiles[t], prm, &f->own_status[t], &f->own_iters[t], &own[t], &f->own_mask[t]);
     f->own_axis[t] = (int8_t)own[t].k;
     f->own_abc[3 * t] = own[t].a; f->own_abc[3 * t + 1] = own[t].b; f->own_abc[3 * t + 2] = own[t].c;
     if (f->t_status) { f->t_status[t] = 0; f->t_iters[t] = 0; f->t_c[t] = 0; f->t_mask[t] = 0; }
@@ -770,7 +816,7 @@ uint64_t orc_encode_sequences(int nseq, int nf, int key_index, const float *cons
 #pragma omp parallel for schedule(dynamic, 1)
   for (int q = 0; q < nseq; q++) {
     int i = q * nf + key_index;
-    orc_encode_key(ranges + (size_t)i * npx, s, prm, &fb[i].f);
+    orc_encode_key(ranges + (size_t)i * npx, s, prm, NULL, &fb[i].f);
   }
 #pragma omp parallel for schedule(dynamic, 1)
   for (int i = 0; i < nfr; i++) {

@@ -82,6 +82,8 @@ typedef struct {
   uint64_t coded_bits[4];          /* optimal Huffman cost per stream */
   uint64_t size_bytes;             /* frame size: header + coded streams + tables */
   int32_t range_error;             /* set if a residual cannot be coded within eps */
+  /* learned plane seeding (key frames): 0 no seed, 1 seed accepted, 2 seed fell back */
+  int8_t *seeded;                  /* T entries, may be NULL */
 } orc_frame;
 
 void orc_tables(int H, int W, const float *elev, float az0, float *cut, float *ebx, float *eby,
@@ -95,7 +97,11 @@ void orc_project(const float *xyz, int64_t n, const float *M, const orc_sensor *
  * eigenvalues ascending.  Returns 0, or 1 if degenerate. */
 int orc_tls(int n, const double *p, double *normal, double *c, double *evals);
 
-void orc_encode_key(const float *range, const orc_sensor *s, const orc_params *prm, orc_frame *out);
+/* seed (may be NULL): per tile (n_x, n_y, n_z, planarity logit) from the
+ * seed network; a tile with logit > 0 tries one refit from the seed plane
+ * and keeps it when it passes the acceptance test, else runs the plain fit. */
+void orc_encode_key(const float *range, const orc_sensor *s, const orc_params *prm, const float *seed,
+                    orc_frame *out);
 void orc_encode_pred(const orc_frame *key, const float *range, const orc_sensor *s,
                      const orc_params *prm, orc_frame *out);
 

@@ -136,7 +136,9 @@ typedef struct {
   uint64_t mask;            /* own plane's reproduced pixels, bit i*tw+k */
   uint64_t t_mask;          /* temporal fit's reproduced pixels */
   float t_c;                /* temporal offset c' */
-  uint8_t t_iters, seeded, pad[2];
+  uint8_t t_iters;
+  uint8_t seeded;           /* learned seed: 0 none, 1 accepted, 2 fell back to the plain fit */
+  uint8_t pad[2];
 } pc_tile_rec;
 
 /* Section offsets (bytes) of one frame stream buffer.  Sizes:
@@ -229,6 +231,47 @@ pc_status pc_encode_pred(pc_ctx *ctx, const void *key, const float *range, const
  * frame (NULL for a key frame). */
 pc_status pc_decode(pc_ctx *ctx, const void *key, const void *frame, const pc_sensor *sensor,
                     const pc_params *params, float *range_out, void *stream);
+
+/* ---- learned plane seeding -------------------------------------------------
+ * A small convolutional network proposes, per 4x8 tile, a plane normal and a
+ * planarity logit from the key frame's range image; pc_fit_key tries one
+ * refit from each planar seed and falls back to the plain fit when the seed
+ * does not pass the same acceptance test (learned plane seeding of the
+ * Sec. III-C fit).  Network: four 3x3 convolutions, zero padding 1, channels
+ * 4 -> 16 -> 32 -> 32 -> 4, strides (2,2), (2,2), (1,2), (1,1), ReLU after
+ * the first three; input channels (r, x, y, z) / 16 with (x, y, z) = r d at
+ * the FP32 pixel directions; inputs, weights and stored activations bfloat16
+ * (round to nearest even), FP32 accumulation on MFMA.  Parameters: one FP32
+ * vector of PC_NET_PARAMS values, per layer W[out][in][ky][kx] then b[out].
+ * Sensors need H % 4 == 0 and W % 8 == 0 (else PC_ERR_UNSUPPORTED). */
+#define PC_NET_PARAMS 15636
+
+/* Device workspace of one frame's forward pass (kept for its backward pass). */
+size_t pc_net_workspace_size(const pc_sensor *sensor);
+
+/* seed[H/4][W/8][4] (FP32: n_x, n_y, n_z, logit) from range[H][W]; the
+ * workspace keeps the activations for pc_net_backward. */
+pc_status pc_net_forward(pc_ctx *ctx, const float *params, const float *range, const pc_sensor *sensor, void *work,
+                         size_t work_bytes, float *seed, void *stream);
+
+/* Gradient of a loss with respect to the parameters, ADDED to grad[PC_NET_PARAMS],
+ * given dseed = d loss / d seed and the workspace of the matching forward
+ * pass (bfloat16 roundings pass gradients straight through). */
+pc_status pc_net_backward(pc_ctx *ctx, const float *params, const pc_sensor *sensor, void *work, size_t work_bytes,
+                          const float *dseed, float *grad, void *stream);
+
+/* Training loss against labels from a plain key-frame stream `labels`
+ * (pc_fit_key without seed, 4x8 tiles): tiles with a fit attempt are
+ * labelled, planar = accepted, normal = the stored plane's unit normal.
+ * loss[0] (device) = mean over labelled tiles of BCE(logit, planar) +
+ * planar * (1 - |cos(seed normal, label normal)|); dseed = its gradient. */
+pc_status pc_net_loss(pc_ctx *ctx, const float *seed, const void *labels, const pc_sensor *sensor,
+                      const pc_params *params, float *dseed, float *loss, void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8; Kingma & Ba 2015) on
+ * params with moments m, v (PC_NET_PARAMS each); step counts from 1. */
+pc_status pc_net_adam(pc_ctx *ctx, float *params, const float *grad, float *m, float *v, int32_t step, float lr,
+                      void *stream);
 
 /* ---- batched encoding ------------------------------------------------------
  * Many frames of many sensors (and groups of frames with their key frames)

@@ -231,6 +231,7 @@ pc_status pcc_check_all(const pc_sensor *s, const pc_params *p) {
   return st;
 }
 EncParams pcc_enc_params(const pc_params *p) { return enc_params(p); }
+pc_status pcc_check_sensor(const pc_sensor *s) { return check_sensor(s); }
 int pcc_ctx_device(pc_ctx *ctx) { return ctx->device; }
 
 // ------------------------------------------------------------------ the ABI

@@ -293,6 +293,39 @@ __device__ __forceinline__ void list_push(StripSmem<TH, TW> &sm, int q, int TC, 
   sm.list(q, TC)[at] = (int16_t)tc;
 }
 
+// The fits of one iteration for the tiles on list q (n of them, every thread
+// having read n after the last barrier): (a) FP32 fits, the near-degenerate
+// ones gathered on the FP64 list; (b) FP64 fits of those, on_degenerate(tc)
+// for a degenerate scatter.  Planes go to sm.plane.  Ends after a barrier
+// with list q's and the FP64 list's counters cleared.
+template <int TH, int TW, class OnDegenerate>
+__device__ void fit_pass(StripSmem<TH, TW> &sm, int q, int n, int TC, int &fits, int &fp64, OnDegenerate on_degenerate) {
+  const int tid = threadIdx.x;
+  const int16_t *L = sm.list(q, TC);
+  const uint64_t *cur = sm.cur();
+  for (int e = tid; e < n; e += kBlock) {
+    const int tc = L[e];
+    TileRows<TH, TW> T = tile_at<TH, TW>(sm, tc);
+    Plane P{0, 0.f, 0.f, 0.f};
+    fits++;
+    if (fit_plane_f32(T, cur[tc], P)) sm.plane[tc] = pack_plane(P);
+    else list_push<TH, TW>(sm, 2, TC, tc);
+  }
+  __syncthreads();
+  const int nf = sm.misc[M_F64];
+  if (tid == 0) sm.misc[M_LIST + q] = 0;      // every thread has read n before (a)
+  for (int e = tid; e < nf; e += kBlock) {
+    const int tc = sm.list(2, TC)[e];
+    TileRows<TH, TW> T = tile_at<TH, TW>(sm, tc);
+    Plane P{0, 0.f, 0.f, 0.f};
+    fp64++;
+    if (fit_plane_f64(T, cur[tc], P)) sm.plane[tc] = pack_plane(P);
+    else on_degenerate(tc);
+  }
+  __syncthreads();
+  if (tid == 0) sm.misc[M_F64] = 0;            // every thread has read nf before (b)
+}
+
 // Own least-squares fits (Sec. III-C) of the tiles with take(tc): fit,
 // keep the pixels the plane reproduces, refit on them, up to max_iter fits,
 // converged when the kept set stops changing; accepted when at least
@@ -318,30 +351,8 @@ __device__ void own_fits(StripSmem<TH, TW> &sm, const EncParams &p, int TC, Take
   for (int it = 1; it <= p.max_iter && n > 0; it++) {
     const int q = (it - 1) & 1;
     const int16_t *L = sm.list(q, TC);
-    // (a) FP32 fits; near-degenerate ones go to the FP64 list
-    for (int e = tid; e < n; e += kBlock) {
-      const int tc = L[e];
-      TileRows<TH, TW> T = tile_at<TH, TW>(sm, tc);
-      Plane P{0, 0.f, 0.f, 0.f};
-      fits++;
-      if (fit_plane_f32(T, cur[tc], P)) sm.plane[tc] = pack_plane(P);
-      else list_push<TH, TW>(sm, 2, TC, tc);
-    }
-    __syncthreads();
-    // (b) FP64 fits
-    const int nf = sm.misc[M_F64];
-    if (tid == 0) sm.misc[M_LIST + q] = 0;      // every thread has read n before (a)
-    for (int e = tid; e < nf; e += kBlock) {
-      const int tc = sm.list(2, TC)[e];
-      TileRows<TH, TW> T = tile_at<TH, TW>(sm, tc);
-      Plane P{0, 0.f, 0.f, 0.f};
-      fp64++;
-      if (fit_plane_f64(T, cur[tc], P)) sm.plane[tc] = pack_plane(P);
-      else sm.stat[tc] = ST_DEGENERATE;
-    }
-    __syncthreads();
-    if (tid == 0) sm.misc[M_F64] = 0;            // every thread has read nf before (b)
-    // (c) kept pixels, convergence
+    fit_pass<TH, TW>(sm, q, n, TC, fits, fp64, [&](int tc) { sm.stat[tc] = ST_DEGENERATE; });
+    // kept pixels, convergence
     for (int e = tid; e < n; e += kBlock) {
       const int tc = L[e];
       sm.iters[tc] = (uint8_t)it;
@@ -373,6 +384,91 @@ __device__ void own_fits(StripSmem<TH, TW> &sm, const EncParams &p, int TC, Take
     sm.misc[M_LIST] = 0;
     sm.misc[M_LIST + 1] = 0;
   }
+  __syncthreads();
+}
+
+// Offset of a seed plane (normal held) through all of the tile's points:
+// the FP64 mean of p_k + a p_k1 + b p_k2 over the valid pixels with p = r d,
+// in pixel order, rounded once (the kept set of the refit depends on it).
+template <class Tile>
+__device__ __forceinline__ float seed_offset(const Tile &T, const Plane &Q) {
+  const int k1 = Q.k == 0 ? 1 : 0, k2 = Q.k == 2 ? 1 : 2;
+  double sum = 0.0;
+  int n = 0;
+  T.each([&](int, float r, const Dir &d) {
+    const double p[3] = {(double)r * (double)d.x, (double)r * (double)d.y, (double)r * (double)d.z};
+    const double v = p[Q.k] + (double)Q.a * p[k1] + (double)Q.b * p[k2];
+    sum += r > 0.0f ? v : 0.0;
+    n += r > 0.0f;
+  });
+  return (float)(sum / (double)n);
+}
+
+// Seeded fits (learned plane seeding) of a key-frame strip: a tile whose
+// seed logit is positive takes the seed normal's stored form (FP32
+// coefficients), its offset along the tile's points, the points that plane
+// reproduces, one least-squares refit on them, and the own fit's acceptance
+// test.  Accepted tiles get their plane, mask, status ACCEPTED and one
+// iteration; seed state in sm.elig (key frames do not use it otherwise):
+// 0 no seed, 1 accepted, 2 fell back to the plain fit.
+template <int TH, int TW>
+__device__ void seeded_fits(StripSmem<TH, TW> &sm, const EncParams &p, int TC, const float4 *__restrict__ seed,
+                            int &fits, int &fp64) {
+  const int tid = threadIdx.x;
+  uint64_t *cur = sm.cur();
+  for (int tc = tid; tc < TC; tc += kBlock) {
+    uint8_t state = 0;
+    const float4 s4 = seed[tc];
+    if (s4.w > 0.0f && sm.nv[tc] >= p.min_pts && isfinite(s4.x) && isfinite(s4.y) && isfinite(s4.z)) {
+      const float n[3] = {s4.x, s4.y, s4.z};
+      int k = 0;
+      float m = fabsf(n[0]);
+      if (fabsf(n[1]) > m) { k = 1; m = fabsf(n[1]); }
+      if (fabsf(n[2]) > m) { k = 2; m = fabsf(n[2]); }
+      if (m > 0.0f) {
+        const int k1 = k == 0 ? 1 : 0, k2 = k == 2 ? 1 : 2;
+        Plane Q{k, n[k1] / n[k], n[k2] / n[k], 0.0f};
+        TileRows<TH, TW> T = tile_at<TH, TW>(sm, tc);
+        Q.c = seed_offset(T, Q);
+        const uint64_t S1 = inliers(T, Q, p.eps);
+        state = 2;
+        if (__popcll(S1) >= p.min_pts) {
+          cur[tc] = S1;
+          list_push<TH, TW>(sm, 0, TC, tc);
+          state = 3;
+        }
+      }
+    }
+    sm.elig[tc] = state;
+  }
+  __syncthreads();
+  const int n = sm.misc[M_LIST];
+  if (n > 0) {
+    fit_pass<TH, TW>(sm, 0, n, TC, fits, fp64, [&](int tc) { sm.elig[tc] = 2; });
+    const int16_t *L = sm.list(0, TC);
+    for (int e = tid; e < n; e += kBlock) {
+      const int tc = L[e];
+      if (sm.elig[tc] == 2) continue;
+      TileRows<TH, TW> T = tile_at<TH, TW>(sm, tc);
+      const uint64_t S2 = inliers(T, unpack_plane(sm.plane[tc]), p.eps);
+      if (__popcll(S2) >= need_of(p, sm.nv[tc])) {
+        sm.omask[tc] = S2;
+        sm.stat[tc] = ST_ACCEPTED;
+        sm.iters[tc] = 1;
+        sm.elig[tc] = 1;
+      } else {
+        sm.elig[tc] = 2;
+      }
+    }
+  }
+  __syncthreads();
+  int ns = 0, nb = 0;
+  for (int tc = tid; tc < TC; tc += kBlock) {
+    ns += sm.elig[tc] == 1;
+    nb += sm.elig[tc] == 2;
+  }
+  if (ns) atomicAdd(&sm.misc[M_SEEDED], ns);
+  if (nb) atomicAdd(&sm.misc[M_FALLBACK], nb);
   __syncthreads();
 }
 
@@ -834,13 +930,20 @@ __device__ void key_strip(char *smem_raw, const StripSrc &src, const SensorDev &
   count_valid<TH, TW>(sm, TC);
   __syncthreads();
   int fits = 0, fp64 = 0;
-  own_fits<TH, TW>(sm, p, TC, [](int) { return true; }, fits, fp64);
+  if (seed) {
+    seeded_fits<TH, TW>(sm, p, TC, reinterpret_cast<const float4 *>(seed) + (int64_t)tr * TC, fits, fp64);
+    own_fits<TH, TW>(sm, p, TC, [&](int tc) { return sm.elig[tc] != 1; }, fits, fp64);
+  } else {
+    for (int tc = threadIdx.x; tc < TC; tc += kBlock) sm.elig[tc] = 0;
+    own_fits<TH, TW>(sm, p, TC, [](int) { return true; }, fits, fp64);
+  }
   for (int tc = threadIdx.x; tc < TC; tc += kBlock) {
     Plane P = unpack_plane(sm.plane[tc]);
     pc_tile_rec rec;
     rec.a = P.a; rec.b = P.b; rec.c = P.c;
     rec.axis = (uint8_t)P.k; rec.status = sm.stat[tc]; rec.iters = sm.iters[tc]; rec.t_status = 0;
-    rec.mask = sm.omask[tc]; rec.t_mask = 0; rec.t_c = 0.f; rec.t_iters = 0; rec.seeded = 0; rec.pad[0] = rec.pad[1] = 0;
+    rec.mask = sm.omask[tc]; rec.t_mask = 0; rec.t_c = 0.f; rec.t_iters = 0; rec.seeded = sm.elig[tc];
+    rec.pad[0] = rec.pad[1] = 0;
     f.tiles[tr * TC + tc] = rec;
   }
   grow_spatial<TH, TW>(sm, p, f, tr, false);

@@ -85,9 +85,11 @@ def lib():
         L.pc_workspace_size.restype = C.c_size_t
         for name in ("pc_stream_layout", "pc_ctx_create", "pc_ctx_destroy", "pc_sensor_register", "pc_sensor_tables",
                      "pc_project", "pc_fit_key", "pc_encode_pred", "pc_decode", "pc_check", "pc_batch_create",
-                     "pc_batch_run", "pc_batch_info", "pc_batch_profile", "pc_batch_destroy"):
+                     "pc_batch_run", "pc_batch_info", "pc_batch_profile", "pc_batch_destroy", "pc_net_forward",
+                     "pc_net_backward", "pc_net_loss", "pc_net_adam"):
             getattr(L, name).restype = C.c_int
         L.pc_batch_workspace_size.restype = C.c_size_t
+        L.pc_net_workspace_size.restype = C.c_size_t
         _lib = L
     return _lib
 
@@ -95,7 +97,9 @@ def lib():
 EXPORTED = ("pc_stream_layout", "pc_workspace_size", "pc_ctx_create", "pc_ctx_destroy", "pc_sensor_register",
             "pc_sensor_tables", "pc_project", "pc_fit_key", "pc_encode_pred", "pc_decode", "pc_check",
             "pc_last_error", "pc_version", "pc_batch_workspace_size", "pc_batch_create", "pc_batch_run",
-            "pc_batch_info", "pc_batch_profile", "pc_batch_destroy")
+            "pc_batch_info", "pc_batch_profile", "pc_batch_destroy", "pc_net_workspace_size", "pc_net_forward",
+            "pc_net_backward", "pc_net_loss", "pc_net_adam")
+PC_NET_PARAMS = 15636
 LAUNCH_KINDS = {0: "reset", 1: "count", 2: "offsets", 3: "scatter", 4: "key", 5: "pred", 6: "finish"}
 
 
@@ -188,6 +192,31 @@ def pc_project(ctx, xyz, n: int, M_host, sensor: Sensor, range_out, src_idx=None
 def pc_fit_key(ctx, range_img, sensor: Sensor, prm: pc_params, seed, out, stream=None):
     _check(lib().pc_fit_key(ctx, _ptr(range_img), C.byref(sensor.c), C.byref(prm), _ptr(seed), _ptr(out),
                             _stream(stream)))
+
+
+def pc_net_workspace_size(sensor: Sensor) -> int:
+    return int(lib().pc_net_workspace_size(C.byref(sensor.c)))
+
+
+def pc_net_forward(ctx, params, range_img, sensor: Sensor, work, seed, stream=None):
+    _check(lib().pc_net_forward(ctx, _ptr(params), _ptr(range_img), C.byref(sensor.c), _ptr(work),
+                                C.c_size_t(work.numel() * work.element_size()), _ptr(seed), _stream(stream)))
+
+
+def pc_net_backward(ctx, params, sensor: Sensor, work, dseed, grad, stream=None):
+    _check(lib().pc_net_backward(ctx, _ptr(params), C.byref(sensor.c), _ptr(work),
+                                 C.c_size_t(work.numel() * work.element_size()), _ptr(dseed), _ptr(grad),
+                                 _stream(stream)))
+
+
+def pc_net_loss(ctx, seed, labels, sensor: Sensor, prm: pc_params, dseed, loss, stream=None):
+    _check(lib().pc_net_loss(ctx, _ptr(seed), _ptr(labels), C.byref(sensor.c), C.byref(prm), _ptr(dseed), _ptr(loss),
+                             _stream(stream)))
+
+
+def pc_net_adam(ctx, params, grad, m, v, step: int, lr: float, stream=None):
+    _check(lib().pc_net_adam(ctx, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), C.c_int32(step), C.c_float(lr),
+                             _stream(stream)))
 
 
 def pc_encode_pred(ctx, key, range_img, M_host, sensor: Sensor, prm: pc_params, out, stream=None):

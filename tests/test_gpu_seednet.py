@@ -1,0 +1,189 @@
+"""GPU parity of the plane-seed network and the seeded key-frame fit against
+the oracle: forward seeds and parameter gradients within cosine >= 0.999 and
+relative L2 error <= 2e-2 per tensor (bfloat16 inputs and weights, FP32
+accumulation against FP64), the loss and its gradient, one Adam step, and the
+seeded fit with fallback on a 64x2048 frame."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2008_06972_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2008_06972_amd import pcc  # noqa: E402
+import oracle  # noqa: E402
+from oracle import seednet as sn  # noqa: E402
+from gpu_common import compare_frame, residual_codes_agree  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _agree(g, o):
+    g = np.asarray(g, np.float64).ravel()
+    o = np.asarray(o, np.float64).ravel()
+    cos = float(g @ o / (np.linalg.norm(g) * np.linalg.norm(o) + 1e-300))
+    rel = float(np.linalg.norm(g - o) / (np.linalg.norm(o) + 1e-300))
+    return cos, rel
+
+
+@pytest.fixture(scope="module")
+def frame():
+    s = synth.SENSORS["c2"]
+    S = pcc.Sensor.of(s)
+    ctx = pcc.Context([S])
+    pts, _, _ = synth.make_frame(s, "c2", 2100)
+    xyz = torch.from_numpy(pts).to(DEV)
+    rng = torch.empty(s.H, s.W, dtype=torch.float32, device=DEV)
+    pcc.pc_project(ctx.h, xyz, len(pts), None, S, rng)
+    torch.cuda.synchronize()
+    tb = oracle.Tables.of(s)
+    yield dict(s=s, S=S, ctx=ctx, rng=rng, tb=tb, rng_np=rng.cpu().numpy())
+    ctx.close()
+
+
+def _params(seed):
+    p = sn.init_params(seed)
+    rng = np.random.default_rng(seed + 1)
+    p[-84:] = rng.normal(0, 0.05, 84).astype(np.float32)      # nonzero biases
+    return p
+
+
+def _gpu_forward(fr, p):
+    S = fr["S"]
+    work = torch.zeros(pcc.pc_net_workspace_size(S), dtype=torch.uint8, device=DEV)
+    seed = torch.zeros(S.H // 4, S.W // 8, 4, dtype=torch.float32, device=DEV)
+    pt = torch.from_numpy(p).to(DEV)
+    pcc.pc_net_forward(fr["ctx"].h, pt, fr["rng"], S, work, seed)
+    torch.cuda.synchronize()
+    return pt, work, seed
+
+
+def test_net_forward_matches_oracle(frame):
+    p = _params(11)
+    pt, work, seed = _gpu_forward(frame, p)
+    x0 = sn.net_input(frame["rng_np"], frame["tb"].directions())
+    ref, _ = sn.forward(p, x0)
+    g = seed.cpu().numpy().transpose(2, 0, 1)
+    cos, rel = _agree(g, ref)
+    say("forward cos", cos, "rel", rel)
+    assert g.shape == ref.shape
+    assert cos >= 0.999 and rel <= 2e-2
+    for c in range(4):
+        cc, rc = _agree(g[c], ref[c])
+        assert cc >= 0.999 and rc <= 2e-2, (c, cc, rc)
+
+
+def test_net_backward_matches_oracle(frame):
+    p = _params(12)
+    pt, work, seed = _gpu_forward(frame, p)
+    rng = np.random.default_rng(3)
+    dseed = rng.normal(0, 1e-3, seed.shape).astype(np.float32)
+    grad = torch.zeros(pcc.PC_NET_PARAMS, dtype=torch.float32, device=DEV)
+    pcc.pc_net_backward(frame["ctx"].h, pt, frame["S"], work, torch.from_numpy(dseed).to(DEV), grad)
+    torch.cuda.synchronize()
+    x0 = sn.net_input(frame["rng_np"], frame["tb"].directions())
+    _, cache = sn.forward(p, x0)
+    ref = sn.backward(p, cache, dseed.transpose(2, 0, 1))
+    g = grad.cpu().numpy()
+    at = 0
+    for li, (i, o, _) in enumerate(sn.LAYERS):
+        for name, n in (("W", o * i * 9), ("b", o)):
+            cos, rel = _agree(g[at:at + n], ref[at:at + n])
+            say("layer", li + 1, name, "cos", cos, "rel", rel)
+            assert cos >= 0.999 and rel <= 2e-2, (li, name, cos, rel)
+            at += n
+
+
+def test_net_loss_and_adam_match_oracle(frame):
+    S, s = frame["S"], frame["s"]
+    prm = pcc.params(eps=0.02, tile_h=4, tile_w=8)
+    labels = pcc.FrameStream(S, prm, DEV)
+    pcc.pc_fit_key(frame["ctx"].h, frame["rng"], S, prm, None, labels)
+    p = _params(13)
+    pt, work, seed = _gpu_forward(frame, p)
+    dseed = torch.zeros_like(seed)
+    loss = torch.zeros(1, dtype=torch.float32, device=DEV)
+    pcc.pc_net_loss(frame["ctx"].h, seed, labels, S, prm, dseed, loss)
+    torch.cuda.synchronize()
+    tiles = labels.host()["tiles"].reshape(s.H // 4, s.W // 8)
+    planar, nrm, valid = sn.labels_from_tiles(tiles["status"], tiles["axis"],
+                                              np.stack([tiles["a"], tiles["b"], tiles["c"]], -1))
+    sg = seed.cpu().numpy().transpose(2, 0, 1).astype(np.float64)
+    L, dref = sn.loss(sg, planar, nrm, valid)
+    say("loss gpu", float(loss.item()), "oracle", L)
+    assert abs(float(loss.item()) - L) <= 1e-4 * max(1.0, abs(L))
+    cos, rel = _agree(dseed.cpu().numpy().transpose(2, 0, 1), dref)
+    assert cos >= 0.99999 and rel <= 1e-4, (cos, rel)
+    # one Adam step
+    grad = np.random.default_rng(4).normal(0, 1e-2, pcc.PC_NET_PARAMS).astype(np.float32)
+    m = np.random.default_rng(5).normal(0, 1e-3, pcc.PC_NET_PARAMS).astype(np.float32)
+    v = np.abs(np.random.default_rng(6).normal(0, 1e-4, pcc.PC_NET_PARAMS)).astype(np.float32)
+    pw, mw, vw = (torch.from_numpy(a.copy()).to(DEV) for a in (p, m, v))
+    pcc.pc_net_adam(frame["ctx"].h, pw, torch.from_numpy(grad).to(DEV), mw, vw, 3, 1e-3)
+    torch.cuda.synchronize()
+    pr, mr, vr = sn.adam(p.astype(np.float64), grad.astype(np.float64), m.astype(np.float64), v.astype(np.float64),
+                         3, 1e-3)
+    # FP32 step against FP64: beta2 = 0.999 rounded to FP32 alone moves
+    # (1 - beta2) by 5e-5 relative
+    assert np.allclose(pw.cpu().numpy(), pr, rtol=1e-5, atol=1e-7)
+    assert np.allclose(mw.cpu().numpy(), mr, rtol=1e-5, atol=1e-9)
+    assert np.allclose(vw.cpu().numpy(), vr, rtol=2e-4, atol=1e-12)
+
+
+def test_seeded_key_fit_matches_oracle(frame):
+    """Seeds = the plain fit's own normals (perturbed) with positive logits on
+    accepted tiles and a few deliberately wrong seeds: the GPU and the oracle
+    take the same seeded / fallback decisions and agree like plain key frames."""
+    S, s, tb = frame["S"], frame["s"], frame["tb"]
+    prm = pcc.params(eps=0.02, tile_h=4, tile_w=8)
+    oprm = oracle.Params(eps=0.02, th=4, tw=8)
+    plain = oracle.encode_key(frame["rng_np"], tb, oprm)
+    T = len(plain.cls)
+    rng = np.random.default_rng(7)
+    seed = np.zeros((T, 4), np.float32)
+    for t in range(T):
+        if plain.own_status[t] != oracle.ACCEPTED:
+            continue
+        k = int(plain.own_axis[t])
+        n = np.zeros(3)
+        k1, k2 = (1, 2) if k == 0 else ((0, 2) if k == 1 else (0, 1))
+        n[k], n[k1], n[k2] = 1.0, plain.own_abc[t][0], plain.own_abc[t][1]
+        n = n / np.linalg.norm(n) + rng.normal(0, 2e-4, 3)
+        if rng.random() < 0.05:
+            n = rng.normal(size=3)                  # a wrong seed
+        seed[t, :3] = n
+        seed[t, 3] = 2.0
+    o = oracle.encode_key(frame["rng_np"], tb, oprm, seed)
+    fs = pcc.FrameStream(S, prm, DEV)
+    pcc.pc_fit_key(frame["ctx"].h, frame["rng"], S, prm, torch.from_numpy(seed).to(DEV), fs)
+    dec = torch.empty_like(frame["rng"])
+    pcc.pc_decode(frame["ctx"].h, None, fs, S, prm, dec)
+    torch.cuda.synchronize()
+    g = fs.host()
+    st = compare_frame(oracle, g, o, frame["rng_np"])
+    ok, nboth, ndiff = residual_codes_agree(g, o, frame["rng_np"], 4, 8)
+    gs = g["tiles"]["seeded"]
+    st.update(seeded_agree=float(np.mean(gs == o.seeded)), gpu_seeded=int((gs == 1).sum()),
+              orc_seeded=int((o.seeded == 1).sum()), gpu_fallback=int((gs == 2).sum()),
+              orc_fallback=int((o.seeded == 2).sum()), info_seeded=g["info"].seeded, info_fallback=g["info"].fallback)
+    say(st)
+    v = frame["rng_np"] > 0
+    err = np.abs(dec.cpu().numpy().astype(np.float64) - frame["rng_np"].astype(np.float64))
+    assert err[v].max() <= 0.02
+    assert ok
+    assert st["gpu_seeded"] > 0.5 * (seed[:, 3] > 0).sum()
+    assert st["seeded_agree"] >= 0.99 and st["cls_agree"] >= 0.97, st
+    assert st["info_seeded"] == st["gpu_seeded"] and st["info_fallback"] == st["gpu_fallback"]
+    assert st["size_rel"] <= 0.005
+    assert st["worst_normal_rad"] <= 1e-4 and st["worst_offset_rel"] <= 1e-4, st

@@ -13,7 +13,10 @@ every frame, key-frame spatial encoding, predicted-frame temporal encoding,
 residual quantisation, stream histograms and Huffman sizes.
 
 Forms: "plain" launches the per-frame C-ABI calls frame by frame;
-"batched" replays one HIP graph of persistent kernels over all frames.
+"batched" replays one HIP graph of persistent kernels over all frames;
+"learned" is the batched graph with the plane-seed network seeding the key
+frames' fits (the headline when its weights are present).  The ablation
+batched vs learned isolates the network's effect from batching's.
 Prints one JSON line (rank 0).
 """
 from __future__ import annotations
@@ -81,7 +84,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seqs", type=int, default=96)
-    ap.add_argument("--forms", default="plain,batched")
+    ap.add_argument("--forms", default="plain,batched,learned")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2008_06972_amd", "weights", "seednet_c2.f32"),
+                    help="seed-network parameters for the learned form")
     ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--cpu-seqs", type=int, default=96, help="oracle sample (sequences)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -146,15 +151,16 @@ def main():
     forms = {}
     sizes = {}
 
-    # ------------------------------------------------------------ batched
-    outs_b = [pcc.FrameStream(S, prm, dev) for _ in range(nfr)]
-    batch = None
-    if "batched" in a.forms:
+    # ------------------------------------------------- batched / learned
+    batches = {}
+
+    def run_batched(name, net):
+        outs = [pcc.FrameStream(S, prm, dev) for _ in range(nfr)]
         fr = [dict(xyz=xyz[i], M=None if i == key_of(i) else transforms[i], sensor=S, params=prm, key=key_of(i),
-                   out=outs_b[i]) for i in range(nfr)]
-        batch = pcc.Batch(ctx, fr, persistent=True, graph=True)
+                   out=outs[i]) for i in range(nfr)]
+        batch = pcc.Batch(ctx, fr, persistent=True, graph=True, net=net)
         nitems, ngroups, grid = batch.info()
-        log(f"batch: {nitems} strip items, {ngroups} groups, persistent grid {grid}")
+        log(f"{name}: {nitems} strip items, {ngroups} groups, persistent grid {grid}")
         for _ in range(a.warmup):
             batch.run()
         torch.cuda.synchronize()
@@ -165,10 +171,27 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / a.steps
-        forms["batched"] = {"ms_per_step": ms, "frames_per_s": nfr / (ms / 1e3)}
-        infos = [o.info() for o in outs_b]
-        sizes["batched"] = np.array([i.size_bytes for i in infos], np.int64)
-        log(f"batched: {ms:.3f} ms/step, {nfr / (ms / 1e3):.0f} frames/s")
+        infos = [o.info() for o in outs]
+        key_infos = [infos[i] for i in range(nfr) if i == key_of(i)]
+        tiles = sum(sum(i.tiles) for i in infos)
+        st = {"ms_per_step": ms, "frames_per_s": nfr / (ms / 1e3),
+              "fits_per_tile": sum(i.fits for i in infos) / max(1, tiles),
+              "key_fits_per_tile": sum(i.fits for i in key_infos) / max(1, sum(sum(i.tiles) for i in key_infos)),
+              "seeded_tiles": int(sum(i.seeded for i in infos)), "fallback_tiles": int(sum(i.fallback for i in infos))}
+        st["fallback_rate"] = st["fallback_tiles"] / max(1, st["seeded_tiles"] + st["fallback_tiles"])
+        forms[name] = st
+        sizes[name] = np.array([i.size_bytes for i in infos], np.int64)
+        batch.outs = outs
+        batches[name] = batch
+        log(f"{name}: {ms:.3f} ms/step, {nfr / (ms / 1e3):.0f} frames/s")
+
+    if "batched" in a.forms:
+        run_batched("batched", None)
+    net = None
+    if "learned" in a.forms and os.path.exists(a.weights):
+        net = torch.from_numpy(np.fromfile(a.weights, dtype="<f4")).to(dev)
+        assert net.numel() == pcc.PC_NET_PARAMS, a.weights
+        run_batched("learned", net)
 
     # -------------------------------------------------------------- plain
     if "plain" in a.forms:
@@ -209,7 +232,17 @@ def main():
         forms[name]["compression_ratio"] = 12.0 * finite_pts / tot
         forms[name]["bytes"] = tot
     result["forms"] = forms
-    head = "batched" if "batched" in forms else "plain"
+    head = "learned" if "learned" in forms else ("batched" if "batched" in forms else "plain")
+    if "learned" in forms and "plain" in forms:
+        result["learned_over_plain_ratio"] = forms["learned"]["compression_ratio"] / forms["plain"]["compression_ratio"]
+    if "learned" in forms and "batched" in forms:
+        result["ablation"] = {
+            "batched_plain_fps": forms["batched"]["frames_per_s"], "batched_learned_fps": forms["learned"]["frames_per_s"],
+            "batched_plain_ratio": forms["batched"]["compression_ratio"],
+            "batched_learned_ratio": forms["learned"]["compression_ratio"],
+            "key_fits_per_tile_plain": forms["batched"]["key_fits_per_tile"],
+            "key_fits_per_tile_learned": forms["learned"]["key_fits_per_tile"],
+            "fallback_rate": forms["learned"]["fallback_rate"]}
     result["form"] = head
     result["value"] = forms[head]["frames_per_s"]
     result["ms_per_step"] = forms[head]["ms_per_step"]
@@ -217,6 +250,7 @@ def main():
     result["compression_ratio_16B_per_point"] = forms[head]["compression_ratio"] * 16.0 / 12.0
 
     # ------------------------------------------------------------ roofline
+    batch = batches.get(head)
     if batch is not None:
         # per-launch durations: HIP events between the launches of the same
         # launch sequence, on the same stream, averaged over --steps passes
@@ -225,7 +259,7 @@ def main():
             prof += batch.profile(stream.cuda_stream)
         prof = [(k, t / a.steps) for k, t in prof]
         log("per-launch ms:", prof)
-        infos = [o.info() for o in outs_b]
+        infos = [o.info() for o in batch.outs]
         n_res_k = sum(i.n_res for j, i in enumerate(infos) if j == key_of(j))
         n_res_p = sum(i.n_res for j, i in enumerate(infos) if j != key_of(j))
         nk = sum(1 for j in range(nfr) if j == key_of(j))
@@ -264,15 +298,15 @@ def main():
         result["cpu_baseline"] = {"value": len(sample) / dt, "unit": "frames/s", "cores": oracle.num_threads(),
                                   "kind": "oracle",
                                   "sample": f"first {nq} sequences ({len(sample)} frames) of the same workload, "
-                                            f"{dt:.1f}s wall",
+                                            f"plain fits (no seed network), {dt:.1f}s wall",
                                   "compression_ratio": 12.0 * ofin / total}
         for name, sz in sizes.items():
             rel = abs(int(sz[: nq * N_FRAMES].sum()) - total) / total
             result["cpu_baseline"][f"size_rel_diff_{name}"] = rel
         log(f"oracle: {len(sample) / dt:.1f} frames/s on {oracle.num_threads()} threads")
     print(json.dumps(result), flush=True)
-    if batch is not None:
-        batch.close()
+    for b in batches.values():
+        b.close()
     ctx.close()
 
 

@@ -300,13 +300,18 @@ typedef struct {
   int32_t persistent;        /* 1: persistent work-groups pull strips from an atomic queue; 0: a work-group per strip */
   int32_t graph;             /* 1: capture the batch in a HIP graph at the first run and replay it afterwards */
   int32_t blocks_per_cu;     /* persistent grid = CUs * this (at most one work-group per item); 0 = 4 */
+  int32_t pad;
+  const float *net;          /* device PC_NET_PARAMS seed-network parameters, or NULL: key frames with 4x8
+                                tiles and no seeds of their own get seeds from this network inside the batch */
 } pc_batch_opts;
 
 typedef struct pc_batch pc_batch;
 
 /* Device workspace a batch plan needs (descriptor table, work items, block
- * tables, counters, and 16 bytes per point for staging and the strip bins). */
-size_t pc_batch_workspace_size(const pc_frame_desc *frames, int32_t nframes);
+ * tables, counters, 16 bytes per point for staging and the strip bins, and
+ * with a seed network about 27 bytes per pixel of each seeded key frame).
+ * opts may be NULL. */
+size_t pc_batch_workspace_size(const pc_frame_desc *frames, int32_t nframes, const pc_batch_opts *opts);
 
 /* Check the frames, build and upload the descriptor table into the
  * workspace.  The workspace, the frames' xyz, range and out buffers must stay
@@ -334,6 +339,8 @@ pc_status pc_batch_info(const pc_batch *batch, int32_t *nitems, int32_t *ngroups
 #define PC_LAUNCH_KEY 4
 #define PC_LAUNCH_PRED 5
 #define PC_LAUNCH_FINISH 6
+#define PC_LAUNCH_KEYIMAGE 7  /* key-frame range images for the seed network */
+#define PC_LAUNCH_NET 8       /* the seed network's forward pass */
 pc_status pc_batch_profile(pc_batch *batch, void *stream, float *ms, int32_t *kinds, int32_t cap, int32_t *count);
 
 pc_status pc_batch_destroy(pc_batch *batch);

@@ -9,6 +9,9 @@
 //   offsets  per frame, exclusive sum of the strip counts
 //   scatter  move the staged points into their strips' buckets, reserving
 //            space once per (work-group, strip)
+//   keyimage (with a seed network) the key frames' range images, built per
+//            strip from the buckets in LDS
+//   net      the seed network's forward pass over those key frames
 //   key      persistent work-groups pull (key frame, strip) items from an
 //            atomic counter; each builds its strip from the bucket with LDS
 //            atomicMin (nearest point wins, Sec. III-D) and encodes it
@@ -28,6 +31,7 @@
 
 #include "encode_strip.h"
 #include "project.h"
+#include "seednet.h"
 
 namespace pcc {
 
@@ -53,6 +57,7 @@ struct FrameDescDev {
   int *bcur;       // [TR] scatter cursors
   float *range_out;
   const float *seed;
+  float *net_range;  // key frame's range image for the seed network, or NULL
   FrameDev f;
 };
 
@@ -202,6 +207,19 @@ __global__ void __launch_bounds__(kBlock) k_batch_pred_grid(const FrameDescDev *
   pred_strip<TH, TW>(smem_raw, d[D.key].f, src_of(D), D.s, D.p, D.f, fi.y);
 }
 
+// Range image of a key frame's strip for the seed network: the strip's
+// bucket resolved in LDS (nearest point wins) and written out.
+template <int TH, int TW>
+__global__ void __launch_bounds__(kBlock) k_batch_keyimage(const FrameDescDev *__restrict__ d,
+                                                           const int2 *__restrict__ items) {
+  extern __shared__ __align__(16) char smem_raw[];
+  const int2 fi = items[blockIdx.x];
+  const FrameDescDev &D = d[fi.x];
+  StripSmem<TH, TW> sm;
+  sm.r = reinterpret_cast<float *>(smem_raw);
+  load_source<TH, TW>(sm, StripSrc{nullptr, D.bucket, D.bcount, D.boff, D.net_range}, D.s, fi.y);
+}
+
 __global__ void __launch_bounds__(256) k_batch_finish(const FrameDescDev *__restrict__ d) {
   const FrameDescDev &D = d[blockIdx.x];
   finish_frame(D.f, D.kind, D.M, D.hasM);
@@ -226,6 +244,16 @@ struct BatchPlan {
   int bin_blocks = 0;
   std::vector<Group> groups;
   int persistent = 1;
+  // seed network (key frames with 4x8 tiles)
+  int nnet = 0;
+  const float *net_params = nullptr;
+  uint16_t *net_wpk = nullptr;
+  int2 *d_net_items = nullptr;
+  int n_net_items = 0;
+  size_t net_smem = 0;
+  NetInputJob *d_net_in = nullptr;
+  ConvJob *d_net_conv = nullptr;
+  int net_px[5] = {0, 0, 0, 0, 0};
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   int use_graph = 0;
@@ -272,6 +300,13 @@ static hipError_t batch_launches(BatchPlan &P, hipStream_t st, Mark mark) {
     hipLaunchKernelGGL(k_batch_scatter, dim3(P.bin_blocks), dim3(kBinBlock), 0, st, P.d_desc, P.d_bin_owner, P.d_bin_first);
     mark(PC_LAUNCH_SCATTER);
   }
+  if (P.nnet) {
+    hipLaunchKernelGGL((k_batch_keyimage<4, 8>), dim3(P.n_net_items), dim3(kBlock), P.net_smem, st, P.d_desc,
+                       P.d_net_items);
+    mark(PC_LAUNCH_KEYIMAGE);
+    net_forward_batch(P.net_params, P.net_wpk, P.d_net_in, P.d_net_conv, P.nnet, P.net_px, st);
+    mark(PC_LAUNCH_NET);
+  }
   for (int pass = 0; pass < 2; pass++) {      // key groups, then predicted groups
     for (int gi = 0; gi < ngroups; gi++) {
       const Group &g = P.groups[gi];
@@ -315,15 +350,31 @@ int pcc_ctx_device(pc_ctx *ctx);
 static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct BatchSizes {
-  size_t desc, items, bins, counters, buckets, total;
-  int nitems, bin_blocks;
+  size_t desc, items, bins, counters, buckets, net, total;
+  int nitems, bin_blocks, nnet, net_items;
   int64_t strips;
 };
 
-static pc_status batch_sizes(const pc_frame_desc *frames, int32_t nframes, BatchSizes &B) {
+// Does frame i get seeds from the batch's network?  Key frames with 4x8
+// tiles, a sensor the network takes, and no seeds of their own.
+static bool net_frame(const pc_frame_desc &F, int i, const pc_batch_opts *o) {
+  return o && o->net && F.key == i && !F.seed && F.params->tile_h == 4 && F.params->tile_w == 8 &&
+         F.sensor->H % 4 == 0 && F.sensor->W % 8 == 0;
+}
+
+// Network workspace of one frame: range image, activations, seeds.
+static size_t net_frame_bytes(int H, int W) {
+  size_t a0, a1, a2, a3;
+  return a256(4 * (size_t)H * W) + net_forward_act_bytes(H, W, &a0, &a1, &a2, &a3) +
+         a256(16 * (size_t)(H / 4) * (W / 8));
+}
+
+static pc_status batch_sizes(const pc_frame_desc *frames, int32_t nframes, const pc_batch_opts *opts,
+                             BatchSizes &B) {
   memset(&B, 0, sizeof B);
   int64_t items = 0, bb = 0, strips = 0;
-  size_t buckets = 0;
+  size_t buckets = 0, net = 0;
+  int nnet = 0, net_items = 0;
   for (int i = 0; i < nframes; i++) {
     const pc_frame_desc &F = frames[i];
     if (!F.sensor || !F.params) return set_error(PC_ERR_ARG, "frame %d: sensor or params is NULL", i);
@@ -333,25 +384,35 @@ static pc_status batch_sizes(const pc_frame_desc *frames, int32_t nframes, Batch
     strips += tr;
     bb += (F.n + kBinChunk - 1) / kBinChunk;
     buckets += 2 * a256(sizeof(uint2) * (size_t)F.n);
+    if (net_frame(F, i, opts)) {
+      nnet++;
+      net_items += tr;
+      net += net_frame_bytes(F.sensor->H, F.sensor->W);
+    }
   }
   if (items > 0x7fffffff || bb > 0x7fffffff) return set_error(PC_ERR_CAPACITY, "batch too large");
+  if (nnet) net += a256(net_packed_bytes()) + a256(sizeof(NetInputJob) * nnet) + a256(sizeof(ConvJob) * 4 * nnet) +
+                   a256(sizeof(int2) * net_items);
   B.nitems = (int)items;
   B.bin_blocks = (int)bb;
   B.strips = strips;
+  B.nnet = nnet;
+  B.net_items = net_items;
   B.desc = a256(sizeof(FrameDescDev) * (size_t)nframes);
   B.items = a256(sizeof(int2) * (size_t)items);
   B.bins = a256(sizeof(int) * ((size_t)bb + (size_t)nframes));
   B.counters = a256(sizeof(int) * (64 + 3 * (size_t)strips));
   B.buckets = buckets;
-  B.total = B.desc + B.items + B.bins + B.counters + B.buckets;
+  B.net = net;
+  B.total = B.desc + B.items + B.bins + B.counters + B.buckets + B.net;
   return PC_OK;
 }
 
 extern "C" {
 
-size_t pc_batch_workspace_size(const pc_frame_desc *frames, int32_t nframes) {
+size_t pc_batch_workspace_size(const pc_frame_desc *frames, int32_t nframes, const pc_batch_opts *opts) {
   BatchSizes B;
-  if (!frames || nframes <= 0 || batch_sizes(frames, nframes, B) != PC_OK) return 0;
+  if (!frames || nframes <= 0 || batch_sizes(frames, nframes, opts, B) != PC_OK) return 0;
   return B.total;
 }
 
@@ -360,17 +421,39 @@ pc_status pc_batch_create(pc_ctx *ctx, const pc_frame_desc *frames, int32_t nfra
   if (!ctx || !out) return set_error(PC_ERR_ARG, "ctx or output is NULL");
   if (!frames || nframes <= 0) return set_error(PC_ERR_ARG, "no frames");
   BatchSizes B;
-  pc_status st = batch_sizes(frames, nframes, B);
+  pc_status st = batch_sizes(frames, nframes, opts, B);
   if (st) return st;
   if (!workspace || ws_bytes < B.total)
     return set_error(PC_ERR_CAPACITY, "batch workspace %zu bytes < %zu needed", ws_bytes, B.total);
-  pc_batch_opts o = opts ? *opts : pc_batch_opts{1, 1, 0};
+  pc_batch_opts o = opts ? *opts : pc_batch_opts{1, 1, 0, 0, nullptr};
   if (o.blocks_per_cu < 0) return set_error(PC_ERR_ARG, "blocks_per_cu must be >= 0");
   char *ws = (char *)workspace;
   int *counters = (int *)(ws + B.desc + B.items + B.bins);
   int *strip_counts = counters + 64;
   char *bucket_ws = ws + B.desc + B.items + B.bins + B.counters;
+  char *net_ws = bucket_ws + B.buckets;
   std::vector<FrameDescDev> desc((size_t)nframes);
+  // seed network: packed weights, job tables, strip items, then per frame
+  // range image, activations and seeds
+  uint16_t *net_wpk = nullptr;
+  NetInputJob *d_net_in = nullptr;
+  ConvJob *d_net_conv = nullptr;
+  int2 *d_net_items = nullptr;
+  std::vector<NetInputJob> net_in;
+  std::vector<ConvJob> net_conv[4];
+  std::vector<int2> net_items;
+  int net_px[5] = {0, 0, 0, 0, 0};
+  int net_maxW = 0;
+  if (B.nnet) {
+    net_wpk = (uint16_t *)net_ws;
+    net_ws += a256(net_packed_bytes());
+    d_net_in = (NetInputJob *)net_ws;
+    net_ws += a256(sizeof(NetInputJob) * B.nnet);
+    d_net_conv = (ConvJob *)net_ws;
+    net_ws += a256(sizeof(ConvJob) * 4 * B.nnet);
+    d_net_items = (int2 *)net_ws;
+    net_ws += a256(sizeof(int2) * B.net_items);
+  }
   int64_t strip_at = 0;
   for (int i = 0; i < nframes; i++) {
     const pc_frame_desc &F = frames[i];
@@ -411,6 +494,32 @@ pc_status pc_batch_create(pc_ctx *ctx, const pc_frame_desc *frames, int32_t nfra
     strip_at += L.TR;
     D.range_out = F.range;
     D.seed = F.seed;
+    if (net_frame(F, i, &o)) {
+      const int H = F.sensor->H, W = F.sensor->W;
+      size_t a0b, a1b, a2b, a3b;
+      net_forward_act_bytes(H, W, &a0b, &a1b, &a2b, &a3b);
+      float *range = (float *)net_ws;
+      net_ws += a256(4 * (size_t)H * W);
+      uint16_t *a0 = (uint16_t *)net_ws, *a1 = (uint16_t *)(net_ws + a0b), *a2 = (uint16_t *)(net_ws + a0b + a1b),
+               *a3 = (uint16_t *)(net_ws + a0b + a1b + a2b);
+      net_ws += a0b + a1b + a2b + a3b;
+      float *seedbuf = (float *)net_ws;
+      net_ws += a256(16 * (size_t)(H / 4) * (W / 8));
+      D.net_range = range;
+      D.seed = seedbuf;
+      net_in.push_back(NetInputJob{range, a0, D.s.ce, D.s.se, D.s.ca, D.s.sa, H, W});
+      net_conv[0].push_back(ConvJob{a0, H, W, a1, H / 2, W / 2});
+      net_conv[1].push_back(ConvJob{a1, H / 2, W / 2, a2, H / 4, W / 4});
+      net_conv[2].push_back(ConvJob{a2, H / 4, W / 4, a3, H / 4, W / 8});
+      net_conv[3].push_back(ConvJob{a3, H / 4, W / 8, seedbuf, H / 4, W / 8});
+      net_px[0] = std::max(net_px[0], H * W);
+      net_px[1] = std::max(net_px[1], (H / 2) * (W / 2));
+      net_px[2] = std::max(net_px[2], (H / 4) * (W / 4));
+      net_px[3] = std::max(net_px[3], (H / 4) * (W / 8));
+      net_px[4] = std::max(net_px[4], (H / 4) * (W / 8));
+      net_maxW = std::max(net_maxW, W);
+      for (int tr = 0; tr < L.TR; tr++) net_items.push_back(make_int2(i, tr));
+    }
   }
   // items grouped by (kind, tile shape); inside a group, frames in order
   pc_batch *b = new pc_batch();
@@ -448,6 +557,31 @@ pc_status pc_batch_create(pc_ctx *ctx, const pc_frame_desc *frames, int32_t nfra
       P.groups.push_back(g);
     }
   if ((int)P.groups.size() > 64) { delete b; return set_error(PC_ERR_CAPACITY, "too many groups"); }
+  if (B.nnet) {
+    P.nnet = B.nnet;
+    P.net_params = o.net;
+    P.net_wpk = net_wpk;
+    P.d_net_items = d_net_items;
+    P.n_net_items = (int)net_items.size();
+    P.net_smem = sizeof(float) * (size_t)(net_maxW / 8) * StripSmem<4, 8>::NP;
+    P.d_net_in = d_net_in;
+    P.d_net_conv = d_net_conv;
+    for (int q = 0; q < 5; q++) P.net_px[q] = net_px[q];
+    if (hipFuncSetAttribute((const void *)k_batch_keyimage<4, 8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)P.net_smem) != hipSuccess) {
+      delete b;
+      return set_error(PC_ERR_DEVICE, "shared memory attribute failed");
+    }
+    std::vector<ConvJob> conv;
+    for (int l = 0; l < 4; l++) conv.insert(conv.end(), net_conv[l].begin(), net_conv[l].end());
+    bool nok = hipMemcpy(d_net_in, net_in.data(), sizeof(NetInputJob) * net_in.size(), hipMemcpyHostToDevice) == hipSuccess &&
+               hipMemcpy(d_net_conv, conv.data(), sizeof(ConvJob) * conv.size(), hipMemcpyHostToDevice) == hipSuccess &&
+               hipMemcpy(d_net_items, net_items.data(), sizeof(int2) * net_items.size(), hipMemcpyHostToDevice) == hipSuccess;
+    if (!nok) {
+      delete b;
+      return set_error(PC_ERR_DEVICE, "network table upload failed");
+    }
+  }
   // block -> frame table of the binning passes
   std::vector<int> bin_owner, bin_first(nframes);
   for (int i = 0; i < nframes; i++) {

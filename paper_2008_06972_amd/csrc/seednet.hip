@@ -17,7 +17,7 @@
 // Backward (training only) runs on the vector ALUs in FP32.
 //
 // Parameters: one FP32 vector, per layer W[out][in][ky][kx] then b[out].
-#include "pc_internal.h"
+#include "seednet.h"
 
 namespace pcc {
 
@@ -74,20 +74,17 @@ __global__ void k_net_pack(const float *__restrict__ params, uint16_t *__restric
   packed[e] = bf16_rne(w);
 }
 
-struct ConvJob {
-  const uint16_t *in;     // NHWC bf16, Hi x Wi x ci
-  int Hi, Wi;
-  void *out;              // NHWC bf16 Ho x Wo x co, or FP32 [Ho][Wo][4] for the last layer
-  int Ho, Wo;
-};
-
-// Input channels of the first layer from a range image.
-__global__ void k_net_input(const float *__restrict__ range, SensorDev s, int H, int W, uint16_t *__restrict__ a0) {
+// Input channels of the first layer from a range image (one job, or
+// jobs[blockIdx.y]).
+__global__ void k_net_input(NetInputJob job, const NetInputJob *__restrict__ jobs) {
+  const NetInputJob J = jobs ? jobs[blockIdx.y] : job;
+  const int H = J.H, W = J.W;
+  uint16_t *__restrict__ a0 = J.a0;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= H * W) return;
   const int v = p / W, u = p - v * W;
-  const float r = range[p];
-  const float ce = s.ce[v], se = s.se[v], ca = s.ca[u], sa = s.sa[u];
+  const float r = J.range[p];
+  const float ce = J.ce[v], se = J.se[v], ca = J.ca[u], sa = J.sa[u];
   const float dx = ce * ca, dy = ce * sa;
   uint16_t *o = a0 + 4 * (size_t)p;
   o[0] = bf16_rne(r * 0.0625f);
@@ -198,7 +195,30 @@ void net_pack(const float *params, uint16_t *wpk, hipStream_t st) {
 
 void net_input(const float *range, const SensorDev &s, uint16_t *a0, hipStream_t st) {
   const int n = s.H * s.W;
-  hipLaunchKernelGGL(k_net_input, dim3((n + 255) / 256), dim3(256), 0, st, range, s, s.H, s.W, a0);
+  NetInputJob j{range, a0, s.ce, s.se, s.ca, s.sa, s.H, s.W};
+  hipLaunchKernelGGL(k_net_input, dim3((n + 255) / 256), dim3(256), 0, st, j, (const NetInputJob *)nullptr);
+}
+
+// Forward pass over many frames: input jobs in_jobs[n], convolution jobs
+// conv_jobs[4][n] (device tables); max_px[0] = largest H*W, max_px[1 + l] =
+// largest output of layer l.
+void net_forward_batch(const float *params, uint16_t *wpk, const NetInputJob *in_jobs, const ConvJob *conv_jobs, int n,
+                       const int *max_px, hipStream_t st) {
+  net_pack(params, wpk, st);
+  NetInputJob none{};
+  hipLaunchKernelGGL(k_net_input, dim3((max_px[0] + 255) / 256, n), dim3(256), 0, st, none, in_jobs);
+  ConvJob j[4] = {};
+  net_layers(params, wpk, j, conv_jobs, n, max_px + 1, st);
+}
+
+size_t net_packed_bytes() { return 2 * (size_t)net_packed_elems(); }
+
+size_t net_forward_act_bytes(int H, int W, size_t *a0, size_t *a1, size_t *a2, size_t *a3) {
+  *a0 = a256n(2 * 4 * (size_t)H * W);
+  *a1 = a256n(2 * 16 * (size_t)(H / 2) * (W / 2));
+  *a2 = a256n(2 * 32 * (size_t)(H / 4) * (W / 4));
+  *a3 = a256n(2 * 32 * (size_t)(H / 4) * (W / 8));
+  return *a0 + *a1 + *a2 + *a3;
 }
 
 hipError_t net_forward(const float *params, const float *range, const SensorDev &s, char *work, float *seed,

@@ -60,7 +60,8 @@ class pc_frame_desc(C.Structure):
 
 
 class pc_batch_opts(C.Structure):
-    _fields_ = [("persistent", C.c_int32), ("graph", C.c_int32), ("blocks_per_cu", C.c_int32)]
+    _fields_ = [("persistent", C.c_int32), ("graph", C.c_int32), ("blocks_per_cu", C.c_int32), ("pad", C.c_int32),
+                ("net", C.c_void_p)]
 
 
 # numpy views of the device records
@@ -100,7 +101,8 @@ EXPORTED = ("pc_stream_layout", "pc_workspace_size", "pc_ctx_create", "pc_ctx_de
             "pc_batch_info", "pc_batch_profile", "pc_batch_destroy", "pc_net_workspace_size", "pc_net_forward",
             "pc_net_backward", "pc_net_loss", "pc_net_adam")
 PC_NET_PARAMS = 15636
-LAUNCH_KINDS = {0: "reset", 1: "count", 2: "offsets", 3: "scatter", 4: "key", 5: "pred", 6: "finish"}
+LAUNCH_KINDS = {0: "reset", 1: "count", 2: "offsets", 3: "scatter", 4: "key", 5: "pred", 6: "finish",
+                7: "keyimage", 8: "net"}
 
 
 def _check(st: int):
@@ -235,9 +237,9 @@ def pc_check(ctx, frames, stream=None):
     _check(lib().pc_check(ctx, _stream(stream), arr, C.c_int32(len(frames))))
 
 
-def pc_batch_workspace_size(frames) -> int:
+def pc_batch_workspace_size(frames, opts=None) -> int:
     arr = (pc_frame_desc * len(frames))(*frames)
-    return int(lib().pc_batch_workspace_size(arr, C.c_int32(len(frames))))
+    return int(lib().pc_batch_workspace_size(arr, C.c_int32(len(frames)), C.byref(opts) if opts is not None else None))
 
 
 def pc_batch_create(ctx, frames, opts, workspace, ws_bytes):
@@ -351,7 +353,7 @@ class Batch:
     M (host 4x4 or None), sensor (Sensor), params (pc_params), key (int),
     out (FrameStream), range (device tensor or None), seed (tensor or None)."""
 
-    def __init__(self, ctx: Context, frames, persistent=True, graph=True, blocks_per_cu=0):
+    def __init__(self, ctx: Context, frames, persistent=True, graph=True, blocks_per_cu=0, net=None):
         import torch
         self._keep = []
         descs = []
@@ -373,9 +375,11 @@ class Batch:
             descs.append(d)
             self._keep += [f["sensor"], f["params"]]
         self.frames = frames
-        ws = pc_batch_workspace_size(descs)
+        self.net = net
+        opts = pc_batch_opts(1 if persistent else 0, 1 if graph else 0, blocks_per_cu, 0,
+                             net.data_ptr() if net is not None else None)
+        ws = pc_batch_workspace_size(descs, opts)
         self.ws = torch.empty(ws, dtype=torch.uint8, device=frames[0]["xyz"].device)
-        opts = pc_batch_opts(1 if persistent else 0, 1 if graph else 0, blocks_per_cu)
         self.h = pc_batch_create(ctx.h, descs, opts, self.ws, ws)
 
     def run(self, stream=None):

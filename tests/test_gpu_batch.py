@@ -106,3 +106,62 @@ def test_batch_rejects_bad_descriptors():
         pcc.Batch(ctx, [dict(xyz=xyz, sensor=S, params=prm4, key=1, out=o[0], M=np.eye(4)),
                         dict(xyz=xyz, sensor=S, params=prm4, key=0, out=o[1], M=np.eye(4))])
     ctx.close()
+
+
+def test_batch_with_seed_network_equals_per_frame():
+    """With a seed network the batch builds its key frames' range images,
+    runs the network and seeds the 4x8 key frames; every stream must equal the
+    per-frame path pc_project -> pc_net_forward -> pc_fit_key(seed) (and
+    pc_encode_pred against that key frame).  Key frames with other tile
+    shapes are not seeded."""
+    from oracle import seednet as sn
+    sensors, frames = _mixed_frames()
+    ctx = pcc.Context(sensors)
+    rng_np = np.random.default_rng(21)
+    params = sn.init_params(21)
+    params[-4:] = np.float32(2.0)            # positive logits: most key tiles try their seed
+    net = torch.from_numpy(params).to(DEV)
+    order = sorted(range(len(frames)), key=lambda i: frames[i]["key"] != i)
+    ref = [None] * len(frames)
+    seeded_any = False
+    for i in order:
+        f = frames[i]
+        S, prm = f["sensor"], f["params"]
+        xyz = torch.from_numpy(f["np"]).to(DEV)
+        rng = torch.empty(S.H, S.W, dtype=torch.float32, device=DEV)
+        pcc.pc_project(ctx.h, xyz, len(f["np"]), f["M"], S, rng)
+        fs = pcc.FrameStream(S, prm, DEV)
+        if f["key"] == i:
+            seed = None
+            if prm.tile_h == 4 and prm.tile_w == 8:
+                work = torch.zeros(pcc.pc_net_workspace_size(S), dtype=torch.uint8, device=DEV)
+                seed = torch.zeros(S.H // 4, S.W // 8, 4, dtype=torch.float32, device=DEV)
+                pcc.pc_net_forward(ctx.h, net, rng, S, work, seed)
+            pcc.pc_fit_key(ctx.h, rng, S, prm, seed, fs)
+        else:
+            pcc.pc_encode_pred(ctx.h, ref[f["key"]], rng, f["M"], S, prm, fs)
+        torch.cuda.synchronize()
+        ref[i] = fs
+    outs = [pcc.FrameStream(f["sensor"], f["params"], DEV) for f in frames]
+    bf = [dict(xyz=torch.from_numpy(f["np"]).to(DEV), M=f["M"], sensor=f["sensor"], params=f["params"],
+               key=f["key"], out=o) for f, o in zip(frames, outs)]
+    batch = pcc.Batch(ctx, bf, persistent=True, graph=True, net=net)
+    for rep in range(2):
+        for o in outs:
+            o.buf.fill_(0xCD)
+        batch.run()
+        torch.cuda.synchronize()
+        for i, (o, r) in enumerate(zip(outs, ref)):
+            a, b = o.host(), r.host()
+            assert a["info"].size_bytes == b["info"].size_bytes, (rep, i)
+            assert a["info"].seeded == b["info"].seeded and a["info"].fallback == b["info"].fallback, (rep, i)
+            for k in ("occ", "cls", "mask", "run_of", "nruns", "nres", "codes", "strip"):
+                assert np.array_equal(a[k], b[k]), (rep, i, k)
+            if frames[i]["key"] == i and frames[i]["params"].tile_w == 8:
+                seeded_any |= a["info"].seeded + a["info"].fallback > 0
+    assert seeded_any                      # the seeds were tried (accepted or fallen back)
+    prof = batch.profile()
+    kinds = [k for k, _ in prof]
+    assert "keyimage" in kinds and "net" in kinds
+    batch.close()
+    ctx.close()

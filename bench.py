@@ -85,6 +85,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seqs", type=int, default=96)
     ap.add_argument("--forms", default="plain,batched,learned")
+    ap.add_argument("--tune-seqs", type=int, default=8, help="sequences the autotuner times candidates on (0 = off)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2008_06972_amd", "weights", "seednet_c2.f32"),
                     help="seed-network parameters for the learned form")
     ap.add_argument("--plain-steps", type=int, default=5)
@@ -154,11 +155,15 @@ def main():
     # ------------------------------------------------- batched / learned
     batches = {}
 
-    def run_batched(name, net):
-        outs = [pcc.FrameStream(S, prm, dev) for _ in range(nfr)]
-        fr = [dict(xyz=xyz[i], M=None if i == key_of(i) else transforms[i], sensor=S, params=prm, key=key_of(i),
+    def run_batched(name, net, cfg=None):
+        prm_b = prm if cfg is None else pcc.params(eps=EPS, tile_h=cfg.tile[0], tile_w=cfg.tile[1], max_iter=5)
+        outs = [pcc.FrameStream(S, prm_b, dev) for _ in range(nfr)]
+        fr = [dict(xyz=xyz[i], M=None if i == key_of(i) else transforms[i], sensor=S, params=prm_b, key=key_of(i),
                    out=outs[i]) for i in range(nfr)]
-        batch = pcc.Batch(ctx, fr, persistent=True, graph=True, net=net)
+        pers = True if cfg is None else cfg.persistent
+        bpc = 0 if cfg is None else cfg.blocks_per_cu
+        batch = pcc.Batch(ctx, fr, persistent=pers, graph=True, blocks_per_cu=bpc,
+                          net=net if (cfg is None or cfg.seeded) else None)
         nitems, ngroups, grid = batch.info()
         log(f"{name}: {nitems} strip items, {ngroups} groups, persistent grid {grid}")
         for _ in range(a.warmup):
@@ -175,6 +180,7 @@ def main():
         key_infos = [infos[i] for i in range(nfr) if i == key_of(i)]
         tiles = sum(sum(i.tiles) for i in infos)
         st = {"ms_per_step": ms, "frames_per_s": nfr / (ms / 1e3),
+              "mapping": "default 4x8 persistent" if cfg is None else cfg.key(),
               "fits_per_tile": sum(i.fits for i in infos) / max(1, tiles),
               "key_fits_per_tile": sum(i.fits for i in key_infos) / max(1, sum(sum(i.tiles) for i in key_infos)),
               "seeded_tiles": int(sum(i.seeded for i in infos)), "fallback_tiles": int(sum(i.fallback for i in infos))}
@@ -185,13 +191,33 @@ def main():
         batches[name] = batch
         log(f"{name}: {ms:.3f} ms/step, {nfr / (ms / 1e3):.0f} frames/s")
 
-    if "batched" in a.forms:
-        run_batched("batched", None)
     net = None
     if "learned" in a.forms and os.path.exists(a.weights):
         net = torch.from_numpy(np.fromfile(a.weights, dtype="<f4")).to(dev)
         assert net.numel() == pcc.PC_NET_PARAMS, a.weights
-        run_batched("learned", net)
+    tuned = {}
+    if a.tune_seqs > 0:
+        # autotune the mapping on a sample (first --tune-seqs sequences):
+        # fastest plan whose ratio >= 0.98 x the plain 4x8 ratio
+        from paper_2008_06972_amd import autotune
+        sample = [(frames_np[q * N_FRAMES:(q + 1) * N_FRAMES], transforms[q * N_FRAMES:(q + 1) * N_FRAMES])
+                  for q in range(min(a.tune_seqs, a.seqs))]
+        t1 = time.time()
+        for name, shapes, use_net in (("batched", autotune.SHAPES, None), ("learned", ((4, 8),), net)):
+            if name not in a.forms or (name == "learned" and net is None):
+                continue
+            log(f"autotune {name}:")
+            best, cands, ref_ratio = autotune.tune(pcc, torch, ctx, S, EPS, sample, KEY_INDEX, net=use_net,
+                                                   shapes=shapes, log=log)
+            tuned[name] = best
+            result.setdefault("autotune", {})[name] = {
+                "chosen": best.key() if best else None, "reference_ratio": ref_ratio,
+                "candidates": {c.key(): {"ms": round(c.ms, 4), "ratio": round(c.ratio, 4), "ok": c.ok} for c in cands}}
+        result.setdefault("autotune", {})["sample"] = f"{len(sample)} sequences, {time.time() - t1:.1f}s"
+    if "batched" in a.forms:
+        run_batched("batched", None, tuned.get("batched"))
+    if net is not None:
+        run_batched("learned", net, tuned.get("learned"))
 
     # -------------------------------------------------------------- plain
     if "plain" in a.forms:
@@ -222,7 +248,7 @@ def main():
                           "host_ms_per_step": (time.time() - t_host) * 1e3 / a.plain_steps}
         sizes["plain"] = np.array([o.info().size_bytes for o in outs_p], np.int64)
         log(f"plain: {ms:.3f} ms/step, {nfr / (ms / 1e3):.0f} frames/s")
-        if "batched" in sizes:
+        if "batched" in sizes and forms["batched"]["mapping"].startswith(("default", "4x8")):
             same = bool(np.array_equal(sizes["plain"], sizes["batched"]))
             result["plain_equals_batched"] = same
             log("plain and batched streams have equal sizes:", same)
@@ -269,11 +295,12 @@ def main():
         # per point; the strip encoders read the bins and write the streams
         pts_k = sum(int(fin_per_frame[j]) for j in range(nfr) if j == key_of(j))
         pts_p = finite_pts - pts_k
+        Tb = batch.outs[0].L.T            # tiles per frame of the timed mapping
         alg = {
             "count": 12 * finite_pts,
             "scatter": 12 * finite_pts + 8 * finite_pts,
-            "key": 8 * pts_k + nk * (HW // 8 + 16 * T + 8 * T) + 2 * n_res_k,
-            "pred": 8 * pts_p + npf * (HW // 8 + 16 * T + 8 * T + 16 * T) + 2 * n_res_p,
+            "key": 8 * pts_k + nk * (HW // 8 + 16 * Tb + 8 * Tb) + 2 * n_res_k,
+            "pred": 8 * pts_p + npf * (HW // 8 + 16 * Tb + 8 * Tb + 16 * Tb) + 2 * n_res_p,
         }
         dur = {}
         for kind, t in prof:

@@ -1,0 +1,110 @@
+"""Autotuner of the batched encoder's mapping.
+
+For one sensor and error bound it times candidate plans on a sample of the
+workload and keeps the fastest whose compression ratio is at least
+``ratio_floor`` times the reference ratio (the plain 4x8-tile encoding of
+the same sample): a tile shape changes the encoding itself, so speed may
+not be bought with size.  Candidates combine
+
+* tile shape: 4x4, 4x8, 4x16, 8x8 (the compiled shapes);
+* work distribution: persistent work-groups pulling (frame, strip) items
+  from an atomic queue, or one work-group per strip;
+* persistent grid size: work-groups per CU.
+
+With a seed network only 4x8 tiles are seeded, so other shapes are timed
+without it.  Timing uses HIP events around replays of the captured graph.
+"""
+from __future__ import annotations
+
+import itertools
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SHAPES = ((4, 8), (4, 4), (4, 16), (8, 8))
+
+
+@dataclass
+class Candidate:
+    tile: tuple
+    persistent: bool
+    blocks_per_cu: int
+    seeded: bool
+    ms: float = float("nan")
+    ratio: float = float("nan")
+    ok: bool = False
+    notes: dict = field(default_factory=dict)
+
+    def key(self):
+        return f"{self.tile[0]}x{self.tile[1]} {'persistent' if self.persistent else 'grid'} " \
+               f"bpc={self.blocks_per_cu}{' seeded' if self.seeded else ''}"
+
+
+def candidates(shapes=SHAPES, blocks=(2, 4, 8), with_net=False):
+    out = []
+    for (th, tw), pers in itertools.product(shapes, (True, False)):
+        for b in (blocks if pers else (0,)):
+            out.append(Candidate((th, tw), pers, b, with_net and (th, tw) == (4, 8)))
+    return out
+
+
+def choose(cands, ref_ratio: float, ratio_floor: float = 0.98):
+    """Fastest candidate whose ratio >= ratio_floor * ref_ratio (None if none)."""
+    best = None
+    for c in cands:
+        c.ok = bool(np.isfinite(c.ms) and c.ratio >= ratio_floor * ref_ratio)
+        if c.ok and (best is None or c.ms < best.ms):
+            best = c
+    return best
+
+
+def measure(pcc, torch, ctx, sensor, eps, seqs, key_index, cand: Candidate, net=None, reps=5, warmup=2,
+            max_iter=5):
+    """Time one candidate on the sample; returns (ms per replay, ratio)."""
+    dev = torch.device("cuda:0")
+    prm = pcc.params(eps=eps, tile_h=cand.tile[0], tile_w=cand.tile[1], max_iter=max_iter)
+    frames = []
+    outs = []
+    pts = 0
+    for q, (fr, tr) in enumerate(seqs):
+        base = len(frames)
+        for i, p in enumerate(fr):
+            o = pcc.FrameStream(sensor, prm, dev)
+            outs.append(o)
+            frames.append(dict(xyz=torch.from_numpy(p).to(dev), M=None if i == key_index else tr[i], sensor=sensor,
+                               params=prm, key=base + key_index, out=o))
+            pts += int(np.isfinite(p).all(axis=1).sum())
+    batch = pcc.Batch(ctx, frames, persistent=cand.persistent, graph=True, blocks_per_cu=cand.blocks_per_cu,
+                      net=net if cand.seeded else None)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        batch.run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        batch.run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    size = sum(int(o.info().size_bytes) for o in outs)
+    batch.close()
+    return ms, 12.0 * pts / size
+
+
+def tune(pcc, torch, ctx, sensor, eps, seqs, key_index, net=None, ratio_floor=0.98, shapes=SHAPES, blocks=(2, 4, 8),
+         reps=5, log=None):
+    """Measure every candidate on the sample ``seqs`` (list of (frames,
+    transforms)); returns (best Candidate, all candidates, reference ratio).
+    The reference is the plain 4x8 encoding of the same sample."""
+    ref = Candidate((4, 8), True, 4, False)
+    ref.ms, ref_ratio = measure(pcc, torch, ctx, sensor, eps, seqs, key_index, ref, reps=1)
+    cands = candidates(shapes, blocks, with_net=net is not None)
+    for c in cands:
+        try:
+            c.ms, c.ratio = measure(pcc, torch, ctx, sensor, eps, seqs, key_index, c, net=net, reps=reps)
+        except pcc.PcError as e:          # shape not valid for this sensor
+            c.notes["error"] = str(e)
+        if log:
+            log(f"  {c.key():32s} {c.ms:8.3f} ms  ratio {c.ratio:7.3f}")
+    return choose(cands, ref_ratio, ratio_floor), cands, ref_ratio

@@ -69,19 +69,20 @@ __global__ void k_batch_reset(int *a, int64_t n) {
 
 // blocks [first[f], first[f+1]) belong to frame f; owner[b] = f
 __global__ void __launch_bounds__(kBinBlock) k_batch_count(const FrameDescDev *__restrict__ d, const int *__restrict__ owner,
-                                                           const int *__restrict__ first) {
+                                                           const int *__restrict__ first, int base) {
   __shared__ int hist[256];
-  const int fidx = __builtin_amdgcn_readfirstlane(owner[blockIdx.x]);
+  const int blk = base + blockIdx.x;
+  const int fidx = __builtin_amdgcn_readfirstlane(owner[blk]);
   const FrameDescDev &D = d[fidx];
   const int th = D.p.th, TR = D.f.TR;
   for (int t = threadIdx.x; t < TR; t += kBinBlock) hist[t] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)(blockIdx.x - first[fidx]) * kBinChunk;
+  const int64_t p0 = (int64_t)(blk - first[fidx]) * kBinChunk;
   const auto *xyz = (const __attribute__((address_space(1))) float *)D.xyz;
   auto *stage = (__attribute__((address_space(1))) uint64_t *)D.stage;    // x | y << 32
 #pragma unroll 2
   for (int q = 0; q < kBinPts; q++) {
-    const int64_t i = base + q * kBinBlock + threadIdx.x;
+    const int64_t i = p0 + q * kBinBlock + threadIdx.x;
     if (i >= D.n) break;
     int v, u;
     float r;
@@ -99,10 +100,11 @@ __global__ void __launch_bounds__(kBinBlock) k_batch_count(const FrameDescDev *_
     if (hist[t]) atomicAdd(&D.bcount[t], hist[t]);
 }
 
-__global__ void k_batch_offsets(const FrameDescDev *__restrict__ d, int nframes) {
-  int fidx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (fidx >= nframes) return;
-  const FrameDescDev &D = d[fidx];
+// frames[0 .. n): the frames whose strip offsets to compute
+__global__ void k_batch_offsets(const FrameDescDev *__restrict__ d, const int *__restrict__ frames, int n) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const FrameDescDev &D = d[frames[q]];
   int run = 0;
   for (int t = 0; t < D.f.TR; t++) {
     D.boff[t] = run;
@@ -112,14 +114,16 @@ __global__ void k_batch_offsets(const FrameDescDev *__restrict__ d, int nframes)
 }
 
 __global__ void __launch_bounds__(kBinBlock) k_batch_scatter(const FrameDescDev *__restrict__ d,
-                                                             const int *__restrict__ owner, const int *__restrict__ first) {
+                                                             const int *__restrict__ owner, const int *__restrict__ first,
+                                                             int bbase) {
   __shared__ int cnt[256], base[256], lim[256];
-  const int fidx = __builtin_amdgcn_readfirstlane(owner[blockIdx.x]);
+  const int blk = bbase + blockIdx.x;
+  const int fidx = __builtin_amdgcn_readfirstlane(owner[blk]);
   const FrameDescDev &D = d[fidx];
   const int TR = D.f.TR;
   for (int t = threadIdx.x; t < TR; t += kBinBlock) cnt[t] = 0;
   __syncthreads();
-  const int64_t b0 = (int64_t)(blockIdx.x - first[fidx]) * kBinChunk;
+  const int64_t b0 = (int64_t)(blk - first[fidx]) * kBinChunk;
   // entries are x | y << 32: x = strip << 16 | slot (~0 dropped), y = range bits
   const auto *stage = (const __attribute__((address_space(1))) uint64_t *)D.stage;
   auto *bucket = (__attribute__((address_space(1))) uint64_t *)D.bucket;
@@ -239,6 +243,14 @@ struct BatchPlan {
   FrameDescDev *d_desc = nullptr;
   int2 *d_items = nullptr;
   int *d_bin_owner = nullptr, *d_bin_first = nullptr;
+  // key frames' binning blocks come first, then the predicted frames'
+  int bin_blocks_key = 0;
+  int *d_key_frames = nullptr, *d_pred_frames = nullptr;
+  int nkey = 0, npred = 0;
+  // predicted frames are binned on a second stream while the key frames are
+  // encoded (fork and join by events; captured as parallel graph branches)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int *d_counters = nullptr;     // queue counters (64), then the frames' strip counts
   int64_t ncounters = 0;
   int bin_blocks = 0;
@@ -284,22 +296,59 @@ static size_t group_smem(int th, int tw, int W, bool pred) {
 }
 
 // All launches of one batch, in order; mark(kind) follows each (PC_LAUNCH_*).
+static hipError_t launch_group(BatchPlan &P, int gi, hipStream_t st) {
+  const Group &g = P.groups[gi];
+  const void *fn = group_fn(g, P.persistent != 0);
+  const int2 *items = P.d_items + g.first;
+  int nitems = g.count;
+  int *counter = P.d_counters + gi;
+  if (P.persistent) {
+    void *args[] = {(void *)&P.d_desc, (void *)&items, (void *)&nitems, (void *)&counter};
+    return hipLaunchKernel(fn, dim3(g.grid), dim3(kBlock), args, g.smem, st);
+  }
+  void *args[] = {(void *)&P.d_desc, (void *)&items};
+  return hipLaunchKernel(fn, dim3(g.count), dim3(kBlock), args, g.smem, st);
+}
+
+// Binning of one frame subset: count, offsets, scatter.
 template <class Mark>
-static hipError_t batch_launches(BatchPlan &P, hipStream_t st, Mark mark) {
+static void bin_frames(BatchPlan &P, bool key, hipStream_t st, Mark mark) {
+  const int nb = key ? P.bin_blocks_key : P.bin_blocks - P.bin_blocks_key;
+  const int base = key ? 0 : P.bin_blocks_key;
+  const int nf = key ? P.nkey : P.npred;
+  if (!nf) return;
+  if (nb) {
+    hipLaunchKernelGGL(k_batch_count, dim3(nb), dim3(kBinBlock), 0, st, P.d_desc, P.d_bin_owner, P.d_bin_first, base);
+    mark(PC_LAUNCH_COUNT);
+  }
+  hipLaunchKernelGGL(k_batch_offsets, dim3((nf + 63) / 64), dim3(64), 0, st, P.d_desc,
+                     key ? P.d_key_frames : P.d_pred_frames, nf);
+  mark(PC_LAUNCH_OFFSETS);
+  if (nb) {
+    hipLaunchKernelGGL(k_batch_scatter, dim3(nb), dim3(kBinBlock), 0, st, P.d_desc, P.d_bin_owner, P.d_bin_first,
+                       base);
+    mark(PC_LAUNCH_SCATTER);
+  }
+}
+
+// All launches of one batch, in order; mark(kind) follows each (PC_LAUNCH_*).
+// concurrent: the predicted frames' binning runs on the side stream while
+// the key frames are binned, seeded and encoded; serial: one stream.
+template <class Mark>
+static hipError_t batch_launches(BatchPlan &P, hipStream_t st, Mark mark, bool concurrent) {
   const int ngroups = (int)P.groups.size();
   int rb = (int)std::min<int64_t>(1024, (P.ncounters + 255) / 256);
   hipLaunchKernelGGL(k_batch_reset, dim3(rb), dim3(256), 0, st, P.d_counters, P.ncounters);
   mark(PC_LAUNCH_RESET);
-  if (P.bin_blocks) {
-    hipLaunchKernelGGL(k_batch_count, dim3(P.bin_blocks), dim3(kBinBlock), 0, st, P.d_desc, P.d_bin_owner, P.d_bin_first);
-    mark(PC_LAUNCH_COUNT);
+  concurrent = concurrent && P.side && P.npred > 0;
+  if (concurrent) {
+    hipEventRecord(P.ev_fork, st);
+    hipStreamWaitEvent(P.side, P.ev_fork, 0);
+    bin_frames(P, false, P.side, mark);
+    hipEventRecord(P.ev_join, P.side);
   }
-  hipLaunchKernelGGL(k_batch_offsets, dim3((P.nframes + 63) / 64), dim3(64), 0, st, P.d_desc, P.nframes);
-  mark(PC_LAUNCH_OFFSETS);
-  if (P.bin_blocks) {
-    hipLaunchKernelGGL(k_batch_scatter, dim3(P.bin_blocks), dim3(kBinBlock), 0, st, P.d_desc, P.d_bin_owner, P.d_bin_first);
-    mark(PC_LAUNCH_SCATTER);
-  }
+  bin_frames(P, true, st, mark);
+  if (!concurrent) bin_frames(P, false, st, mark);
   if (P.nnet) {
     hipLaunchKernelGGL((k_batch_keyimage<4, 8>), dim3(P.n_net_items), dim3(kBlock), P.net_smem, st, P.d_desc,
                        P.d_net_items);
@@ -308,21 +357,11 @@ static hipError_t batch_launches(BatchPlan &P, hipStream_t st, Mark mark) {
     mark(PC_LAUNCH_NET);
   }
   for (int pass = 0; pass < 2; pass++) {      // key groups, then predicted groups
+    if (pass == 1 && concurrent) hipStreamWaitEvent(st, P.ev_join, 0);
     for (int gi = 0; gi < ngroups; gi++) {
       const Group &g = P.groups[gi];
       if (g.kind != pass || g.count == 0) continue;
-      const void *fn = group_fn(g, P.persistent != 0);
-      const int2 *items = P.d_items + g.first;
-      int nitems = g.count;
-      int *counter = P.d_counters + gi;
-      hipError_t e;
-      if (P.persistent) {
-        void *args[] = {(void *)&P.d_desc, (void *)&items, (void *)&nitems, (void *)&counter};
-        e = hipLaunchKernel(fn, dim3(g.grid), dim3(kBlock), args, g.smem, st);
-      } else {
-        void *args[] = {(void *)&P.d_desc, (void *)&items};
-        e = hipLaunchKernel(fn, dim3(g.count), dim3(kBlock), args, g.smem, st);
-      }
+      hipError_t e = launch_group(P, gi, st);
       if (e != hipSuccess) return e;
       mark(pass == 0 ? PC_LAUNCH_KEY : PC_LAUNCH_PRED);
     }
@@ -400,7 +439,7 @@ static pc_status batch_sizes(const pc_frame_desc *frames, int32_t nframes, const
   B.net_items = net_items;
   B.desc = a256(sizeof(FrameDescDev) * (size_t)nframes);
   B.items = a256(sizeof(int2) * (size_t)items);
-  B.bins = a256(sizeof(int) * ((size_t)bb + (size_t)nframes));
+  B.bins = a256(sizeof(int) * ((size_t)bb + 2 * (size_t)nframes));     // owner, first, frame lists
   B.counters = a256(sizeof(int) * (64 + 3 * (size_t)strips));
   B.buckets = buckets;
   B.net = net;
@@ -582,23 +621,34 @@ pc_status pc_batch_create(pc_ctx *ctx, const pc_frame_desc *frames, int32_t nfra
       return set_error(PC_ERR_DEVICE, "network table upload failed");
     }
   }
-  // block -> frame table of the binning passes
-  std::vector<int> bin_owner, bin_first(nframes);
-  for (int i = 0; i < nframes; i++) {
-    bin_first[i] = (int)bin_owner.size();
-    for (int64_t q = 0; q < (desc[i].n + kBinChunk - 1) / kBinChunk; q++) bin_owner.push_back(i);
-  }
+  // block -> frame table of the binning passes: key frames' blocks first
+  std::vector<int> bin_owner, bin_first(nframes), flist;
+  for (int pass = 0; pass < 2; pass++)
+    for (int i = 0; i < nframes; i++) {
+      if (desc[i].kind != pass) continue;
+      bin_first[i] = (int)bin_owner.size();
+      for (int64_t q = 0; q < (desc[i].n + kBinChunk - 1) / kBinChunk; q++) bin_owner.push_back(i);
+      flist.push_back(i);
+      if (pass == 0) P.bin_blocks_key = (int)bin_owner.size(), P.nkey++;
+      else P.npred++;
+    }
   P.bin_blocks = (int)bin_owner.size();
   P.d_desc = (FrameDescDev *)ws;
   P.d_items = (int2 *)(ws + B.desc);
   P.d_bin_owner = (int *)(ws + B.desc + B.items);
   P.d_bin_first = P.d_bin_owner + bin_owner.size();
+  P.d_key_frames = P.d_bin_first + nframes;
+  P.d_pred_frames = P.d_key_frames + P.nkey;
   P.d_counters = counters;
   P.ncounters = 64 + B.strips;      // queue counters and the strip counts (offsets and cursors are rewritten)
   bool ok = hipMemcpy(P.d_desc, desc.data(), sizeof(FrameDescDev) * desc.size(), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(P.d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice) == hipSuccess &&
             (bin_owner.empty() || hipMemcpy(P.d_bin_owner, bin_owner.data(), sizeof(int) * bin_owner.size(), hipMemcpyHostToDevice) == hipSuccess) &&
-            hipMemcpy(P.d_bin_first, bin_first.data(), sizeof(int) * nframes, hipMemcpyHostToDevice) == hipSuccess;
+            hipMemcpy(P.d_bin_first, bin_first.data(), sizeof(int) * nframes, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(P.d_key_frames, flist.data(), sizeof(int) * nframes, hipMemcpyHostToDevice) == hipSuccess &&
+            hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&P.ev_fork, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&P.ev_join, hipEventDisableTiming) == hipSuccess;
   if (!ok) {
     delete b;
     return set_error(PC_ERR_DEVICE, "descriptor upload failed");
@@ -620,7 +670,7 @@ pc_status pc_batch_run(pc_batch *b, void *stream) {
         return set_error(PC_ERR_DEVICE, "stream creation failed");
       hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
       if (e == hipSuccess) {
-        hipError_t le = batch_launches(P, cap, nomark);
+        hipError_t le = batch_launches(P, cap, nomark, true);
         e = hipStreamEndCapture(cap, &P.graph);
         if (le != hipSuccess) e = le;
       }
@@ -632,7 +682,7 @@ pc_status pc_batch_run(pc_batch *b, void *stream) {
     if (e != hipSuccess) return set_error(PC_ERR_DEVICE, "graph launch failed: %s", hipGetErrorString(e));
     return PC_OK;
   }
-  hipError_t e = batch_launches(P, st, nomark);
+  hipError_t e = batch_launches(P, st, nomark, true);
   if (e != hipSuccess) return set_error(PC_ERR_DEVICE, "batch launch failed: %s", hipGetErrorString(e));
   return PC_OK;
 }
@@ -651,7 +701,7 @@ pc_status pc_batch_profile(pc_batch *b, void *stream, float *ms, int32_t *kinds,
     kind.push_back(k);
   };
   mark(-1);
-  hipError_t le = batch_launches(P, st, mark);
+  hipError_t le = batch_launches(P, st, mark, false);
   hipError_t e = hipEventSynchronize(ev.back());
   int n = 0;
   for (size_t i = 1; i < ev.size() && n < cap; i++, n++) {
@@ -684,6 +734,9 @@ pc_status pc_batch_destroy(pc_batch *b) {
   if (!b) return PC_OK;
   if (b->plan.exec) hipGraphExecDestroy(b->plan.exec);
   if (b->plan.graph) hipGraphDestroy(b->plan.graph);
+  if (b->plan.ev_fork) hipEventDestroy(b->plan.ev_fork);
+  if (b->plan.ev_join) hipEventDestroy(b->plan.ev_join);
+  if (b->plan.side) hipStreamDestroy(b->plan.side);
   delete b;
   return PC_OK;
 }

@@ -93,7 +93,12 @@ __global__ void k_net_input(NetInputJob job, const NetInputJob *__restrict__ job
   o[3] = bf16_rne((r * se) * 0.0625f);
 }
 
-// One wavefront: 16 consecutive output pixels x all output channels.
+// One wavefront: kMT groups of 16 consecutive output pixels x all output
+// channels.  The weights (B operands) are loaded once per wavefront and
+// reused for every pixel group; each group's input gathers (A operands) are
+// all issued before its MFMA chain.
+constexpr int kMT = 4;
+
 template <int CI, int CO, int SY, int SX, bool LAST>
 __global__ void __launch_bounds__(256) k_net_conv(ConvJob job, const ConvJob *__restrict__ jobs,
                                                   const uint16_t *__restrict__ wpk, const float *__restrict__ bias) {
@@ -101,42 +106,97 @@ __global__ void __launch_bounds__(256) k_net_conv(ConvJob job, const ConvJob *__
   const ConvJob J = jobs ? jobs[blockIdx.y] : job;
   const int lane = threadIdx.x & 63, g = lane >> 4, m = lane & 15;
   const int npx = J.Ho * J.Wo;
+  const int pw = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 * kMT;
+  if (pw >= npx) return;
+  bf16x4 b[KSTEPS][NB];
+#pragma unroll
+  for (int s = 0; s < KSTEPS; s++)
+#pragma unroll
+    for (int nb = 0; nb < NB; nb++)
+      b[s][nb] = *reinterpret_cast<const bf16x4 *>(wpk + (size_t)(nb * 16 + m) * KPAD + 16 * s + 4 * g);
+  float bv[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; nb++) bv[nb] = nb * 16 + m < CO ? bias[nb * 16 + m] : 0.0f;
+  for (int t = 0; t < kMT; t++) {
+    const int p0 = pw + 16 * t;
+    if (p0 >= npx) break;
+    const int p = p0 + m;
+    const int oy = p / J.Wo, ox = p - oy * J.Wo;
+    bf16x4 a[KSTEPS];
+#pragma unroll
+    for (int s = 0; s < KSTEPS; s++) {
+      const int k0 = 16 * s + 4 * g, pos = k0 / CI, ci0 = k0 % CI;
+      const int iy = oy * SY - 1 + pos / 3, ix = ox * SX - 1 + pos % 3;
+      const bool ok = pos < 9 && p < npx && iy >= 0 && iy < J.Hi && ix >= 0 && ix < J.Wi;
+      const int cy = ok ? iy : 0, cx = ok ? ix : 0;
+      const bf16x4 v = *reinterpret_cast<const bf16x4 *>(J.in + ((size_t)cy * J.Wi + cx) * CI + ci0);
+      a[s] = ok ? v : bf16x4{0, 0, 0, 0};
+    }
+    f32x4 acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; nb++) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < KSTEPS; s++)
+#pragma unroll
+      for (int nb = 0; nb < NB; nb++) acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[s], b[s][nb], acc[nb], 0, 0, 0);
+    // lane holds D[pixel 4g + i][channel nb*16 + m]
+#pragma unroll
+    for (int nb = 0; nb < NB; nb++) {
+      const int ch = nb * 16 + m;
+      if (ch >= CO) continue;
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        const int pix = p0 + 4 * g + i;
+        if (pix >= npx) continue;
+        const float v = acc[nb][i] + bv[nb];
+        if (LAST) static_cast<float *>(J.out)[(size_t)pix * 4 + ch] = v;
+        else static_cast<uint16_t *>(J.out)[(size_t)pix * CO + ch] = bf16_rne(fmaxf(v, 0.0f));
+      }
+    }
+  }
+}
+
+// The first layer straight from the range image (batched forward only):
+// a lane's four K values are the four input channels of one pixel, computed
+// as k_net_input computes them, so the result equals input + first layer.
+__global__ void __launch_bounds__(256) k_net_conv1_range(const NetInputJob *__restrict__ in_jobs,
+                                                         const ConvJob *__restrict__ jobs,
+                                                         const uint16_t *__restrict__ wpk, const float *__restrict__ bias) {
+  constexpr int CI = 4, CO = 16, KPAD = net_kpad(CI), KSTEPS = KPAD / 16;
+  const NetInputJob I = in_jobs[blockIdx.y];
+  const ConvJob J = jobs[blockIdx.y];
+  const int lane = threadIdx.x & 63, g = lane >> 4, m = lane & 15;
+  const int npx = J.Ho * J.Wo;
   const int p0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
   if (p0 >= npx) return;
   const int p = p0 + m;
   const int oy = p / J.Wo, ox = p - oy * J.Wo;
-  f32x4 acc[NB];
-#pragma unroll
-  for (int nb = 0; nb < NB; nb++) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  bf16x4 a[KSTEPS], b[KSTEPS];
 #pragma unroll
   for (int s = 0; s < KSTEPS; s++) {
-    const int k0 = 16 * s + 4 * g, pos = k0 / CI, ci0 = k0 % CI;
-    bf16x4 a = {0, 0, 0, 0};
-    if (pos < 9 && p < npx) {
-      const int iy = oy * SY - 1 + pos / 3, ix = ox * SX - 1 + pos % 3;
-      if (iy >= 0 && iy < J.Hi && ix >= 0 && ix < J.Wi)
-        a = *reinterpret_cast<const bf16x4 *>(J.in + ((size_t)iy * J.Wi + ix) * CI + ci0);
-    }
-#pragma unroll
-    for (int nb = 0; nb < NB; nb++) {
-      const bf16x4 b = *reinterpret_cast<const bf16x4 *>(wpk + (size_t)(nb * 16 + m) * KPAD + k0);
-      acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nb], 0, 0, 0);
-    }
+    const int pos = (16 * s + 4 * g) / CI;
+    const int iy = oy * 2 - 1 + pos / 3, ix = ox * 2 - 1 + pos % 3;
+    const bool ok = pos < 9 && p < npx && iy >= 0 && iy < I.H && ix >= 0 && ix < I.W;
+    const int cy = ok ? iy : 0, cx = ok ? ix : 0;
+    const float r = I.range[(size_t)cy * I.W + cx];
+    const float ce = I.ce[cy], se = I.se[cy], ca = I.ca[cx], sa = I.sa[cx];
+    const float dx = ce * ca, dy = ce * sa;
+    bf16x4 v;
+    v[0] = (short)bf16_rne(r * 0.0625f);
+    v[1] = (short)bf16_rne((r * dx) * 0.0625f);
+    v[2] = (short)bf16_rne((r * dy) * 0.0625f);
+    v[3] = (short)bf16_rne((r * se) * 0.0625f);
+    a[s] = ok ? v : bf16x4{0, 0, 0, 0};
+    b[s] = *reinterpret_cast<const bf16x4 *>(wpk + (size_t)m * KPAD + 16 * s + 4 * g);
   }
-  // lane holds D[pixel 4g + i][channel nb*16 + m]
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int nb = 0; nb < NB; nb++) {
-    const int ch = nb * 16 + m;
-    if (ch >= CO) continue;
-    const float bv = bias[ch];
+  for (int s = 0; s < KSTEPS; s++) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[s], b[s], acc, 0, 0, 0);
+  const float bv = bias[m];
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
-      const int pix = p0 + 4 * g + i;
-      if (pix >= npx) continue;
-      const float v = acc[nb][i] + bv;
-      if (LAST) static_cast<float *>(J.out)[(size_t)pix * 4 + ch] = v;
-      else static_cast<uint16_t *>(J.out)[(size_t)pix * CO + ch] = bf16_rne(fmaxf(v, 0.0f));
-    }
+  for (int i = 0; i < 4; i++) {
+    const int pix = p0 + 4 * g + i;
+    if (pix < npx) static_cast<uint16_t *>(J.out)[(size_t)pix * CO + m] = bf16_rne(fmaxf(acc[i] + bv, 0.0f));
   }
 }
 
@@ -171,7 +231,7 @@ size_t net_workspace_bytes(int H, int W) { return net_work(nullptr, H, W).bytes;
 template <int CI, int CO, int SY, int SX, bool LAST>
 static void launch_conv(const ConvJob &j, const ConvJob *jobs, int njobs, int max_px, const uint16_t *wpk,
                         const float *bias, hipStream_t st) {
-  const int blocks = (max_px + 63) / 64;
+  const int blocks = (max_px + 64 * kMT - 1) / (64 * kMT);
   hipLaunchKernelGGL((k_net_conv<CI, CO, SY, SX, LAST>), dim3(blocks, njobs), dim3(256), 0, st, j, jobs, wpk, bias);
 }
 
@@ -205,10 +265,14 @@ void net_input(const float *range, const SensorDev &s, uint16_t *a0, hipStream_t
 void net_forward_batch(const float *params, uint16_t *wpk, const NetInputJob *in_jobs, const ConvJob *conv_jobs, int n,
                        const int *max_px, hipStream_t st) {
   net_pack(params, wpk, st);
-  NetInputJob none{};
-  hipLaunchKernelGGL(k_net_input, dim3((max_px[0] + 255) / 256, n), dim3(256), 0, st, none, in_jobs);
-  ConvJob j[4] = {};
-  net_layers(params, wpk, j, conv_jobs, n, max_px + 1, st);
+  hipLaunchKernelGGL(k_net_conv1_range, dim3((max_px[1] + 63) / 64, n), dim3(256), 0, st, in_jobs, conv_jobs,
+                     wpk + net_layer(0).poff, params + net_layer(0).boff);
+  launch_conv<16, 32, 2, 2, false>(ConvJob{}, conv_jobs + n, n, max_px[2], wpk + net_layer(1).poff,
+                                   params + net_layer(1).boff, st);
+  launch_conv<32, 32, 1, 2, false>(ConvJob{}, conv_jobs + 2 * n, n, max_px[3], wpk + net_layer(2).poff,
+                                   params + net_layer(2).boff, st);
+  launch_conv<32, 4, 1, 1, true>(ConvJob{}, conv_jobs + 3 * n, n, max_px[4], wpk + net_layer(3).poff,
+                                 params + net_layer(3).boff, st);
 }
 
 size_t net_packed_bytes() { return 2 * (size_t)net_packed_elems(); }

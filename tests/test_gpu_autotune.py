@@ -1,0 +1,30 @@
+"""Autotuner on the GPU: every candidate plan runs, and the chosen plan keeps
+the compression ratio within the floor of the plain 4x8 reference."""
+import numpy as np
+import pytest
+
+from paper_2008_06972_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2008_06972_amd import autotune, pcc  # noqa: E402
+
+
+def test_autotune_picks_a_valid_fast_plan():
+    s = synth.SENSORS["c1"]
+    S = pcc.Sensor.of(s)
+    ctx = pcc.Context([S])
+    seqs = []
+    for seed in (3100, 3101):
+        q = synth.make_sequence(s, "c1", seed, n_frames=10, shuffle=True)
+        seqs.append((q.frames, q.transforms))
+    best, cands, ref = autotune.tune(pcc, torch, ctx, S, 0.02, seqs, 5, shapes=((4, 8), (4, 4)), blocks=(2, 4), reps=2)
+    assert len(cands) == 6
+    assert all(np.isfinite(c.ms) and c.ms > 0 for c in cands)
+    assert best is not None and best.ok and best.ratio >= 0.98 * ref
+    assert best.ms == min(c.ms for c in cands if c.ok)
+    ctx.close()

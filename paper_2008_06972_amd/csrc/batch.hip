@@ -74,7 +74,7 @@ __global__ void __launch_bounds__(kBinBlock) k_batch_count(const FrameDescDev *_
   const int blk = base + blockIdx.x;
   const int fidx = __builtin_amdgcn_readfirstlane(owner[blk]);
   const FrameDescDev &D = d[fidx];
-  const int th = D.p.th, TR = D.f.TR;
+  const int th = D.p.th, thl = __ffs(th) - 1, TR = D.f.TR;     // tile heights are powers of two
   for (int t = threadIdx.x; t < TR; t += kBinBlock) hist[t] = 0;
   __syncthreads();
   const int64_t p0 = (int64_t)(blk - first[fidx]) * kBinChunk;
@@ -88,8 +88,8 @@ __global__ void __launch_bounds__(kBinBlock) k_batch_count(const FrameDescDev *_
     float r;
     uint64_t e = ~0ull;
     if (project_point(D.s, D.M, D.hasM, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], v, u, r) == PROJ_KEPT) {
-      const int strip = v / th;
-      const uint32_t x = ((uint32_t)strip << 16) | (uint32_t)strip_slot(v - strip * th, u, th, D.twl);
+      const int strip = v >> thl;
+      const uint32_t x = ((uint32_t)strip << 16) | (uint32_t)strip_slot(v & (th - 1), u, th, D.twl);
       e = (uint64_t)x | ((uint64_t)__float_as_uint(r) << 32);
       atomicAdd(&hist[strip], 1);
     }

@@ -835,7 +835,6 @@ __device__ void residuals_and_streams(StripSmem<TH, TW> &sm, const SensorDev &s,
   // codes, raster order within the strip
   uint16_t *res = f.res + (int64_t)tr * TH * W;
   uint32_t bad = 0;
-  uint32_t hi_last = 0u, hi_run = 0u;     // run of equal high code bytes not yet in the histogram
   for (int tc = tid; tc < TC; tc += kBlock) {
     int cl = sm.cls[tc];
     bool cov = cl == CLS_SPATIAL || cl == CLS_TEMPORAL;
@@ -857,17 +856,11 @@ __device__ void residuals_and_streams(StripSmem<TH, TW> &sm, const SensorDev &s,
           uint32_t code = (uint32_t)q;
           res[o++] = (uint16_t)code;
           hist_byte(sm.hist, S_RES, code & 255u);
-          if ((code >> 8) != hi_last) {
-            if (hi_run) atomicAdd(&sm.hist[S_RES * 256 + hi_last], hi_run);
-            hi_last = code >> 8;
-            hi_run = 0u;
-          }
-          hi_run++;
+          hist_byte(sm.hist, S_RES, code >> 8);
         }
       }
     }
   }
-  if (hi_run) atomicAdd(&sm.hist[S_RES * 256 + hi_last], hi_run);
   // per-tile outputs
   for (int tc = tid; tc < TC; tc += kBlock) {
     int t = tr * TC + tc;

@@ -349,35 +349,39 @@ __device__ __forceinline__ bool fit_plane_f64(const Tile &T, uint64_t S, Plane &
 }
 
 // Least-squares plane through the pixels in S, FP32:
-//  1. mean of r*d;
-//  2. scatter of the deviations e = fma(r, d, -mean) (one rounding from the
-//     exact product) and a closed-form eigenframe of it;
-//  3. the scatter again with each deviation rotated into that frame, so the
-//     small eigen-directions are accumulated free of the large one's
-//     rounding (elongated tiles: far ground seen by few beams);
-//  4. Jacobi on the nearly diagonal result, rotated back.
+//  1. sums of the deviations from one of the tile's points, p - p0 =
+//     fma(r, d, -p0) (one rounding), and of their products: the mean and an
+//     approximate scatter, whose closed-form eigenframe follows;
+//  2. the scatter again about the mean with each deviation rotated into
+//     that frame, so the small eigen-directions are accumulated free of the
+//     large one's rounding (elongated tiles: far ground seen by few beams);
+//  3. Jacobi on the nearly diagonal result, rotated back.
 // Returns false when FP32 cannot decide: the two smallest eigenvalues are
 // within kNearDegenerate of the largest (the caller then fits in FP64).
 // Pixels outside S enter every sum with weight 0 (no branches).
 template <class Tile>
 __device__ __forceinline__ bool fit_plane_f32(const Tile &T, uint64_t S, Plane &P) {
   float n = (float)__popcll(S);
+  // shift: the first pixel in S
+  const int j0 = __ffsll((long long)S) - 1;
+  const int i0 = j0 / Tile::TWc, k0 = j0 % Tile::TWc;
+  const Dir d0 = dir_of(T.ce[i0], T.se[i0], T.cal[k0 * T.cstride], T.sal[k0 * T.cstride]);
+  const float r0 = T.rp[j0];
+  const float px = r0 * d0.x, py = r0 * d0.y, pz = r0 * d0.z;
   float sx = 0.f, sy = 0.f, sz = 0.f;
-  T.each([&](int j, float r, const Dir &d) {
-    float rw = r * bitw(S, j);
-    sx = fmaf(rw, d.x, sx);
-    sy = fmaf(rw, d.y, sy);
-    sz = fmaf(rw, d.z, sz);
-  });
-  const float in = frcp(n);
-  float mx = sx * in, my = sy * in, mz = sz * in;
   float cxx = 0.f, cxy = 0.f, cxz = 0.f, cyy = 0.f, cyz = 0.f, czz = 0.f;
   T.each([&](int j, float r, const Dir &d) {
     float w = bitw(S, j);
-    float ex = fmaf(r, d.x, -mx) * w, ey = fmaf(r, d.y, -my) * w, ez = fmaf(r, d.z, -mz) * w;
+    float ex = fmaf(r, d.x, -px) * w, ey = fmaf(r, d.y, -py) * w, ez = fmaf(r, d.z, -pz) * w;
+    sx += ex; sy += ey; sz += ez;
     cxx = fmaf(ex, ex, cxx); cxy = fmaf(ex, ey, cxy); cxz = fmaf(ex, ez, cxz);
     cyy = fmaf(ey, ey, cyy); cyz = fmaf(ey, ez, cyz); czz = fmaf(ez, ez, czz);
   });
+  const float in = frcp(n);
+  const float ux0 = sx * in, uy0 = sy * in, uz0 = sz * in;
+  cxx -= sx * ux0; cxy -= sx * uy0; cxz -= sx * uz0;
+  cyy -= sy * uy0; cyz -= sy * uz0; czz -= sz * uz0;
+  const float mx = px + ux0, my = py + uy0, mz = pz + uz0;
   float ax, ay, az, lx, ly, lz;
   if (!eig3_frame_f32(cxx, cxy, cxz, cyy, cyz, czz, ax, ay, az, lx, ly, lz)) return false;
   float bx = ly * az - lz * ay, by = lz * ax - lx * az, bz = lx * ay - ly * ax;   // a2 = a3 x a1
@@ -397,7 +401,7 @@ __device__ __forceinline__ bool fit_plane_f32(const Tile &T, uint64_t S, Plane &
   s11 -= q1 * u1; s12 -= q1 * u2; s13 -= q1 * u3;
   s22 -= q2 * u2; s23 -= q2 * u3; s33 -= q3 * u3;
   float w1, w2, w3, l1, l2, l3;
-  jacobi3_f32(s11, s12, s13, s22, s23, s33, 4, w1, w2, w3, l1, l2, l3);
+  jacobi3_f32(s11, s12, s13, s22, s23, s33, 3, w1, w2, w3, l1, l2, l3);
   if (!((l2 - l1) > kNearDegenerate * l3)) return false;
   float nx = w1 * ax + w2 * bx + w3 * lx;
   float ny = w1 * ay + w2 * by + w3 * ly;

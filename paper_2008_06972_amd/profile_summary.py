@@ -10,7 +10,8 @@ reads the per-dispatch FETCH_SIZE and WRITE_SIZE counters (KiB) of the
 batched encoder's kernels and of a plain device copy of COPY_BYTES bytes
 (read once, written once); the copy's readings give the scale from counter
 units to bytes, which is applied to every kernel.  The result is JSON keyed
-by launch kind (count, scatter, key, pred, finish) with the hash of the
+by launch kind (count, scatter, keyimage, net, key, pred, finish, ...) with
+the hash of the
 kernel sources it was taken on.
 """
 from __future__ import annotations
@@ -23,7 +24,8 @@ import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
-KINDS = (("k_batch_count", "count"), ("k_batch_scatter", "scatter"), ("k_batch_key", "key"),
+KINDS = (("k_batch_count", "count"), ("k_batch_scatter", "scatter"), ("k_batch_keyimage", "keyimage"),
+         ("k_net_", "net"), ("k_batch_key", "key"),
          ("k_batch_pred", "pred"), ("k_batch_finish", "finish"), ("k_batch_offsets", "offsets"),
          ("k_batch_reset", "reset"))
 

@@ -11,8 +11,7 @@ batched encoder's kernels and of a plain device copy of COPY_BYTES bytes
 (read once, written once); the copy's readings give the scale from counter
 units to bytes, which is applied to every kernel.  The result is JSON keyed
 by launch kind (count, scatter, keyimage, net, key, pred, finish, ...) with
-the hash of the
-kernel sources it was taken on.
+the hash of the kernel sources it was taken on.
 """
 from __future__ import annotations
 

@@ -100,6 +100,8 @@ static pc_status check_params(const pc_sensor *s, const pc_params *p) {
   if (s) {
     if (s->H % p->tile_h || s->W % p->tile_w)
       return set_error(PC_ERR_UNSUPPORTED, "H %% tile_h and W %% tile_w must be 0 (%dx%d, tile %dx%d)", s->H, s->W, p->tile_h, p->tile_w);
+    // also keeps every strip's per-byte stream counts below 2^16 (16-bit
+    // LDS histogram bins): at most 2 bytes per pixel and 17 per run
     if ((size_t)p->tile_h * s->W > 16384) return set_error(PC_ERR_UNSUPPORTED, "tile_h * W must be <= 16384");
     if (pcc::strip_lds_bytes(p->tile_h, p->tile_w, s->W, true) > kMaxStripLds)
       return set_error(PC_ERR_UNSUPPORTED, "a %dx%d-tile strip of width %d needs more than %zu bytes of LDS", p->tile_h,

@@ -161,7 +161,7 @@ __device__ __forceinline__ StripSrc src_of(const FrameDescDev &D) {
 }
 
 template <int TH, int TW>
-__global__ void __launch_bounds__(kBlock) k_batch_key(const FrameDescDev *__restrict__ d, const int2 *__restrict__ items,
+__global__ void __launch_bounds__(kBlock, kStripWavesPerEU) k_batch_key(const FrameDescDev *__restrict__ d, const int2 *__restrict__ items,
                                                       int nitems, int *counter) {
   extern __shared__ __align__(16) char smem_raw[];
   __shared__ int s_item;
@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_key(const FrameDescDev *__rest
 }
 
 template <int TH, int TW>
-__global__ void __launch_bounds__(kBlock) k_batch_pred(const FrameDescDev *__restrict__ d, const int2 *__restrict__ items,
+__global__ void __launch_bounds__(kBlock, kStripWavesPerEU) k_batch_pred(const FrameDescDev *__restrict__ d, const int2 *__restrict__ items,
                                                        int nitems, int *counter) {
   extern __shared__ __align__(16) char smem_raw[];
   __shared__ int s_item;
@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_pred(const FrameDescDev *__res
 
 // One work-group per strip (no queue), for comparison and for the autotuner.
 template <int TH, int TW>
-__global__ void __launch_bounds__(kBlock) k_batch_key_grid(const FrameDescDev *__restrict__ d, const int2 *__restrict__ items) {
+__global__ void __launch_bounds__(kBlock, kStripWavesPerEU) k_batch_key_grid(const FrameDescDev *__restrict__ d, const int2 *__restrict__ items) {
   extern __shared__ __align__(16) char smem_raw[];
   const int2 fi = items[blockIdx.x];
   const FrameDescDev &D = d[fi.x];
@@ -204,7 +204,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_key_grid(const FrameDescDev *_
 }
 
 template <int TH, int TW>
-__global__ void __launch_bounds__(kBlock) k_batch_pred_grid(const FrameDescDev *__restrict__ d, const int2 *__restrict__ items) {
+__global__ void __launch_bounds__(kBlock, kStripWavesPerEU) k_batch_pred_grid(const FrameDescDev *__restrict__ d, const int2 *__restrict__ items) {
   extern __shared__ __align__(16) char smem_raw[];
   const int2 fi = items[blockIdx.x];
   const FrameDescDev &D = d[fi.x];
@@ -602,7 +602,7 @@ pc_status pc_batch_create(pc_ctx *ctx, const pc_frame_desc *frames, int32_t nfra
     P.net_wpk = net_wpk;
     P.d_net_items = d_net_items;
     P.n_net_items = (int)net_items.size();
-    P.net_smem = sizeof(float) * (size_t)(net_maxW / 8) * StripSmem<4, 8>::NP;
+    P.net_smem = sizeof(float) * (size_t)(net_maxW / 8) * StripSmem<4, 8>::N;
     P.d_net_in = d_net_in;
     P.d_net_conv = d_net_conv;
     for (int q = 0; q < 5; q++) P.net_px[q] = net_px[q];

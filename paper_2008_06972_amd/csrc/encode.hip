@@ -5,7 +5,7 @@
 namespace pcc {
 
 template <int TH, int TW>
-__global__ void __launch_bounds__(kBlock) k_encode_key(const float *__restrict__ range, SensorDev s, EncParams p,
+__global__ void __launch_bounds__(kBlock, kStripWavesPerEU) k_encode_key(const float *__restrict__ range, SensorDev s, EncParams p,
                                                        const float *__restrict__ seed, FrameDev f) {
   extern __shared__ __align__(16) char smem_raw[];
   StripSrc src{range, nullptr, nullptr, nullptr, nullptr};
@@ -13,7 +13,7 @@ __global__ void __launch_bounds__(kBlock) k_encode_key(const float *__restrict__
 }
 
 template <int TH, int TW>
-__global__ void __launch_bounds__(kBlock) k_encode_pred(const float *__restrict__ range, SensorDev s, EncParams p,
+__global__ void __launch_bounds__(kBlock, kStripWavesPerEU) k_encode_pred(const float *__restrict__ range, SensorDev s, EncParams p,
                                                         FrameDev key, FrameDev f) {
   extern __shared__ __align__(16) char smem_raw[];
   StripSrc src{range, nullptr, nullptr, nullptr, nullptr};

@@ -34,12 +34,25 @@ namespace pcc {
 constexpr int kReach = 6;     // tiles a fit measures its reach over before the walk continues it
 
 // ---------------------------------------------------------------- LDS layout
+// Ranges are stored tile-major, N = th*tw per tile with no padding; the
+// 16-byte units of a tile are XOR-swizzled by the tile index, so threads
+// reading the same unit of consecutive tiles (one tile per thread) hit
+// distinct LDS banks, with 32 or with 64 four-byte banks.
+__host__ __device__ constexpr int tile_swizzle(int tc, int units) {
+  return units == 4 ? ((tc >> 1) ^ (tc >> 2)) & 3 : (units == 8 ? (tc ^ (tc >> 3)) & 7 : tc & 15);
+}
+
+// LDS slot of element j (= row * tw + column) of tile tc.
+__host__ __device__ constexpr int tile_elem(int tc, int j, int n) {
+  return tc * n + ((((j >> 2) ^ tile_swizzle(tc, n >> 2))) << 2) + (j & 3);
+}
+
 template <int TH, int TW>
 struct StripSmem {
   static constexpr int N = TH * TW;
-  static constexpr int NP = N + 4;       // tile stride: 16-byte aligned rows, conflict-free 128-bit reads across threads
-  float *r;          // [TC * NP] ranges, tile-major
-  float *ca, *sa;    // [W] column tables
+  static constexpr int UNITS = N / 4;    // 16-byte units per tile
+  float *r;          // [TC * N] ranges, tile-major, units swizzled (tile_elem)
+  const float *gca, *gsa;   // [W] column tables (global memory; read through the caches)
   float *ce, *se;    // [TH] row tables of the strip
   float4 *plane;     // [TC] plane: a, b, c, axis (predicted frames: the temporal pass's, then the own fits')
   uint64_t *omask;   // [TC] pixels that plane reproduces
@@ -57,8 +70,7 @@ struct StripSmem {
   int32_t *krun;     // [TC] key run slot, -1 if the key tile is not plane coded (predicted frames)
   uint32_t *scratch; // fits: cur (u64[TC]), two work lists and the FP64 list (i16[TC] each);
                      // residuals: counts per (row, tile) (u32[TH * TC])
-  uint32_t *hist;    // [4 * 256]
-  uint32_t *occ;     // [TH * W / 32]
+  uint32_t *hist;    // [4 * 256] 16-bit counts, two per word (byte v of a stream in half v & 1)
   int32_t *misc;     // [32] counters
 
   __device__ uint32_t *cnt() const { return scratch; }
@@ -72,24 +84,21 @@ struct StripSmem {
   __host__ __device__ static size_t bytes(int W, int TC, bool pred) {
     auto a16 = [](size_t n) { return (n + 15) & ~(size_t)15; };
     size_t b = 0;
-    b += a16(sizeof(float) * (size_t)TC * NP);
-    b += 2 * a16(sizeof(float) * (size_t)W);
+    b += a16(sizeof(float) * (size_t)TC * N);
     b += 2 * a16(sizeof(float) * 16);
     b += a16(sizeof(float4) * TC) + 2 * a16(sizeof(uint64_t) * TC) + 6 * a16(TC) + a16(sizeof(int32_t) * TC) +
          3 * a16(sizeof(int16_t) * TC);
     b += a16(sizeof(uint64_t) * ((TC + 63) / 64));
     if (pred) b += a16(sizeof(int32_t) * TC);
     b += a16(scratch_bytes(TC));
-    b += a16(sizeof(uint32_t) * 1024) + a16(sizeof(uint32_t) * (TH * W / 32)) + a16(sizeof(int32_t) * 32);
+    b += a16(sizeof(uint32_t) * 512) + a16(sizeof(int32_t) * 32);
     return b + 64;
   }
 
   __device__ void carve(char *base, int W, int TC, bool pred) {
     char *p = base;
     auto take = [&](size_t n) { char *q = p; p += (n + 15) & ~(size_t)15; return q; };
-    r = (float *)take(sizeof(float) * (size_t)TC * NP);
-    ca = (float *)take(sizeof(float) * (size_t)W);
-    sa = (float *)take(sizeof(float) * (size_t)W);
+    r = (float *)take(sizeof(float) * (size_t)TC * N);
     ce = (float *)take(sizeof(float) * 16);
     se = (float *)take(sizeof(float) * 16);
     plane = (float4 *)take(sizeof(float4) * TC);
@@ -108,8 +117,7 @@ struct StripSmem {
     acc = (uint64_t *)take(sizeof(uint64_t) * ((TC + 63) / 64));
     krun = pred ? (int32_t *)take(sizeof(int32_t) * TC) : nullptr;
     scratch = (uint32_t *)take(scratch_bytes(TC));
-    hist = (uint32_t *)take(sizeof(uint32_t) * 1024);
-    occ = (uint32_t *)take(sizeof(uint32_t) * (TH * W / 32));
+    hist = (uint32_t *)take(sizeof(uint32_t) * 512);
     misc = (int32_t *)take(sizeof(int32_t) * 32);
   }
 };
@@ -123,11 +131,10 @@ __host__ __device__ inline size_t strip_lds_bytes(int th, int tw, int W, bool pr
   return 0;
 }
 
-// LDS slot of pixel (row i of the strip, column u) in StripSmem::r: tiles
-// of th*tw ranges (row-major inside the tile) at a stride of th*tw + 4.
+// LDS slot of pixel (row i of the strip, column u) in StripSmem::r.
 __host__ __device__ inline int strip_slot(int i, int u, int th, int tw_log2) {
   const int tw = 1 << tw_log2;
-  return (u >> tw_log2) * (th * tw + 4) + i * tw + (u & (tw - 1));
+  return tile_elem(u >> tw_log2, i * tw + (u & (tw - 1)), th * tw);
 }
 
 // misc[] slots
@@ -138,7 +145,7 @@ __device__ __forceinline__ Plane unpack_plane(float4 v) { return Plane{(int)v.w,
 
 // Bytes of the serialized streams go into the LDS histograms.
 __device__ __forceinline__ void hist_byte(uint32_t *hist, int stream, uint32_t v) {
-  atomicAdd(&hist[stream * 256 + (v & 255u)], 1u);
+  atomicAdd(&hist[stream * 128 + ((v & 255u) >> 1)], 1u << ((v & 1u) << 4));
 }
 __device__ __forceinline__ int varint_bytes(uint32_t *hist, uint32_t v) {
   int n = 0;
@@ -155,14 +162,10 @@ __device__ __forceinline__ void f32_bytes(uint32_t *hist, float x) {
 template <int TH, int TW>
 __device__ void strip_init(StripSmem<TH, TW> &sm, const SensorDev &s, int tr) {
   const int tid = threadIdx.x;
-  for (int q = tid; q < 1024; q += kBlock) sm.hist[q] = 0;
-  for (int q = tid; q < TH * s.W / 32; q += kBlock) sm.occ[q] = 0;
+  for (int q = tid; q < 512; q += kBlock) sm.hist[q] = 0;
   if (tid < 32) sm.misc[tid] = 0;
-  const float4 *ca4 = reinterpret_cast<const float4 *>(s.ca), *sa4 = reinterpret_cast<const float4 *>(s.sa);
-  for (int q = tid; q < s.W / 4; q += kBlock) {
-    reinterpret_cast<float4 *>(sm.ca)[q] = ca4[q];
-    reinterpret_cast<float4 *>(sm.sa)[q] = sa4[q];
-  }
+  sm.gca = s.ca;
+  sm.gsa = s.sa;
   if (tid < TH) {
     sm.ce[tid] = s.ce[tr * TH + tid];
     sm.se[tid] = s.se[tr * TH + tid];
@@ -173,7 +176,7 @@ __device__ void strip_init(StripSmem<TH, TW> &sm, const SensorDev &s, int tr) {
 template <int TH, int TW>
 __device__ __forceinline__ void load_strip(StripSmem<TH, TW> &sm, const float *__restrict__ range, const SensorDev &s,
                                            int tr) {
-  constexpr int NP = StripSmem<TH, TW>::NP;
+  constexpr int N = StripSmem<TH, TW>::N;
   const int W = s.W, nq = W / 4;
   const float4 *src = reinterpret_cast<const float4 *>(range + (int64_t)tr * TH * W);
   for (int e = threadIdx.x; e < TH * nq; e += kBlock) {
@@ -185,7 +188,7 @@ __device__ __forceinline__ void load_strip(StripSmem<TH, TW> &sm, const float *_
     q.z = q.z < INFINITY ? q.z : 0.0f;
     q.w = q.w < INFINITY ? q.w : 0.0f;
     int tc = u / TW, k = u % TW;
-    *reinterpret_cast<float4 *>(sm.r + tc * NP + i * TW + k) = q;
+    *reinterpret_cast<float4 *>(sm.r + tile_elem(tc, i * TW + k, N)) = q;
   }
 }
 
@@ -204,18 +207,18 @@ struct StripSrc {
 
 template <int TH, int TW>
 __device__ __forceinline__ void load_source(StripSmem<TH, TW> &sm, const StripSrc &src, const SensorDev &s, int tr) {
-  constexpr int NP = StripSmem<TH, TW>::NP, U = 8;
+  constexpr int N = StripSmem<TH, TW>::N, U = 8;
   const int W = s.W, TC = W / TW, tid = threadIdx.x;
   if (!src.bucket) {
     load_strip<TH, TW>(sm, src.range, s, tr);
   } else {
     uint32_t *ri = reinterpret_cast<uint32_t *>(sm.r);
-    for (int e = tid; e < TC * NP; e += kBlock) ri[e] = 0x7f800000u;   // +inf: empty
+    for (int e = tid; e < TC * N; e += kBlock) ri[e] = 0x7f800000u;   // +inf: empty
     __syncthreads();
     const int n = src.bcount[tr];
     // entry = slot | range bits << 32
     const auto *b = (const __attribute__((address_space(1))) uint64_t *)(src.bucket + src.boff[tr]);
-    const uint32_t lim = (uint32_t)(TC * NP);
+    const uint32_t lim = (uint32_t)(TC * N);
     // U entries in flight per thread before their atomics
     for (int q0 = tid; q0 < n; q0 += U * kBlock) {
       uint64_t en[U];
@@ -229,7 +232,7 @@ __device__ __forceinline__ void load_source(StripSmem<TH, TW> &sm, const StripSr
         if ((uint32_t)en[u] < lim) atomicMin(&ri[(uint32_t)en[u]], (uint32_t)(en[u] >> 32));
     }
     __syncthreads();
-    for (int e = tid; e < TC * NP; e += kBlock)
+    for (int e = tid; e < TC * N; e += kBlock)
       if (ri[e] == 0x7f800000u) ri[e] = 0u;
   }
   if (src.range_out) {
@@ -237,43 +240,42 @@ __device__ __forceinline__ void load_source(StripSmem<TH, TW> &sm, const StripSr
     float *dst = src.range_out + (int64_t)tr * TH * W;
     for (int e = tid; e < TH * W; e += kBlock) {
       int i = e / W, u = e - i * W;
-      dst[e] = sm.r[(u / TW) * NP + i * TW + (u % TW)];
+      dst[e] = sm.r[tile_elem(u / TW, i * TW + (u % TW), N)];
     }
   }
 }
 
-// A tile of the strip as seen by one thread: ranges and column tables in
-// LDS, the tile's column tables copied into registers.
+// A tile of the strip as seen by one thread: ranges in LDS, the tile's
+// column tables loaded into registers.
 template <int TH, int TW>
 __device__ __forceinline__ TileRows<TH, TW> tile_at(const StripSmem<TH, TW> &sm, int tc) {
   TileRows<TH, TW> T;
-  T.rp = sm.r + tc * StripSmem<TH, TW>::NP;
+  T.rp = sm.r + tc * StripSmem<TH, TW>::N;
+  T.sw = tile_swizzle(tc, StripSmem<TH, TW>::UNITS);
   T.ce = sm.ce;
   T.se = sm.se;
-  T.cal = sm.ca + tc * TW;
-  T.sal = sm.sa + tc * TW;
-  T.cstride = 1;
-  const float4 *ca4 = reinterpret_cast<const float4 *>(T.cal), *sa4 = reinterpret_cast<const float4 *>(T.sal);
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  typedef const __attribute__((address_space(1))) v4f gv4f;
+  gv4f *ca4 = (gv4f *)(sm.gca + tc * TW), *sa4 = (gv4f *)(sm.gsa + tc * TW);
 #pragma unroll
   for (int k4 = 0; k4 < TW / 4; k4++) {
-    float4 c = ca4[k4], d = sa4[k4];
+    const v4f c = ca4[k4], d = sa4[k4];
     T.ca[4 * k4] = c.x; T.ca[4 * k4 + 1] = c.y; T.ca[4 * k4 + 2] = c.z; T.ca[4 * k4 + 3] = c.w;
     T.sa[4 * k4] = d.x; T.sa[4 * k4 + 1] = d.y; T.sa[4 * k4 + 2] = d.z; T.sa[4 * k4 + 3] = d.w;
   }
-  T.V = 0;
-  T.nV = 0;
   return T;
 }
 
 // Valid pixels of tile tc (range > 0), bit j = i * TW + k.
 template <int TH, int TW>
 __device__ __forceinline__ uint64_t valid_bits(const StripSmem<TH, TW> &sm, int tc) {
-  constexpr int NP = StripSmem<TH, TW>::NP;
+  constexpr int N = StripSmem<TH, TW>::N;
   uint32_t lo = 0, hi = 0;
-  const float4 *q = reinterpret_cast<const float4 *>(sm.r + tc * NP);
+  const float4 *q = reinterpret_cast<const float4 *>(sm.r + tc * N);
+  const int sw = tile_swizzle(tc, N / 4);
 #pragma unroll
   for (int j4 = 0; j4 < TH * TW / 4; j4++) {
-    float4 v = q[j4];
+    float4 v = q[j4 ^ sw];
     uint32_t b = (uint32_t)(v.x > 0.0f) | ((uint32_t)(v.y > 0.0f) << 1) | ((uint32_t)(v.z > 0.0f) << 2) |
                  ((uint32_t)(v.w > 0.0f) << 3);
     const int j = 4 * j4;
@@ -392,12 +394,13 @@ __device__ void own_fits(StripSmem<TH, TW> &sm, const EncParams &p, int TC, Take
 // in pixel order, rounded once (the kept set of the refit depends on it).
 template <class Tile>
 __device__ __forceinline__ float seed_offset(const Tile &T, const Plane &Q) {
-  const int k1 = Q.k == 0 ? 1 : 0, k2 = Q.k == 2 ? 1 : 2;
+  const bool isx = Q.k == 0, isz = Q.k == 2;
   double sum = 0.0;
   int n = 0;
   T.each([&](int, float r, const Dir &d) {
-    const double p[3] = {(double)r * (double)d.x, (double)r * (double)d.y, (double)r * (double)d.z};
-    const double v = p[Q.k] + (double)Q.a * p[k1] + (double)Q.b * p[k2];
+    const double px = (double)r * (double)d.x, py = (double)r * (double)d.y, pz = (double)r * (double)d.z;
+    const double pk = isz ? pz : (isx ? px : py), pk1 = isx ? py : px, pk2 = isz ? py : pz;
+    const double v = pk + (double)Q.a * pk1 + (double)Q.b * pk2;
     sum += r > 0.0f ? v : 0.0;
     n += r > 0.0f;
   });
@@ -420,14 +423,15 @@ __device__ void seeded_fits(StripSmem<TH, TW> &sm, const EncParams &p, int TC, c
     uint8_t state = 0;
     const float4 s4 = seed[tc];
     if (s4.w > 0.0f && sm.nv[tc] >= p.min_pts && isfinite(s4.x) && isfinite(s4.y) && isfinite(s4.z)) {
-      const float n[3] = {s4.x, s4.y, s4.z};
       int k = 0;
-      float m = fabsf(n[0]);
-      if (fabsf(n[1]) > m) { k = 1; m = fabsf(n[1]); }
-      if (fabsf(n[2]) > m) { k = 2; m = fabsf(n[2]); }
+      float m = fabsf(s4.x);
+      if (fabsf(s4.y) > m) { k = 1; m = fabsf(s4.y); }
+      if (fabsf(s4.z) > m) { k = 2; m = fabsf(s4.z); }
       if (m > 0.0f) {
-        const int k1 = k == 0 ? 1 : 0, k2 = k == 2 ? 1 : 2;
-        Plane Q{k, n[k1] / n[k], n[k2] / n[k], 0.0f};
+        // stored form: dominant component k, then the other two in order
+        const float nk = k == 0 ? s4.x : (k == 1 ? s4.y : s4.z);
+        const float n1 = k == 0 ? s4.y : s4.x, n2 = k == 2 ? s4.y : s4.z;
+        Plane Q{k, n1 / nk, n2 / nk, 0.0f};
         TileRows<TH, TW> T = tile_at<TH, TW>(sm, tc);
         Q.c = seed_offset(T, Q);
         const uint64_t S1 = inliers(T, Q, p.eps);
@@ -563,16 +567,16 @@ __device__ __forceinline__ uint64_t inliers_at(const StripSmem<TH, TW> &sm, int 
 template <int TH, int TW, class Allowed>
 __device__ int extend_beyond(const StripSmem<TH, TW> &sm, const EncParams &p, const Plane &P, int s, int t, int TC,
                              Allowed allowed) {
-  constexpr int N = TH * TW, NP = StripSmem<TH, TW>::NP, TPW = 64 / N;
+  constexpr int N = TH * TW, TPW = 64 / N;
   const int lane = threadIdx.x & 63, w = lane / N, j = lane % N, i = j / TW, k = j % TW;
   const uint64_t segmask = (N == 64) ? ~0ull : ((1ull << N) - 1ull);
   int added = 0;
   while (t < TC) {
     const int tt = t + w;
     const bool in = tt < TC;
-    const float r = in ? sm.r[tt * NP + j] : 0.0f;
+    const float r = in ? sm.r[tile_elem(tt, j, N)] : 0.0f;
     bool inl = false;
-    if (r > 0.0f) inl = reproduces(P, dir_of(sm.ce[i], sm.se[i], sm.ca[tt * TW + k], sm.sa[tt * TW + k]), r, p.eps);
+    if (r > 0.0f) inl = reproduces(P, dir_of(sm.ce[i], sm.se[i], sm.gca[tt * TW + k], sm.gsa[tt * TW + k]), r, p.eps);
     const uint64_t B = __ballot(inl);
     const uint64_t m = (B >> (w * N)) & segmask;
     const bool ext = in && allowed(s, tt) && __popcll(m) >= need_of(p, in ? sm.nv[tt] : 0);
@@ -807,23 +811,16 @@ __device__ __forceinline__ uint64_t pext64(uint64_t m, uint64_t sel) {
 template <int TH, int TW>
 __device__ void residuals_and_streams(StripSmem<TH, TW> &sm, const SensorDev &s,
                                       const EncParams &p, const FrameDev &f, int tr, int fits, int fp64) {
-  constexpr int N = TH * TW, NP = StripSmem<TH, TW>::NP;
+  constexpr int N = TH * TW;
   const int TC = f.TC, W = s.W, tid = threadIdx.x;
-  // counts per (row in strip, tile) in raster order, OCC words, MASK bytes
+  // counts per (row in strip, tile) in raster order, MASK bytes
   for (int tc = tid; tc < TC; tc += kBlock) {
-    uint64_t V = 0;
-#pragma unroll
-    for (int j = 0; j < N; j++) V |= (uint64_t)(sm.r[tc * NP + j] > 0.0f) << j;
+    const uint64_t V = valid_bits<TH, TW>(sm, tc);
     int cl = sm.cls[tc];
     bool cov = cl == CLS_SPATIAL || cl == CLS_TEMPORAL;
     uint64_t R = V & ~(cov ? sm.fmask[tc] : 0ull);
 #pragma unroll
-    for (int i = 0; i < TH; i++) {
-      uint32_t rowbits = (uint32_t)((V >> (i * TW)) & ((1ull << TW) - 1ull));
-      sm.cnt()[i * TC + tc] = __popc((uint32_t)((R >> (i * TW)) & ((1ull << TW) - 1ull)));
-      int bit = i * W + tc * TW;
-      if (rowbits) atomicOr(&sm.occ[bit >> 5], rowbits << (bit & 31));
-    }
+    for (int i = 0; i < TH; i++) sm.cnt()[i * TC + tc] = __popc((uint32_t)((R >> (i * TW)) & ((1ull << TW) - 1ull)));
     int nv = sm.nv[tc];
     if (cov && nv > 0) {
       uint64_t packed = pext64(sm.fmask[tc], V);
@@ -845,7 +842,7 @@ __device__ void residuals_and_streams(StripSmem<TH, TW> &sm, const SensorDev &s,
 #pragma unroll
       for (int k = 0; k < TW; k++) {
         int j = i * TW + k;
-        float r = sm.r[tc * NP + j];
+        float r = sm.r[tile_elem(tc, j, N)];
         if (r > 0.0f && !((fm >> j) & 1ull)) {
           float q = rintf(r * p.inv);
           double back = (double)(q * p.step);
@@ -883,17 +880,28 @@ __device__ void residuals_and_streams(StripSmem<TH, TW> &sm, const SensorDev &s,
   atomicAdd(&red[6], fp64);
   if (bad) atomicOr(&red[7], 1);
   __syncthreads();
-  // OCC words to global and into the OCC histogram (little-endian bytes)
+  // OCC words (bit u % 32 of word (i * W + u) / 32: pixel (i, u) not
+  // empty) from the ranges, to global and into the OCC histogram
+  // (little-endian bytes).  A word covers 32 columns of one row: 32 / TW
+  // tiles, whole 16-byte units of each.
   const int nw = TH * W / 32;
   uint32_t *occ = f.occ + (int64_t)tr * nw;
   for (int q = tid; q < nw; q += kBlock) {
-    uint32_t wv = sm.occ[q];
+    const int i = q / (W / 32), u0 = (q % (W / 32)) * 32;
+    uint32_t wv = 0;
+#pragma unroll
+    for (int c4 = 0; c4 < 8; c4++) {
+      const int u = u0 + 4 * c4;
+      const float4 v = *reinterpret_cast<const float4 *>(sm.r + tile_elem(u / TW, i * TW + (u % TW), N));
+      wv |= ((uint32_t)(v.x > 0.0f) | ((uint32_t)(v.y > 0.0f) << 1) | ((uint32_t)(v.z > 0.0f) << 2) |
+             ((uint32_t)(v.w > 0.0f) << 3)) << (4 * c4);
+    }
     occ[q] = wv;
     for (int b = 0; b < 4; b++) hist_byte(sm.hist, S_OCC, (wv >> (8 * b)) & 255u);
   }
   __syncthreads();
   uint32_t *ss = f.strip + (int64_t)tr * PC_STRIP_WORDS;
-  for (int q = tid; q < 1024; q += kBlock) ss[q] = sm.hist[q];
+  for (int q = tid; q < 1024; q += kBlock) ss[q] = (sm.hist[q >> 1] >> ((q & 1) << 4)) & 0xffffu;
   if (tid == 0) {
     uint32_t *st = ss + 1024;
     st[PC_SS_VALID] = red[0];
@@ -919,7 +927,7 @@ __device__ __forceinline__ void count_valid(StripSmem<TH, TW> &sm, int TC) {
 
 // Key frame, one tile-row strip (Sec. III-C).
 template <int TH, int TW>
-__device__ void key_strip(char *smem_raw, const StripSrc &src, const SensorDev &s, const EncParams &p,
+__device__ __forceinline__ void key_strip(char *smem_raw, const StripSrc &src, const SensorDev &s, const EncParams &p,
                           const float *__restrict__ seed, const FrameDev &f, int tr) {
   StripSmem<TH, TW> sm;
   const int TC = f.TC;
@@ -954,7 +962,7 @@ __device__ void key_strip(char *smem_raw, const StripSrc &src, const SensorDev &
 
 // Predicted frame, one tile-row strip (Sec. III-D).
 template <int TH, int TW>
-__device__ void pred_strip(char *smem_raw, const FrameDev &key, const StripSrc &src, const SensorDev &s,
+__device__ __forceinline__ void pred_strip(char *smem_raw, const FrameDev &key, const StripSrc &src, const SensorDev &s,
                            const EncParams &p, const FrameDev &f, int tr) {
   StripSmem<TH, TW> sm;
   const int TC = f.TC;

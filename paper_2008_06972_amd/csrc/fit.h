@@ -236,27 +236,38 @@ __device__ __forceinline__ void jacobi3_f32(float a00, float a01, float a02, flo
 }
 
 // -------------------------------------------------------------- tile views
-// A tile as its owning thread sees it: ranges in LDS (tile-major, rows of
-// TW values 16-byte aligned), the TW column direction tables in registers,
-// the TH row tables in LDS (broadcast reads).  Loops go row by row: a row's
-// ranges arrive with 128-bit LDS reads and its pixels are unrolled.
+// A tile as its owning thread sees it: ranges in LDS (tile-major, the
+// tile's 16-byte units XOR-swizzled by sw), the TW column direction tables
+// in registers, the TH row tables in LDS (broadcast reads).  Loops go row by
+// row: a row's ranges arrive with 128-bit LDS reads and its pixels are
+// unrolled.
 template <int TH, int TW>
 struct TileRows {
   static constexpr int N = TH * TW;
   static constexpr int TWc = TW;
-  const float *rp;           // tile base: row i at rp + i * TW
+  const float *rp;           // tile base: element j at rp[4 * ((j / 4) ^ sw) + j % 4]
+  int sw;
   const float *ce, *se;      // TH row tables (LDS)
   float ca[TW], sa[TW];      // column tables of this tile (registers)
-  const float *cal, *sal;    // the same tables in LDS: column k at cal[k * cstride]
-  int cstride;
-  uint64_t V;
-  int nV;
+
+  __device__ __forceinline__ float at(int j) const { return rp[(((j >> 2) ^ sw) << 2) | (j & 3)]; }
+  // direction of pixel (i, k) for a k known only at run time: the column
+  // tables are selected from registers
+  __device__ __forceinline__ Dir dir_at(int i, int k) const {
+    float c = ca[0], s = sa[0];
+#pragma unroll
+    for (int q = 1; q < TW; q++) {
+      c = k == q ? ca[q] : c;
+      s = k == q ? sa[q] : s;
+    }
+    return dir_of(ce[i], se[i], c, s);
+  }
 
   __device__ __forceinline__ void row(int i, float (&r)[TW]) const {
-    const float4 *q = reinterpret_cast<const float4 *>(rp + i * TW);
+    const float4 *q = reinterpret_cast<const float4 *>(rp);
 #pragma unroll
     for (int k4 = 0; k4 < TW / 4; k4++) {
-      float4 v = q[k4];
+      float4 v = q[(i * (TW / 4) + k4) ^ sw];
       r[4 * k4] = v.x; r[4 * k4 + 1] = v.y; r[4 * k4 + 2] = v.z; r[4 * k4 + 3] = v.w;
     }
   }
@@ -311,8 +322,7 @@ __device__ __forceinline__ uint64_t inliers(const Tile &T, const Plane &P, float
     const int j = __ffsll((long long)u) - 1;
     u &= u - 1;
     const int i = j / Tile::TWc, k = j % Tile::TWc;
-    const Dir d = dir_of(T.ce[i], T.se[i], T.cal[k * T.cstride], T.sal[k * T.cstride]);
-    if (reproduces_exact(P.c, plane_den(P, d), T.rp[j], eps)) m |= 1ull << j;
+    if (reproduces_exact(P.c, plane_den(P, T.dir_at(i, k)), T.at(j), eps)) m |= 1ull << j;
   }
   return m;
 }
@@ -365,8 +375,8 @@ __device__ __forceinline__ bool fit_plane_f32(const Tile &T, uint64_t S, Plane &
   // shift: the first pixel in S
   const int j0 = __ffsll((long long)S) - 1;
   const int i0 = j0 / Tile::TWc, k0 = j0 % Tile::TWc;
-  const Dir d0 = dir_of(T.ce[i0], T.se[i0], T.cal[k0 * T.cstride], T.sal[k0 * T.cstride]);
-  const float r0 = T.rp[j0];
+  const Dir d0 = T.dir_at(i0, k0);
+  const float r0 = T.at(j0);
   const float px = r0 * d0.x, py = r0 * d0.y, pz = r0 * d0.z;
   float sx = 0.f, sy = 0.f, sz = 0.f;
   float cxx = 0.f, cxy = 0.f, cxz = 0.f, cyy = 0.f, cyz = 0.f, czz = 0.f;

@@ -10,6 +10,7 @@
 namespace pcc {
 
 constexpr int kBlock = 256;            // threads per strip work-group
+constexpr int kStripWavesPerEU = 3;  // strip encoders: three work-groups of four waves per CU (registers <= 168)
 constexpr size_t kMaxStripLds = 159 * 1024;   // LDS a strip work-group may take (160 KiB per CU, less static use)
 constexpr float kNearDegenerate = 1e-4f;   // FP32 eigen gap below this * lambda_max -> FP64 solve
 constexpr double kDegenerate = 1e-6;       // lambda_mid <= this * lambda_max -> no plane

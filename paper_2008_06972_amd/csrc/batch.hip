@@ -100,16 +100,29 @@ __global__ void __launch_bounds__(kBinBlock) k_batch_count(const FrameDescDev *_
     if (hist[t]) atomicAdd(&D.bcount[t], hist[t]);
 }
 
-// frames[0 .. n): the frames whose strip offsets to compute
-__global__ void k_batch_offsets(const FrameDescDev *__restrict__ d, const int *__restrict__ frames, int n) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= n) return;
-  const FrameDescDev &D = d[frames[q]];
-  int run = 0;
-  for (int t = 0; t < D.f.TR; t++) {
-    D.boff[t] = run;
-    D.bcur[t] = run;
-    run += D.bcount[t];
+// frames[0 .. n): the frames whose strip offsets to compute, one wavefront
+// per frame (exclusive prefix sum of the strip counts)
+__global__ void __launch_bounds__(256) k_batch_offsets(const FrameDescDev *__restrict__ d, const int *__restrict__ frames,
+                                                       int n) {
+  const int w = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6), lane = (int)(threadIdx.x & 63);
+  if (w >= n) return;
+  const FrameDescDev &D = d[frames[w]];
+  const int TR = D.f.TR;
+  int carry = 0;
+  for (int t0 = 0; t0 < TR; t0 += 64) {
+    const int t = t0 + lane;
+    const int c = t < TR ? D.bcount[t] : 0;
+    int x = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (t < TR) {
+      D.boff[t] = carry + x - c;
+      D.bcur[t] = carry + x - c;
+    }
+    carry += __shfl(x, 63, 64);
   }
 }
 
@@ -321,7 +334,7 @@ static void bin_frames(BatchPlan &P, bool key, hipStream_t st, Mark mark) {
     hipLaunchKernelGGL(k_batch_count, dim3(nb), dim3(kBinBlock), 0, st, P.d_desc, P.d_bin_owner, P.d_bin_first, base);
     mark(PC_LAUNCH_COUNT);
   }
-  hipLaunchKernelGGL(k_batch_offsets, dim3((nf + 63) / 64), dim3(64), 0, st, P.d_desc,
+  hipLaunchKernelGGL(k_batch_offsets, dim3((nf + 3) / 4), dim3(256), 0, st, P.d_desc,
                      key ? P.d_key_frames : P.d_pred_frames, nf);
   mark(PC_LAUNCH_OFFSETS);
   if (nb) {

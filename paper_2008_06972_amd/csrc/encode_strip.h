@@ -31,6 +31,16 @@
 
 namespace pcc {
 
+// Thread index inside the strip encoders, opaque to the optimizer: the
+// persistent kernels run the encoders in a loop over work items, and values
+// derived from the thread index would otherwise be hoisted out of that loop
+// and held in registers across the whole encoder.
+__device__ __forceinline__ int strip_tid() {
+  int t = (int)threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 constexpr int kReach = 6;     // tiles a fit measures its reach over before the walk continues it
 
 // ---------------------------------------------------------------- LDS layout
@@ -161,7 +171,7 @@ __device__ __forceinline__ void f32_bytes(uint32_t *hist, float x) {
 // --------------------------------------------------------- phase 0: loads
 template <int TH, int TW>
 __device__ void strip_init(StripSmem<TH, TW> &sm, const SensorDev &s, int tr) {
-  const int tid = threadIdx.x;
+  const int tid = strip_tid();
   for (int q = tid; q < 512; q += kBlock) sm.hist[q] = 0;
   if (tid < 32) sm.misc[tid] = 0;
   sm.gca = s.ca;
@@ -179,7 +189,7 @@ __device__ __forceinline__ void load_strip(StripSmem<TH, TW> &sm, const float *_
   constexpr int N = StripSmem<TH, TW>::N;
   const int W = s.W, nq = W / 4;
   const float4 *src = reinterpret_cast<const float4 *>(range + (int64_t)tr * TH * W);
-  for (int e = threadIdx.x; e < TH * nq; e += kBlock) {
+  for (int e = strip_tid(); e < TH * nq; e += kBlock) {
     int i = e / nq, u = (e % nq) * 4;
     float4 q = src[e];
     // empty pixels are 0 (+inf is taken as empty too)
@@ -208,7 +218,7 @@ struct StripSrc {
 template <int TH, int TW>
 __device__ __forceinline__ void load_source(StripSmem<TH, TW> &sm, const StripSrc &src, const SensorDev &s, int tr) {
   constexpr int N = StripSmem<TH, TW>::N, U = 8;
-  const int W = s.W, TC = W / TW, tid = threadIdx.x;
+  const int W = s.W, TC = W / TW, tid = strip_tid();
   if (!src.bucket) {
     load_strip<TH, TW>(sm, src.range, s, tr);
   } else {
@@ -298,11 +308,13 @@ __device__ __forceinline__ void list_push(StripSmem<TH, TW> &sm, int q, int TC, 
 // The fits of one iteration for the tiles on list q (n of them, every thread
 // having read n after the last barrier): (a) FP32 fits, the near-degenerate
 // ones gathered on the FP64 list; (b) FP64 fits of those, on_degenerate(tc)
-// for a degenerate scatter.  Planes go to sm.plane.  Ends after a barrier
-// with list q's and the FP64 list's counters cleared.
-template <int TH, int TW, class OnDegenerate>
-__device__ void fit_pass(StripSmem<TH, TW> &sm, int q, int n, int TC, int &fits, int &fp64, OnDegenerate on_degenerate) {
-  const int tid = threadIdx.x;
+// for a degenerate scatter.  Each plane goes to sm.plane and, in the same
+// thread, to keep(T, tc, P) (the kept-pixel test of the caller).  Ends after
+// a barrier with list q's and the FP64 list's counters cleared.
+template <int TH, int TW, class OnDegenerate, class Keep>
+__device__ void fit_pass(StripSmem<TH, TW> &sm, int q, int n, int TC, int &fits, int &fp64, OnDegenerate on_degenerate,
+                         Keep keep) {
+  const int tid = strip_tid();
   const int16_t *L = sm.list(q, TC);
   const uint64_t *cur = sm.cur();
   for (int e = tid; e < n; e += kBlock) {
@@ -310,19 +322,28 @@ __device__ void fit_pass(StripSmem<TH, TW> &sm, int q, int n, int TC, int &fits,
     TileRows<TH, TW> T = tile_at<TH, TW>(sm, tc);
     Plane P{0, 0.f, 0.f, 0.f};
     fits++;
-    if (fit_plane_f32(T, cur[tc], P)) sm.plane[tc] = pack_plane(P);
-    else list_push<TH, TW>(sm, 2, TC, tc);
+    if (fit_plane_f32(T, cur[tc], P)) {
+      sm.plane[tc] = pack_plane(P);
+      keep(T, tc, P);
+    } else {
+      list_push<TH, TW>(sm, 2, TC, tc);
+    }
   }
   __syncthreads();
   const int nf = sm.misc[M_F64];
   if (tid == 0) sm.misc[M_LIST + q] = 0;      // every thread has read n before (a)
+  if (nf == 0) return;
   for (int e = tid; e < nf; e += kBlock) {
     const int tc = sm.list(2, TC)[e];
     TileRows<TH, TW> T = tile_at<TH, TW>(sm, tc);
     Plane P{0, 0.f, 0.f, 0.f};
     fp64++;
-    if (fit_plane_f64(T, cur[tc], P)) sm.plane[tc] = pack_plane(P);
-    else on_degenerate(tc);
+    if (fit_plane_f64(T, cur[tc], P)) {
+      sm.plane[tc] = pack_plane(P);
+      keep(T, tc, P);
+    } else {
+      on_degenerate(tc);
+    }
   }
   __syncthreads();
   if (tid == 0) sm.misc[M_F64] = 0;            // every thread has read nf before (b)
@@ -334,7 +355,7 @@ __device__ void fit_pass(StripSmem<TH, TW> &sm, int q, int n, int TC, int &fits,
 // need(n) pixels are kept.  Results in plane/omask/stat/iters.
 template <int TH, int TW, class Take>
 __device__ void own_fits(StripSmem<TH, TW> &sm, const EncParams &p, int TC, Take take, int &fits, int &fp64) {
-  const int tid = threadIdx.x;
+  const int tid = strip_tid();
   uint64_t *cur = sm.cur();
   for (int tc = tid; tc < TC; tc += kBlock) {
     if (!take(tc)) continue;
@@ -352,33 +373,31 @@ __device__ void own_fits(StripSmem<TH, TW> &sm, const EncParams &p, int TC, Take
   int n = sm.misc[M_LIST];
   for (int it = 1; it <= p.max_iter && n > 0; it++) {
     const int q = (it - 1) & 1;
-    const int16_t *L = sm.list(q, TC);
-    fit_pass<TH, TW>(sm, q, n, TC, fits, fp64, [&](int tc) { sm.stat[tc] = ST_DEGENERATE; });
-    // kept pixels, convergence
-    for (int e = tid; e < n; e += kBlock) {
-      const int tc = L[e];
-      sm.iters[tc] = (uint8_t)it;
-      if (sm.stat[tc] == ST_DEGENERATE) {
-        sm.omask[tc] = 0;
-        continue;
-      }
-      TileRows<TH, TW> T = tile_at<TH, TW>(sm, tc);
-      const uint64_t S = cur[tc];
-      const uint64_t S2 = inliers(T, unpack_plane(sm.plane[tc]), p.eps);
-      if (S2 != S && __popcll(S2) < p.min_pts) {
-        sm.stat[tc] = ST_FAILED;
-        sm.omask[tc] = 0;
-        continue;
-      }
-      sm.omask[tc] = S2;
-      if (S2 != S && it < p.max_iter) {
-        cur[tc] = S2;
-        list_push<TH, TW>(sm, q ^ 1, TC, tc);
-      } else {
-        sm.stat[tc] = __popcll(S2) >= need_of(p, sm.nv[tc]) ? ST_ACCEPTED : ST_REJECTED;
-      }
-    }
-    __syncthreads();
+    fit_pass<TH, TW>(
+        sm, q, n, TC, fits, fp64,
+        [&](int tc) {
+          sm.iters[tc] = (uint8_t)it;
+          sm.stat[tc] = ST_DEGENERATE;
+          sm.omask[tc] = 0;
+        },
+        [&](const TileRows<TH, TW> &T, int tc, const Plane &P) {
+          // kept pixels, convergence
+          sm.iters[tc] = (uint8_t)it;
+          const uint64_t S = cur[tc];
+          const uint64_t S2 = inliers(T, P, p.eps);
+          if (S2 != S && __popcll(S2) < p.min_pts) {
+            sm.stat[tc] = ST_FAILED;
+            sm.omask[tc] = 0;
+            return;
+          }
+          sm.omask[tc] = S2;
+          if (S2 != S && it < p.max_iter) {
+            cur[tc] = S2;
+            list_push<TH, TW>(sm, q ^ 1, TC, tc);
+          } else {
+            sm.stat[tc] = __popcll(S2) >= need_of(p, sm.nv[tc]) ? ST_ACCEPTED : ST_REJECTED;
+          }
+        });
     n = sm.misc[M_LIST + (q ^ 1)];
   }
   __syncthreads();
@@ -417,7 +436,7 @@ __device__ __forceinline__ float seed_offset(const Tile &T, const Plane &Q) {
 template <int TH, int TW>
 __device__ void seeded_fits(StripSmem<TH, TW> &sm, const EncParams &p, int TC, const float4 *__restrict__ seed,
                             int &fits, int &fp64) {
-  const int tid = threadIdx.x;
+  const int tid = strip_tid();
   uint64_t *cur = sm.cur();
   for (int tc = tid; tc < TC; tc += kBlock) {
     uint8_t state = 0;
@@ -447,24 +466,20 @@ __device__ void seeded_fits(StripSmem<TH, TW> &sm, const EncParams &p, int TC, c
   }
   __syncthreads();
   const int n = sm.misc[M_LIST];
-  if (n > 0) {
-    fit_pass<TH, TW>(sm, 0, n, TC, fits, fp64, [&](int tc) { sm.elig[tc] = 2; });
-    const int16_t *L = sm.list(0, TC);
-    for (int e = tid; e < n; e += kBlock) {
-      const int tc = L[e];
-      if (sm.elig[tc] == 2) continue;
-      TileRows<TH, TW> T = tile_at<TH, TW>(sm, tc);
-      const uint64_t S2 = inliers(T, unpack_plane(sm.plane[tc]), p.eps);
-      if (__popcll(S2) >= need_of(p, sm.nv[tc])) {
-        sm.omask[tc] = S2;
-        sm.stat[tc] = ST_ACCEPTED;
-        sm.iters[tc] = 1;
-        sm.elig[tc] = 1;
-      } else {
-        sm.elig[tc] = 2;
-      }
-    }
-  }
+  if (n > 0)
+    fit_pass<TH, TW>(
+        sm, 0, n, TC, fits, fp64, [&](int tc) { sm.elig[tc] = 2; },
+        [&](const TileRows<TH, TW> &T, int tc, const Plane &P) {
+          const uint64_t S2 = inliers(T, P, p.eps);
+          if (__popcll(S2) >= need_of(p, sm.nv[tc])) {
+            sm.omask[tc] = S2;
+            sm.stat[tc] = ST_ACCEPTED;
+            sm.iters[tc] = 1;
+            sm.elig[tc] = 1;
+          } else {
+            sm.elig[tc] = 2;
+          }
+        });
   __syncthreads();
   int ns = 0, nb = 0;
   for (int tc = tid; tc < TC; tc += kBlock) {
@@ -482,7 +497,7 @@ __device__ void seeded_fits(StripSmem<TH, TW> &sm, const EncParams &p, int TC, c
 // stat: 2 accepted, 1 not, 0 no key plane.  Results in plane/omask/stat/iters.
 template <int TH, int TW>
 __device__ void temporal_fits(StripSmem<TH, TW> &sm, const FrameDev &key, const EncParams &p, int tr, int TC) {
-  const int tid = threadIdx.x;
+  const int tid = strip_tid();
   uint64_t *cur = sm.cur();
   for (int tc = tid; tc < TC; tc += kBlock) {
     const int t = tr * TC + tc;
@@ -568,7 +583,7 @@ template <int TH, int TW, class Allowed>
 __device__ int extend_beyond(const StripSmem<TH, TW> &sm, const EncParams &p, const Plane &P, int s, int t, int TC,
                              Allowed allowed) {
   constexpr int N = TH * TW, TPW = 64 / N;
-  const int lane = threadIdx.x & 63, w = lane / N, j = lane % N, i = j / TW, k = j % TW;
+  const int lane = strip_tid() & 63, w = lane / N, j = lane % N, i = j / TW, k = j % TW;
   const uint64_t segmask = (N == 64) ? ~0ull : ((1ull << N) - 1ull);
   int added = 0;
   while (t < TC) {
@@ -605,7 +620,7 @@ __device__ int extend_beyond(const StripSmem<TH, TW> &sm, const EncParams &p, co
 template <int TH, int TW, class Member, class Start, class Allowed, class PlaneOf, class MaskOf>
 __device__ int grow_runs(StripSmem<TH, TW> &sm, const EncParams &p, int TC, Member member, Start start,
                          Allowed allowed, PlaneOf plane_of, MaskOf own_mask, int *nr_out) {
-  const int tid = threadIdx.x, nw = (TC + 63) >> 6;
+  const int tid = strip_tid(), nw = (TC + 63) >> 6;
   for (int w = tid >> 6; w < nw; w += kBlock / 64) {
     const int tc = w * 64 + (tid & 63);
     const bool st = tc < TC && start(tc);
@@ -686,13 +701,13 @@ __device__ int grow_runs(StripSmem<TH, TW> &sm, const EncParams &p, int TC, Memb
 // bytes (emit), and the count of runs of the row.
 template <int TH, int TW, class EmitRun>
 __device__ void run_bytes(StripSmem<TH, TW> &sm, int nr, EmitRun emit) {
-  for (int q = threadIdx.x; q < nr; q += kBlock) {
+  for (int q = strip_tid(); q < nr; q += kBlock) {
     int prev_end = q ? sm.rs[q - 1] + sm.rl[q - 1] : 0;
     varint_bytes(sm.hist, (uint32_t)(sm.rs[q] - prev_end));
     varint_bytes(sm.hist, (uint32_t)sm.rl[q]);
     emit(sm.rs[q]);
   }
-  if (threadIdx.x == 0) varint_bytes(sm.hist, (uint32_t)nr);
+  if (strip_tid() == 0) varint_bytes(sm.hist, (uint32_t)nr);
 }
 
 // Spatial growth of one strip (Sec. III-C).  For predicted frames
@@ -700,7 +715,7 @@ __device__ void run_bytes(StripSmem<TH, TW> &sm, int nr, EmitRun emit) {
 // temporal runs and break spatial runs.
 template <int TH, int TW>
 __device__ void grow_spatial(StripSmem<TH, TW> &sm, const EncParams &p, const FrameDev &f, int tr, bool pred) {
-  const int TC = f.TC, tid = threadIdx.x;
+  const int TC = f.TC, tid = strip_tid();
   auto member = [&](int tc) { return !pred || sm.elig[tc] != 0; };
   const int nr = grow_runs<TH, TW>(
       sm, p, TC, member, [&](int tc) { return member(tc) && sm.stat[tc] == ST_ACCEPTED; },
@@ -739,7 +754,7 @@ __device__ void grow_spatial(StripSmem<TH, TW> &sm, const EncParams &p, const Fr
 // tile.  Tiles not covered become eligible for the spatial pass.
 template <int TH, int TW>
 __device__ void grow_temporal(StripSmem<TH, TW> &sm, const EncParams &p, const FrameDev &f, int tr) {
-  const int TC = f.TC, T = f.T, tid = threadIdx.x;
+  const int TC = f.TC, T = f.T, tid = strip_tid();
   const int nr = grow_runs<TH, TW>(
       sm, p, TC, [](int) { return true; }, [&](int tc) { return sm.stat[tc] == 2; },
       [&](int s, int t) { return sm.krun[t] == sm.krun[s]; }, [&](int s) { return unpack_plane(sm.plane[s]); },
@@ -764,7 +779,7 @@ __device__ void grow_temporal(StripSmem<TH, TW> &sm, const EncParams &p, const F
 // Block-wide exclusive scan of sm.cnt()[0 .. n) in place; returns the total.
 template <int TH, int TW>
 __device__ uint32_t block_exclusive_scan(StripSmem<TH, TW> &sm, int n) {
-  const int tid = threadIdx.x;
+  const int tid = strip_tid();
   const int per = (n + kBlock - 1) / kBlock;
   const int b = tid * per, e = min(n, b + per);
   uint32_t local = 0;
@@ -812,7 +827,7 @@ template <int TH, int TW>
 __device__ void residuals_and_streams(StripSmem<TH, TW> &sm, const SensorDev &s,
                                       const EncParams &p, const FrameDev &f, int tr, int fits, int fp64) {
   constexpr int N = TH * TW;
-  const int TC = f.TC, W = s.W, tid = threadIdx.x;
+  const int TC = f.TC, W = s.W, tid = strip_tid();
   // counts per (row in strip, tile) in raster order, MASK bytes
   for (int tc = tid; tc < TC; tc += kBlock) {
     const uint64_t V = valid_bits<TH, TW>(sm, tc);
@@ -922,7 +937,7 @@ __device__ void residuals_and_streams(StripSmem<TH, TW> &sm, const SensorDev &s,
 // Valid-pixel counts of the strip's tiles.
 template <int TH, int TW>
 __device__ __forceinline__ void count_valid(StripSmem<TH, TW> &sm, int TC) {
-  for (int tc = threadIdx.x; tc < TC; tc += kBlock) sm.nv[tc] = (uint8_t)__popcll(valid_bits<TH, TW>(sm, tc));
+  for (int tc = strip_tid(); tc < TC; tc += kBlock) sm.nv[tc] = (uint8_t)__popcll(valid_bits<TH, TW>(sm, tc));
 }
 
 // Key frame, one tile-row strip (Sec. III-C).
@@ -942,10 +957,10 @@ __device__ __forceinline__ void key_strip(char *smem_raw, const StripSrc &src, c
     seeded_fits<TH, TW>(sm, p, TC, reinterpret_cast<const float4 *>(seed) + (int64_t)tr * TC, fits, fp64);
     own_fits<TH, TW>(sm, p, TC, [&](int tc) { return sm.elig[tc] != 1; }, fits, fp64);
   } else {
-    for (int tc = threadIdx.x; tc < TC; tc += kBlock) sm.elig[tc] = 0;
+    for (int tc = strip_tid(); tc < TC; tc += kBlock) sm.elig[tc] = 0;
     own_fits<TH, TW>(sm, p, TC, [](int) { return true; }, fits, fp64);
   }
-  for (int tc = threadIdx.x; tc < TC; tc += kBlock) {
+  for (int tc = strip_tid(); tc < TC; tc += kBlock) {
     Plane P = unpack_plane(sm.plane[tc]);
     pc_tile_rec rec;
     rec.a = P.a; rec.b = P.b; rec.c = P.c;
@@ -955,7 +970,7 @@ __device__ __forceinline__ void key_strip(char *smem_raw, const StripSrc &src, c
     f.tiles[tr * TC + tc] = rec;
   }
   grow_spatial<TH, TW>(sm, p, f, tr, false);
-  if (threadIdx.x == 0) f.nruns[f.TR + tr] = 0;
+  if (strip_tid() == 0) f.nruns[f.TR + tr] = 0;
   __syncthreads();
   residuals_and_streams<TH, TW>(sm, s, p, f, tr, fits, fp64);
 }
@@ -971,7 +986,7 @@ __device__ __forceinline__ void pred_strip(char *smem_raw, const FrameDev &key, 
   load_source<TH, TW>(sm, src, s, tr);
   __syncthreads();
   count_valid<TH, TW>(sm, TC);
-  for (int tc = threadIdx.x; tc < TC; tc += kBlock) {
+  for (int tc = strip_tid(); tc < TC; tc += kBlock) {
     sm.cls[tc] = CLS_EMPTY;
     sm.elig[tc] = 0;
   }
@@ -979,7 +994,7 @@ __device__ __forceinline__ void pred_strip(char *smem_raw, const FrameDev &key, 
   int fits = 0, fp64 = 0;
   // temporal fits against the key frame's run planes, temporal runs
   temporal_fits<TH, TW>(sm, key, p, tr, TC);
-  for (int tc = threadIdx.x; tc < TC; tc += kBlock) {
+  for (int tc = strip_tid(); tc < TC; tc += kBlock) {
     pc_tile_rec rec;
     rec.a = 0.f; rec.b = 0.f; rec.c = 0.f; rec.axis = 0; rec.status = 0; rec.iters = 0;
     rec.t_status = sm.stat[tc]; rec.mask = 0; rec.t_mask = sm.omask[tc]; rec.t_c = sm.plane[tc].z;
@@ -990,7 +1005,7 @@ __device__ __forceinline__ void pred_strip(char *smem_raw, const FrameDev &key, 
   __syncthreads();
   // own fits of the tiles left over, spatial runs
   own_fits<TH, TW>(sm, p, TC, [&](int tc) { return sm.elig[tc] != 0; }, fits, fp64);
-  for (int tc = threadIdx.x; tc < TC; tc += kBlock) {
+  for (int tc = strip_tid(); tc < TC; tc += kBlock) {
     if (!sm.elig[tc]) continue;
     Plane P = unpack_plane(sm.plane[tc]);
     pc_tile_rec *rec = &f.tiles[tr * TC + tc];
@@ -1004,44 +1019,94 @@ __device__ __forceinline__ void pred_strip(char *smem_raw, const FrameDev &key, 
 }
 
 // --------------------------------------------------- per-frame stream size
-// Optimal Huffman cost of a byte histogram: with the leaves sorted, merge the
-// two lightest of (next leaf, next internal node) until one node is left;
-// the cost is the sum of the merged weights (two-queue construction).
-__device__ uint64_t huffman_cost_wave(uint32_t *h, uint64_t *q, int lane) {
-  // rank sort of the 256 counts (ties by index)
-  uint32_t c[4];
-  int rk[4];
+// 256 counts sorted ascending across a wavefront, element e in register
+// e / 64 of lane e % 64: bitonic network, partners in other lanes through
+// shuffles, partners in other registers of the same lane directly.
+__device__ __forceinline__ void wave_sort256(uint32_t (&v)[4], int lane) {
 #pragma unroll
-  for (int e = 0; e < 4; e++) { c[e] = h[lane * 4 + e]; rk[e] = 0; }
-  for (int o = 0; o < 256; o++) {
-    uint32_t x = h[o];
+  for (int k = 2; k <= 256; k <<= 1) {
 #pragma unroll
-    for (int e = 0; e < 4; e++) rk[e] += (x < c[e]) || (x == c[e] && o < lane * 4 + e);
-  }
-  __syncthreads();
-  // h is reused as the sorted array
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      if (j >= 64) {
 #pragma unroll
-  for (int e = 0; e < 4; e++) h[rk[e]] = c[e];
-  __syncthreads();
-  uint64_t cost = 0;
-  if (lane == 0) {
-    int i = 0;
-    while (i < 256 && h[i] == 0) i++;
-    int m = 256 - i;
-    if (m == 1) {
-      cost = h[i];
-    } else if (m > 1) {
-      int qh = 0, qt = 0;
-      for (int step = 0; step < m - 1; step++) {
-        uint64_t ab[2];
-        for (int z = 0; z < 2; z++) {
-          bool take_leaf = i < 256 && (qh == qt || (uint64_t)h[i] <= q[qh]);
-          ab[z] = take_leaf ? (uint64_t)h[i++] : q[qh++];
+        for (int R = 0; R < 4; R++) {
+          if (R & (j >> 6)) continue;
+          const int R2 = R ^ (j >> 6);
+          const bool up = ((64 * R + lane) & k) == 0;
+          const uint32_t lo = min(v[R], v[R2]), hi = max(v[R], v[R2]);
+          v[R] = up ? lo : hi;
+          v[R2] = up ? hi : lo;
         }
-        uint64_t wsum = ab[0] + ab[1];
-        cost += wsum;
-        q[qt++] = wsum;
+      } else {
+#pragma unroll
+        for (int R = 0; R < 4; R++) {
+          const int e = 64 * R + lane;
+          const uint32_t o = (uint32_t)__shfl_xor((int)v[R], j, 64);
+          const bool up = (e & k) == 0, lower = (e & j) == 0;
+          v[R] = (lower == up) ? min(v[R], o) : max(v[R], o);
+        }
       }
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t pick4(const uint32_t (&v)[4], int r) {
+  return r == 0 ? v[0] : (r == 1 ? v[1] : (r == 2 ? v[2] : v[3]));
+}
+
+// Optimal Huffman cost of a byte histogram (256 counts in LDS, one
+// wavefront): with the leaves sorted, merge the two lightest of (next leaf,
+// next internal node) until one node is left; the cost is the sum of the
+// merged weights (two-queue construction).  Leaves and internal nodes stay
+// in registers, 64 to a register; the merge runs on uniform indices and
+// reads one lane of the current block with readlane.  Counts and their
+// total are below 2^32.
+__device__ uint64_t huffman_cost_wave(const uint32_t *h, int lane) {
+  uint32_t v[4];
+#pragma unroll
+  for (int R = 0; R < 4; R++) v[R] = h[64 * R + lane];
+  wave_sort256(v, lane);
+  int i = 0;
+#pragma unroll
+  for (int R = 0; R < 4; R++) i += __popcll(__ballot(v[R] == 0u));
+  const int m = 256 - i;
+  if (m <= 0) return 0;
+  if (m == 1) return (uint32_t)__builtin_amdgcn_readlane((int)pick4(v, i >> 6), i & 63);
+  // lv: block of leaf i; qw: block being written (node qt); qr: block of
+  // node qh when that is an older block; done: finished node blocks
+  uint32_t lv = pick4(v, i >> 6), qw = 0u, qr = 0u;
+  uint32_t done[4] = {0u, 0u, 0u, 0u};
+  int qh = 0, qt = 0;
+  uint64_t cost = 0;
+  for (int step = 0; step < m - 1; step++) {
+    uint32_t ab[2];
+#pragma unroll
+    for (int z = 0; z < 2; z++) {
+      const uint32_t lf = (uint32_t)__builtin_amdgcn_readlane((int)lv, i & 63);
+      const uint32_t nw = (uint32_t)__builtin_amdgcn_readlane((int)qw, qh & 63);
+      const uint32_t nr = (uint32_t)__builtin_amdgcn_readlane((int)qr, qh & 63);
+      const uint32_t nd = ((qh ^ qt) >> 6) == 0 ? nw : nr;
+      const bool take_leaf = i < 256 && (qh == qt || lf <= nd);
+      ab[z] = take_leaf ? lf : nd;
+      if (take_leaf) {
+        i++;
+        if ((i & 63) == 0 && i < 256) lv = pick4(v, i >> 6);
+      } else {
+        qh++;
+        if ((qh & 63) == 0) qr = pick4(done, qh >> 6);
+      }
+    }
+    const uint32_t wsum = ab[0] + ab[1];
+    cost += wsum;
+    qw = lane == (qt & 63) ? wsum : qw;
+    qt++;
+    if ((qt & 63) == 0) {
+      const int b = (qt >> 6) - 1;
+      done[0] = b == 0 ? qw : done[0];
+      done[1] = b == 1 ? qw : done[1];
+      done[2] = b == 2 ? qw : done[2];
+      done[3] = b == 3 ? qw : done[3];
+      if ((qh >> 6) == b) qr = qw;
     }
   }
   return cost;
@@ -1050,22 +1115,33 @@ __device__ uint64_t huffman_cost_wave(uint32_t *h, uint64_t *q, int lane) {
 // Whole-frame totals and the Huffman size; one 256-thread block per frame.
 __device__ void finish_frame(const FrameDev &f, int kind, const Mat12 &M, int hasM) {
   __shared__ uint32_t h[4][256];
-  __shared__ uint64_t q[4][256];
   __shared__ uint32_t st[PC_STRIP_STATS];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < 1024; e += 256) {
-    uint32_t sum = 0;
-    for (int r = 0; r < f.TR; r++) sum += f.strip[(int64_t)r * PC_STRIP_WORDS + e];
-    h[e >> 8][e & 255] = sum;
-  }
-  if (tid < PC_STRIP_STATS) {
-    uint32_t sum = 0;
-    for (int r = 0; r < f.TR; r++) {
-      uint32_t v = f.strip[(int64_t)r * PC_STRIP_WORDS + 1024 + tid];
-      sum = (tid == PC_SS_STATUS) ? (sum | v) : sum + v;
+  const int tid = strip_tid();
+  // strip sums: eight strips' loads in flight per thread and entry
+  const int TR = f.TR;
+  const __attribute__((address_space(1))) uint32_t *ss = (const __attribute__((address_space(1))) uint32_t *)f.strip;
+  uint32_t hs[4] = {0u, 0u, 0u, 0u}, sts = 0u;
+  for (int r0 = 0; r0 < TR; r0 += 8) {
+    uint32_t x[8][4], y[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+      const int r = r0 + k < TR ? r0 + k : r0;       // in range; repeats are masked below
+      const int64_t base = (int64_t)r * PC_STRIP_WORDS;
+#pragma unroll
+      for (int e = 0; e < 4; e++) x[k][e] = ss[base + tid + 256 * e];
+      y[k] = tid < PC_STRIP_STATS ? ss[base + 1024 + tid] : 0u;
     }
-    st[tid] = sum;
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+      if (r0 + k >= TR) break;
+#pragma unroll
+      for (int e = 0; e < 4; e++) hs[e] += x[k][e];
+      sts = (tid == PC_SS_STATUS) ? (sts | y[k]) : sts + y[k];
+    }
   }
+#pragma unroll
+  for (int e = 0; e < 4; e++) h[e][tid] = hs[e];
+  if (tid < PC_STRIP_STATS) st[tid] = sts;
   __syncthreads();
   const int wv = tid >> 6, lane = tid & 63;
   // stream byte counts
@@ -1073,7 +1149,7 @@ __device__ void finish_frame(const FrameDev &f, int kind, const Mat12 &M, int ha
   for (int o = lane; o < 256; o += 64) nbytes += h[wv][o];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) nbytes += __shfl_xor(nbytes, o, 64);
-  uint64_t bits = huffman_cost_wave(h[wv], q[wv], lane);
+  uint64_t bits = huffman_cost_wave(h[wv], lane);
   __shared__ uint64_t sb[4], sc[4];
   if (lane == 0) { sb[wv] = nbytes; sc[wv] = bits; }
   __syncthreads();

@@ -280,8 +280,8 @@ pc_status pc_net_adam(pc_ctx *ctx, float *params, const float *grad, float *m, f
  * the predicted frames' strips, then every frame's size.  Each strip's work
  * item builds its strip's range image in LDS from its bin (nearest point
  * wins) -- the range images never go through device memory unless asked
- * for.  Encoding work is pulled in (frame, strip) items from an atomic queue
- * by persistent work-groups.  Each frame's stream equals what pc_project +
+ * for.  Predicted-frame strips are pulled in (frame, strip) items from an
+ * atomic queue by persistent work-groups.  Each frame's stream equals what pc_project +
  * pc_fit_key / pc_encode_pred give for it. */
 typedef struct {
   const float *xyz;          /* device, n x 3 FP32 points in the frame's own coordinates */
@@ -297,7 +297,8 @@ typedef struct {
 } pc_frame_desc;
 
 typedef struct {
-  int32_t persistent;        /* 1: persistent work-groups pull strips from an atomic queue; 0: a work-group per strip */
+  int32_t persistent;        /* 1: persistent work-groups pull predicted-frame strips from an atomic queue;
+                                0: a work-group per strip (key-frame strips always run this way) */
   int32_t graph;             /* 1: capture the batch in a HIP graph at the first run and replay it afterwards */
   int32_t blocks_per_cu;     /* persistent grid = CUs * this (at most one work-group per item); 0 = 4 */
   int32_t pad;

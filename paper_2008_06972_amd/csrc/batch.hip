@@ -309,13 +309,17 @@ static size_t group_smem(int th, int tw, int W, bool pred) {
 }
 
 // All launches of one batch, in order; mark(kind) follows each (PC_LAUNCH_*).
+// Key-frame groups always run a work-group per strip: they are a tenth of
+// the strips, and their persistent form holds more registers than the
+// three-work-groups-per-CU budget allows.
 static hipError_t launch_group(BatchPlan &P, int gi, hipStream_t st) {
   const Group &g = P.groups[gi];
-  const void *fn = group_fn(g, P.persistent != 0);
+  const bool persistent = P.persistent != 0 && g.kind == 1;
+  const void *fn = group_fn(g, persistent);
   const int2 *items = P.d_items + g.first;
   int nitems = g.count;
   int *counter = P.d_counters + gi;
-  if (P.persistent) {
+  if (persistent) {
     void *args[] = {(void *)&P.d_desc, (void *)&items, (void *)&nitems, (void *)&counter};
     return hipLaunchKernel(fn, dim3(g.grid), dim3(kBlock), args, g.smem, st);
   }

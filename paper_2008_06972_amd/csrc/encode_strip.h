@@ -170,7 +170,7 @@ __device__ __forceinline__ void f32_bytes(uint32_t *hist, float x) {
 
 // --------------------------------------------------------- phase 0: loads
 template <int TH, int TW>
-__device__ void strip_init(StripSmem<TH, TW> &sm, const SensorDev &s, int tr) {
+__device__ __forceinline__ void strip_init(StripSmem<TH, TW> &sm, const SensorDev &s, int tr) {
   const int tid = strip_tid();
   for (int q = tid; q < 512; q += kBlock) sm.hist[q] = 0;
   if (tid < 32) sm.misc[tid] = 0;
@@ -262,6 +262,8 @@ __device__ __forceinline__ TileRows<TH, TW> tile_at(const StripSmem<TH, TW> &sm,
   TileRows<TH, TW> T;
   T.rp = sm.r + tc * StripSmem<TH, TW>::N;
   T.sw = tile_swizzle(tc, StripSmem<TH, TW>::UNITS);
+  T.i0 = 0;
+  T.i1 = TH;
   T.ce = sm.ce;
   T.se = sm.se;
   typedef float v4f __attribute__((ext_vector_type(4)));
@@ -308,23 +310,32 @@ __device__ __forceinline__ void list_push(StripSmem<TH, TW> &sm, int q, int TC, 
 // The fits of one iteration for the tiles on list q (n of them, every thread
 // having read n after the last barrier): (a) FP32 fits, the near-degenerate
 // ones gathered on the FP64 list; (b) FP64 fits of those, on_degenerate(tc)
-// for a degenerate scatter.  Each plane goes to sm.plane and, in the same
-// thread, to keep(T, tc, P) (the kept-pixel test of the caller).  Ends after
-// a barrier with list q's and the FP64 list's counters cleared.
-template <int TH, int TW, class OnDegenerate, class Keep>
-__device__ void fit_pass(StripSmem<TH, TW> &sm, int q, int n, int TC, int &fits, int &fp64, OnDegenerate on_degenerate,
-                         Keep keep) {
-  const int tid = strip_tid();
+// for a degenerate scatter.  Each plane goes to sm.plane and, with the
+// pixels it reproduces, to keep(tc, P, S2).  LANES neighbouring lanes share
+// a tile, TH / LANES of its rows each (short lists, where one thread per
+// tile would leave most of the work-group idle and the iteration bound by
+// one thread's latency).  Ends after a barrier with list q's and the FP64
+// list's counters cleared.
+template <int TH, int TW, int LANES, class OnDegenerate, class Keep>
+__device__ __forceinline__ void fit_pass(StripSmem<TH, TW> &sm, const EncParams &p, int q, int n, int TC, int &fits, int &fp64,
+                         OnDegenerate on_degenerate, Keep keep) {
+  typedef typename LaneGroup<LANES>::type Red;
+  const int tid = strip_tid(), sub = tid & (LANES - 1);
   const int16_t *L = sm.list(q, TC);
   const uint64_t *cur = sm.cur();
-  for (int e = tid; e < n; e += kBlock) {
+  for (int e = tid / LANES; e < n; e += kBlock / LANES) {
     const int tc = L[e];
     TileRows<TH, TW> T = tile_at<TH, TW>(sm, tc);
     Plane P{0, 0.f, 0.f, 0.f};
+    T.i0 = sub * (TH / LANES);
+    T.i1 = T.i0 + TH / LANES;
+    const bool ok = fit_plane_f32(T, cur[tc], P, Red{});
+    const uint64_t S2 = ok ? inliers(T, P, p.eps, Red{}) : 0ull;
+    if (sub != 0) continue;
     fits++;
-    if (fit_plane_f32(T, cur[tc], P)) {
+    if (ok) {
       sm.plane[tc] = pack_plane(P);
-      keep(T, tc, P);
+      keep(tc, P, S2);
     } else {
       list_push<TH, TW>(sm, 2, TC, tc);
     }
@@ -340,7 +351,7 @@ __device__ void fit_pass(StripSmem<TH, TW> &sm, int q, int n, int TC, int &fits,
     fp64++;
     if (fit_plane_f64(T, cur[tc], P)) {
       sm.plane[tc] = pack_plane(P);
-      keep(T, tc, P);
+      keep(tc, P, inliers(T, P, p.eps));
     } else {
       on_degenerate(tc);
     }
@@ -354,7 +365,7 @@ __device__ void fit_pass(StripSmem<TH, TW> &sm, int q, int n, int TC, int &fits,
 // converged when the kept set stops changing; accepted when at least
 // need(n) pixels are kept.  Results in plane/omask/stat/iters.
 template <int TH, int TW, class Take>
-__device__ void own_fits(StripSmem<TH, TW> &sm, const EncParams &p, int TC, Take take, int &fits, int &fp64) {
+__device__ __forceinline__ void own_fits(StripSmem<TH, TW> &sm, const EncParams &p, int TC, Take take, int &fits, int &fp64) {
   const int tid = strip_tid();
   uint64_t *cur = sm.cur();
   for (int tc = tid; tc < TC; tc += kBlock) {
@@ -373,18 +384,15 @@ __device__ void own_fits(StripSmem<TH, TW> &sm, const EncParams &p, int TC, Take
   int n = sm.misc[M_LIST];
   for (int it = 1; it <= p.max_iter && n > 0; it++) {
     const int q = (it - 1) & 1;
-    fit_pass<TH, TW>(
-        sm, q, n, TC, fits, fp64,
-        [&](int tc) {
-          sm.iters[tc] = (uint8_t)it;
-          sm.stat[tc] = ST_DEGENERATE;
-          sm.omask[tc] = 0;
-        },
-        [&](const TileRows<TH, TW> &T, int tc, const Plane &P) {
+    auto degenerate = [&](int tc) {
+      sm.iters[tc] = (uint8_t)it;
+      sm.stat[tc] = ST_DEGENERATE;
+      sm.omask[tc] = 0;
+    };
+    auto kept = [&](int tc, const Plane &P, uint64_t S2) {
           // kept pixels, convergence
           sm.iters[tc] = (uint8_t)it;
           const uint64_t S = cur[tc];
-          const uint64_t S2 = inliers(T, P, p.eps);
           if (S2 != S && __popcll(S2) < p.min_pts) {
             sm.stat[tc] = ST_FAILED;
             sm.omask[tc] = 0;
@@ -397,7 +405,10 @@ __device__ void own_fits(StripSmem<TH, TW> &sm, const EncParams &p, int TC, Take
           } else {
             sm.stat[tc] = __popcll(S2) >= need_of(p, sm.nv[tc]) ? ST_ACCEPTED : ST_REJECTED;
           }
-        });
+    };
+    if (n <= kBlock / 4) fit_pass<TH, TW, 4>(sm, p, q, n, TC, fits, fp64, degenerate, kept);
+    else if (n <= kBlock / 2) fit_pass<TH, TW, 2>(sm, p, q, n, TC, fits, fp64, degenerate, kept);
+    else fit_pass<TH, TW, 1>(sm, p, q, n, TC, fits, fp64, degenerate, kept);
     n = sm.misc[M_LIST + (q ^ 1)];
   }
   __syncthreads();
@@ -434,7 +445,7 @@ __device__ __forceinline__ float seed_offset(const Tile &T, const Plane &Q) {
 // iteration; seed state in sm.elig (key frames do not use it otherwise):
 // 0 no seed, 1 accepted, 2 fell back to the plain fit.
 template <int TH, int TW>
-__device__ void seeded_fits(StripSmem<TH, TW> &sm, const EncParams &p, int TC, const float4 *__restrict__ seed,
+__device__ __forceinline__ void seeded_fits(StripSmem<TH, TW> &sm, const EncParams &p, int TC, const float4 *__restrict__ seed,
                             int &fits, int &fp64) {
   const int tid = strip_tid();
   uint64_t *cur = sm.cur();
@@ -467,10 +478,9 @@ __device__ void seeded_fits(StripSmem<TH, TW> &sm, const EncParams &p, int TC, c
   __syncthreads();
   const int n = sm.misc[M_LIST];
   if (n > 0)
-    fit_pass<TH, TW>(
-        sm, 0, n, TC, fits, fp64, [&](int tc) { sm.elig[tc] = 2; },
-        [&](const TileRows<TH, TW> &T, int tc, const Plane &P) {
-          const uint64_t S2 = inliers(T, P, p.eps);
+    fit_pass<TH, TW, 1>(
+        sm, p, 0, n, TC, fits, fp64, [&](int tc) { sm.elig[tc] = 2; },
+        [&](int tc, const Plane &P, uint64_t S2) {
           if (__popcll(S2) >= need_of(p, sm.nv[tc])) {
             sm.omask[tc] = S2;
             sm.stat[tc] = ST_ACCEPTED;
@@ -491,12 +501,47 @@ __device__ void seeded_fits(StripSmem<TH, TW> &sm, const EncParams &p, int TC, c
   __syncthreads();
 }
 
+// One temporal-fit iteration over list q (n tiles), LANES lanes per tile
+// as in fit_pass: the offset through the kept pixels, the pixels it
+// reproduces, convergence.
+template <int TH, int TW, int LANES>
+__device__ __forceinline__ void temporal_pass(StripSmem<TH, TW> &sm, const EncParams &p, int q, int n, int TC, int it) {
+  typedef typename LaneGroup<LANES>::type Red;
+  const int tid = strip_tid(), sub = tid & (LANES - 1);
+  const int16_t *L = sm.list(q, TC);
+  uint64_t *cur = sm.cur();
+  for (int e = tid / LANES; e < n; e += kBlock / LANES) {
+    const int tc = L[e];
+    TileRows<TH, TW> T = tile_at<TH, TW>(sm, tc);
+    T.i0 = sub * (TH / LANES);
+    T.i1 = T.i0 + TH / LANES;
+    Plane P = unpack_plane(sm.plane[tc]);
+    const uint64_t S = cur[tc];
+    P.c = temporal_offset(T, P, S, Red{});
+    const uint64_t S2 = inliers(T, P, p.eps, Red{});
+    if (sub != 0) continue;
+    sm.iters[tc] = (uint8_t)it;
+    sm.plane[tc] = pack_plane(P);
+    if (S2 != S && __popcll(S2) < p.min_pts) {     // failed: stat stays 1
+      sm.omask[tc] = 0;
+      continue;
+    }
+    sm.omask[tc] = S2;
+    if (S2 != S && it < p.max_iter) {
+      cur[tc] = S2;
+      list_push<TH, TW>(sm, q ^ 1, TC, tc);
+    } else {
+      sm.stat[tc] = __popcll(S2) >= need_of(p, sm.nv[tc]) ? 2 : 1;
+    }
+  }
+}
+
 // Temporal fits (Sec. III-D) of the tiles whose key tile is plane coded:
 // the key run's normal (k, a, b) is held and only the offset varies, with
 // the same iteration, kept-pixel test and acceptance as the own fits.
 // stat: 2 accepted, 1 not, 0 no key plane.  Results in plane/omask/stat/iters.
 template <int TH, int TW>
-__device__ void temporal_fits(StripSmem<TH, TW> &sm, const FrameDev &key, const EncParams &p, int tr, int TC) {
+__device__ __forceinline__ void temporal_fits(StripSmem<TH, TW> &sm, const FrameDev &key, const EncParams &p, int tr, int TC) {
   const int tid = strip_tid();
   uint64_t *cur = sm.cur();
   for (int tc = tid; tc < TC; tc += kBlock) {
@@ -521,28 +566,9 @@ __device__ void temporal_fits(StripSmem<TH, TW> &sm, const FrameDev &key, const 
   int n = sm.misc[M_LIST];
   for (int it = 1; it <= p.max_iter && n > 0; it++) {
     const int q = (it - 1) & 1;
-    const int16_t *L = sm.list(q, TC);
-    for (int e = tid; e < n; e += kBlock) {
-      const int tc = L[e];
-      sm.iters[tc] = (uint8_t)it;
-      TileRows<TH, TW> T = tile_at<TH, TW>(sm, tc);
-      Plane P = unpack_plane(sm.plane[tc]);
-      const uint64_t S = cur[tc];
-      P.c = temporal_offset(T, P, S);
-      sm.plane[tc] = pack_plane(P);
-      const uint64_t S2 = inliers(T, P, p.eps);
-      if (S2 != S && __popcll(S2) < p.min_pts) {     // failed: stat stays 1
-        sm.omask[tc] = 0;
-        continue;
-      }
-      sm.omask[tc] = S2;
-      if (S2 != S && it < p.max_iter) {
-        cur[tc] = S2;
-        list_push<TH, TW>(sm, q ^ 1, TC, tc);
-      } else {
-        sm.stat[tc] = __popcll(S2) >= need_of(p, sm.nv[tc]) ? 2 : 1;
-      }
-    }
+    if (n <= kBlock / 4) temporal_pass<TH, TW, 4>(sm, p, q, n, TC, it);
+    else if (n <= kBlock / 2) temporal_pass<TH, TW, 2>(sm, p, q, n, TC, it);
+    else temporal_pass<TH, TW, 1>(sm, p, q, n, TC, it);
     __syncthreads();
     n = sm.misc[M_LIST + (q ^ 1)];
     if (tid == 0) sm.misc[M_LIST + q] = 0;    // every thread read its count before the pass
@@ -580,7 +606,7 @@ __device__ __forceinline__ uint64_t inliers_at(const StripSmem<TH, TW> &sm, int 
 // 64 / (TH * TW) tiles from tile t on (lane = pixel); returns how many more
 // tiles join.
 template <int TH, int TW, class Allowed>
-__device__ int extend_beyond(const StripSmem<TH, TW> &sm, const EncParams &p, const Plane &P, int s, int t, int TC,
+__device__ __forceinline__ int extend_beyond(const StripSmem<TH, TW> &sm, const EncParams &p, const Plane &P, int s, int t, int TC,
                              Allowed allowed) {
   constexpr int N = TH * TW, TPW = 64 / N;
   const int lane = strip_tid() & 63, w = lane / N, j = lane % N, i = j / TW, k = j % TW;
@@ -607,6 +633,27 @@ __device__ int extend_beyond(const StripSmem<TH, TW> &sm, const EncParams &p, co
   return added;
 }
 
+// One level d of the reach: does the plane of start s (list q, n starts)
+// reproduce tile s + d?  LANES lanes per test as in fit_pass.
+template <int TH, int TW, int LANES, class Allowed, class PlaneOf>
+__device__ __forceinline__ void reach_pass(StripSmem<TH, TW> &sm, const EncParams &p, int q, int n, int TC, int d,
+                                           Allowed allowed, PlaneOf plane_of) {
+  typedef typename LaneGroup<LANES>::type Red;
+  const int tid = strip_tid(), sub = tid & (LANES - 1);
+  const int16_t *L = sm.list(q, TC);
+  for (int e = tid / LANES; e < n; e += kBlock / LANES) {
+    const int s = L[e], t = s + d;
+    if (t >= TC || !allowed(s, t)) continue;
+    TileRows<TH, TW> T = tile_at<TH, TW>(sm, t);
+    T.i0 = sub * (TH / LANES);
+    T.i1 = T.i0 + TH / LANES;
+    const uint64_t m = inliers(T, plane_of(s), p.eps, Red{});
+    if (sub != 0 || __popcll(m) < need_of(p, sm.nv[t])) continue;
+    sm.reach[s] = (uint8_t)d;
+    if (d < kReach) list_push<TH, TW>(sm, q ^ 1, TC, s);
+  }
+}
+
 // Runs of one pass.  Every tile that may start a run (start(tc)) measures
 // its reach -- level by level over a compacted list of the starts still
 // extending, so no thread idles on a neighbour's longer run -- and notes
@@ -618,7 +665,7 @@ __device__ int extend_beyond(const StripSmem<TH, TW> &sm, const EncParams &p, co
 // run plane reproduces.  Writes rs/rl, runof (run index, -1 outside runs,
 // for tiles with member(tc)) and fmask; returns the number of runs.
 template <int TH, int TW, class Member, class Start, class Allowed, class PlaneOf, class MaskOf>
-__device__ int grow_runs(StripSmem<TH, TW> &sm, const EncParams &p, int TC, Member member, Start start,
+__device__ __forceinline__ int grow_runs(StripSmem<TH, TW> &sm, const EncParams &p, int TC, Member member, Start start,
                          Allowed allowed, PlaneOf plane_of, MaskOf own_mask, int *nr_out) {
   const int tid = strip_tid(), nw = (TC + 63) >> 6;
   for (int w = tid >> 6; w < nw; w += kBlock / 64) {
@@ -638,14 +685,9 @@ __device__ int grow_runs(StripSmem<TH, TW> &sm, const EncParams &p, int TC, Memb
   int n = sm.misc[M_LIST];
   for (int d = 1; d <= kReach && n > 0; d++) {
     const int q = (d - 1) & 1;
-    const int16_t *L = sm.list(q, TC);
-    for (int e = tid; e < n; e += kBlock) {
-      const int s = L[e], t = s + d;
-      if (t >= TC || !allowed(s, t)) continue;
-      if (__popcll(inliers_at<TH, TW>(sm, t, plane_of(s), p.eps)) < need_of(p, sm.nv[t])) continue;
-      sm.reach[s] = (uint8_t)d;
-      if (d < kReach) list_push<TH, TW>(sm, q ^ 1, TC, s);
-    }
+    if (n <= kBlock / 4) reach_pass<TH, TW, 4>(sm, p, q, n, TC, d, allowed, plane_of);
+    else if (n <= kBlock / 2) reach_pass<TH, TW, 2>(sm, p, q, n, TC, d, allowed, plane_of);
+    else reach_pass<TH, TW, 1>(sm, p, q, n, TC, d, allowed, plane_of);
     __syncthreads();
     n = sm.misc[M_LIST + (q ^ 1)];
     if (tid == 0) sm.misc[M_LIST + q] = 0;    // every thread read its count before the pass
@@ -700,7 +742,7 @@ __device__ int grow_runs(StripSmem<TH, TW> &sm, const EncParams &p, int TC, Memb
 // gap to the previous run's end, varint of the length, then the run's own
 // bytes (emit), and the count of runs of the row.
 template <int TH, int TW, class EmitRun>
-__device__ void run_bytes(StripSmem<TH, TW> &sm, int nr, EmitRun emit) {
+__device__ __forceinline__ void run_bytes(StripSmem<TH, TW> &sm, int nr, EmitRun emit) {
   for (int q = strip_tid(); q < nr; q += kBlock) {
     int prev_end = q ? sm.rs[q - 1] + sm.rl[q - 1] : 0;
     varint_bytes(sm.hist, (uint32_t)(sm.rs[q] - prev_end));
@@ -714,7 +756,7 @@ __device__ void run_bytes(StripSmem<TH, TW> &sm, int nr, EmitRun emit) {
 // (`pred`), only tiles with elig != 0 take part; the others belong to
 // temporal runs and break spatial runs.
 template <int TH, int TW>
-__device__ void grow_spatial(StripSmem<TH, TW> &sm, const EncParams &p, const FrameDev &f, int tr, bool pred) {
+__device__ __forceinline__ void grow_spatial(StripSmem<TH, TW> &sm, const EncParams &p, const FrameDev &f, int tr, bool pred) {
   const int TC = f.TC, tid = strip_tid();
   auto member = [&](int tc) { return !pred || sm.elig[tc] != 0; };
   const int nr = grow_runs<TH, TW>(
@@ -753,7 +795,7 @@ __device__ void grow_spatial(StripSmem<TH, TW> &sm, const EncParams &p, const Fr
 // stays the same and (key normal, c' of the run start) reproduces the
 // tile.  Tiles not covered become eligible for the spatial pass.
 template <int TH, int TW>
-__device__ void grow_temporal(StripSmem<TH, TW> &sm, const EncParams &p, const FrameDev &f, int tr) {
+__device__ __forceinline__ void grow_temporal(StripSmem<TH, TW> &sm, const EncParams &p, const FrameDev &f, int tr) {
   const int TC = f.TC, T = f.T, tid = strip_tid();
   const int nr = grow_runs<TH, TW>(
       sm, p, TC, [](int) { return true; }, [&](int tc) { return sm.stat[tc] == 2; },
@@ -778,7 +820,7 @@ __device__ void grow_temporal(StripSmem<TH, TW> &sm, const EncParams &p, const F
 // ----------------------------------------------------- phase 3: residuals
 // Block-wide exclusive scan of sm.cnt()[0 .. n) in place; returns the total.
 template <int TH, int TW>
-__device__ uint32_t block_exclusive_scan(StripSmem<TH, TW> &sm, int n) {
+__device__ __forceinline__ uint32_t block_exclusive_scan(StripSmem<TH, TW> &sm, int n) {
   const int tid = strip_tid();
   const int per = (n + kBlock - 1) / kBlock;
   const int b = tid * per, e = min(n, b + per);
@@ -824,7 +866,7 @@ __device__ __forceinline__ uint64_t pext64(uint64_t m, uint64_t sel) {
 }
 
 template <int TH, int TW>
-__device__ void residuals_and_streams(StripSmem<TH, TW> &sm, const SensorDev &s,
+__device__ __forceinline__ void residuals_and_streams(StripSmem<TH, TW> &sm, const SensorDev &s,
                                       const EncParams &p, const FrameDev &f, int tr, int fits, int fp64) {
   constexpr int N = TH * TW;
   const int TC = f.TC, W = s.W, tid = strip_tid();

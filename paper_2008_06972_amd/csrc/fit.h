@@ -247,6 +247,7 @@ struct TileRows {
   static constexpr int TWc = TW;
   const float *rp;           // tile base: element j at rp[4 * ((j / 4) ^ sw) + j % 4]
   int sw;
+  int i0, i1;                // rows this lane visits in each(): all, or its share when lanes split a tile
   const float *ce, *se;      // TH row tables (LDS)
   float ca[TW], sa[TW];      // column tables of this tile (registers)
 
@@ -278,7 +279,7 @@ struct TileRows {
   __device__ __forceinline__ void each(F f) const {
     asm volatile("" ::: "memory");
 #pragma unroll 1
-    for (int i = 0; i < TH; i++) {
+    for (int i = i0; i < i1; i++) {
       float r[TW];
       row(i, r);
       const float cei = ce[i], sei = se[i];
@@ -290,12 +291,45 @@ struct TileRows {
 
 __device__ __forceinline__ float bitw(uint64_t S, int j) { return (float)((S >> j) & 1ull); }
 
+// Combining the partial results of the lanes that share a tile: one lane
+// (nothing to combine), or two or four neighbouring lanes, each holding some
+// of the tile's rows, combined by butterfly DPP moves so that every lane of
+// the group ends with the same bits.
+struct LaneOne {
+  __device__ __forceinline__ float sum(float x) const { return x; }
+  __device__ __forceinline__ uint32_t bor(uint32_t x) const { return x; }
+};
+struct LanePair {
+  __device__ __forceinline__ static int dpp(int x) { return __builtin_amdgcn_update_dpp(x, x, 0xB1, 0xF, 0xF, false); }
+  __device__ __forceinline__ float sum(float x) const { return x + __int_as_float(dpp(__float_as_int(x))); }
+  __device__ __forceinline__ uint32_t bor(uint32_t x) const { return x | (uint32_t)dpp((int)x); }
+};
+struct LaneQuad {
+  template <int Ctrl>
+  __device__ __forceinline__ static int dpp(int x) {
+    return __builtin_amdgcn_update_dpp(x, x, Ctrl, 0xF, 0xF, false);
+  }
+  __device__ __forceinline__ float sum(float x) const {
+    x = x + __int_as_float(dpp<0xB1>(__float_as_int(x)));      // quad_perm(1, 0, 3, 2)
+    return x + __int_as_float(dpp<0x4E>(__float_as_int(x)));   // quad_perm(2, 3, 0, 1)
+  }
+  __device__ __forceinline__ uint32_t bor(uint32_t x) const {
+    x |= (uint32_t)dpp<0xB1>((int)x);
+    return x | (uint32_t)dpp<0x4E>((int)x);
+  }
+};
+
 // Pixels of the tile that plane P reproduces within eps (the decoder's
 // test).  Branch-free over the pixels with the one-ulp reciprocal; the few
 // pixels whose |t - r| lies within rounding reach of eps are decided
 // afterwards with the correctly rounded division.
-template <class Tile>
-__device__ __forceinline__ uint64_t inliers(const Tile &T, const Plane &P, float eps) {
+template <int LANES> struct LaneGroup;
+template <> struct LaneGroup<1> { typedef LaneOne type; };
+template <> struct LaneGroup<2> { typedef LanePair type; };
+template <> struct LaneGroup<4> { typedef LaneQuad type; };
+
+template <class Tile, class Red = LaneOne>
+__device__ __forceinline__ uint64_t inliers(const Tile &T, const Plane &P, float eps, Red red = Red{}) {
   const bool isx = P.k == 0, isz = P.k == 2;
   uint32_t lo = 0, hi = 0, ulo = 0, uhi = 0;
   T.each([&](int j, float r, const Dir &d) {
@@ -324,7 +358,7 @@ __device__ __forceinline__ uint64_t inliers(const Tile &T, const Plane &P, float
     const int i = j / Tile::TWc, k = j % Tile::TWc;
     if (reproduces_exact(P.c, plane_den(P, T.dir_at(i, k)), T.at(j), eps)) m |= 1ull << j;
   }
-  return m;
+  return ((uint64_t)red.bor((uint32_t)(m >> 32)) << 32) | red.bor((uint32_t)m);
 }
 
 // FP64 least squares on the exact products r*d: two-pass centring, Jacobi.
@@ -369,8 +403,8 @@ __device__ __forceinline__ bool fit_plane_f64(const Tile &T, uint64_t S, Plane &
 // Returns false when FP32 cannot decide: the two smallest eigenvalues are
 // within kNearDegenerate of the largest (the caller then fits in FP64).
 // Pixels outside S enter every sum with weight 0 (no branches).
-template <class Tile>
-__device__ __forceinline__ bool fit_plane_f32(const Tile &T, uint64_t S, Plane &P) {
+template <class Tile, class Red = LaneOne>
+__device__ __forceinline__ bool fit_plane_f32(const Tile &T, uint64_t S, Plane &P, Red red = Red{}) {
   float n = (float)__popcll(S);
   // shift: the first pixel in S
   const int j0 = __ffsll((long long)S) - 1;
@@ -387,6 +421,9 @@ __device__ __forceinline__ bool fit_plane_f32(const Tile &T, uint64_t S, Plane &
     cxx = fmaf(ex, ex, cxx); cxy = fmaf(ex, ey, cxy); cxz = fmaf(ex, ez, cxz);
     cyy = fmaf(ey, ey, cyy); cyz = fmaf(ey, ez, cyz); czz = fmaf(ez, ez, czz);
   });
+  sx = red.sum(sx); sy = red.sum(sy); sz = red.sum(sz);
+  cxx = red.sum(cxx); cxy = red.sum(cxy); cxz = red.sum(cxz);
+  cyy = red.sum(cyy); cyz = red.sum(cyz); czz = red.sum(czz);
   const float in = frcp(n);
   const float ux0 = sx * in, uy0 = sy * in, uz0 = sz * in;
   cxx -= sx * ux0; cxy -= sx * uy0; cxz -= sx * uz0;
@@ -407,6 +444,9 @@ __device__ __forceinline__ bool fit_plane_f32(const Tile &T, uint64_t S, Plane &
     s11 = fmaf(e1, e1, s11); s12 = fmaf(e1, e2, s12); s13 = fmaf(e1, e3, s13);
     s22 = fmaf(e2, e2, s22); s23 = fmaf(e2, e3, s23); s33 = fmaf(e3, e3, s33);
   });
+  q1 = red.sum(q1); q2 = red.sum(q2); q3 = red.sum(q3);
+  s11 = red.sum(s11); s12 = red.sum(s12); s13 = red.sum(s13);
+  s22 = red.sum(s22); s23 = red.sum(s23); s33 = red.sum(s33);
   float u1 = q1 * in, u2 = q2 * in, u3 = q3 * in;    // rounding left in the mean
   s11 -= q1 * u1; s12 -= q1 * u2; s13 -= q1 * u3;
   s22 -= q2 * u2; s23 -= q2 * u3; s33 -= q3 * u3;
@@ -431,11 +471,11 @@ __device__ __forceinline__ int need_of(const EncParams &p, int n) { return p.nee
 
 // Offset of the key plane's stored form (normal held) through the pixels in
 // S: the mean of r * (d_k + a d_k1 + b d_k2) (Sec. III-D).
-template <class Tile>
-__device__ __forceinline__ float temporal_offset(const Tile &T, const Plane &Q, uint64_t S) {
+template <class Tile, class Red = LaneOne>
+__device__ __forceinline__ float temporal_offset(const Tile &T, const Plane &Q, uint64_t S, Red red = Red{}) {
   float sum = 0.f;
   T.each([&](int j, float r, const Dir &d) { sum = fmaf(r * bitw(S, j), plane_den(Q, d), sum); });
-  return sum / (float)__popcll(S);
+  return red.sum(sum) / (float)__popcll(S);
 }
 
 }  // namespace pcc

@@ -701,9 +701,12 @@ __device__ __forceinline__ int grow_runs(StripSmem<TH, TW> &sm, const EncParams 
     if (start(tc)) sm.nx[tc] = (int16_t)next_start(sm.acc, tc + 1 + sm.reach[tc], TC);
   __syncthreads();
   if (tid < 64) {
+    // the walk proper: only the chain of run starts; lane k % 64 holds
+    // run k's start and length until 64 runs are stored at once
     const int lane = tid;
     int nr = 0, s = next_start(sm.acc, 0, TC), win = -1;
     uint32_t note = 0;      // this lane's tile of the current window: reach | (nx & 0xffff) << 8
+    int my_s = 0, my_l = 0;
     while (s >= 0) {
       if ((s >> 6) != win) {
         win = s >> 6;
@@ -717,15 +720,28 @@ __device__ __forceinline__ int grow_runs(StripSmem<TH, TW> &sm, const EncParams 
         len += extend_beyond<TH, TW>(sm, p, plane_of(s), s, s + len, TC, allowed);
         nxt = next_start(sm.acc, s + len, TC);
       }
-      for (int q = lane; q < len; q += 64) sm.runof[s + q] = nr;
-      if (lane == 0) {
-        sm.rs[nr] = (int16_t)s;
-        sm.rl[nr] = (int16_t)len;
-      }
+      my_s = lane == (nr & 63) ? s : my_s;
+      my_l = lane == (nr & 63) ? len : my_l;
       nr++;
+      if ((nr & 63) == 0) {
+        sm.rs[nr - 64 + lane] = (int16_t)my_s;
+        sm.rl[nr - 64 + lane] = (int16_t)my_l;
+      }
       s = nxt;
     }
+    if (lane < (nr & 63)) {
+      sm.rs[(nr & ~63) + lane] = (int16_t)my_s;
+      sm.rl[(nr & ~63) + lane] = (int16_t)my_l;
+    }
     if (lane == 0) *nr_out = nr;
+  }
+  __syncthreads();
+  {
+    const int nr = *nr_out;
+    for (int k = tid; k < nr; k += kBlock) {
+      const int s0 = sm.rs[k], len = sm.rl[k];
+      for (int q = 0; q < len; q++) sm.runof[s0 + q] = k;
+    }
   }
   __syncthreads();
   for (int tc = tid; tc < TC; tc += kBlock) {
@@ -922,20 +938,31 @@ __device__ __forceinline__ void residuals_and_streams(StripSmem<TH, TW> &sm, con
     f.mask[t] = (sm.cls[tc] == CLS_SPATIAL || sm.cls[tc] == CLS_TEMPORAL) ? sm.fmask[tc] : 0ull;
     f.run_of[t] = sm.runof[tc];
   }
-  // block reductions of counters
+  // block reductions of counters: wavefront sums, one atomic per wavefront
   __shared__ int red[8];
   if (tid < 8) red[tid] = 0;
   __syncthreads();
-  int nvalid = 0, nc[4] = {0, 0, 0, 0};
+  int v[8] = {0, 0, 0, 0, 0, fits, fp64, (int)bad};
   for (int tc = tid; tc < TC; tc += kBlock) {
-    nvalid += sm.nv[tc];
-    nc[sm.cls[tc]]++;
+    const int cl = sm.cls[tc];
+    v[0] += sm.nv[tc];
+    v[1] += cl == 0;
+    v[2] += cl == 1;
+    v[3] += cl == 2;
+    v[4] += cl == 3;
   }
-  atomicAdd(&red[0], nvalid);
-  for (int c = 0; c < 4; c++) atomicAdd(&red[1 + c], nc[c]);
-  atomicAdd(&red[5], fits);
-  atomicAdd(&red[6], fp64);
-  if (bad) atomicOr(&red[7], 1);
+#pragma unroll
+  for (int c = 0; c < 8; c++) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[c] += __shfl_xor(v[c], o, 64);
+  }
+  if ((tid & 63) < 8) {
+    const int c = tid & 63;
+    int x = v[0];
+#pragma unroll
+    for (int q = 1; q < 8; q++) x = c == q ? v[q] : x;
+    atomicAdd(&red[c], x);       // red[7]: nonzero when any pixel was out of range
+  }
   __syncthreads();
   // OCC words (bit u % 32 of word (i * W + u) / 32: pixel (i, u) not
   // empty) from the ranges, to global and into the OCC histogram

@@ -38,6 +38,7 @@ namespace pcc {
 constexpr int kBinPts = 8;                 // points per thread in the binning passes
 constexpr int kBinBlock = 256;
 constexpr int kBinChunk = kBinPts * kBinBlock;
+constexpr size_t kCountTabMax = 32 * 1024;  // sensor tables up to this size go to LDS in the binning pass
 
 struct FrameDescDev {
   const float *xyz;
@@ -67,15 +68,30 @@ __global__ void k_batch_reset(int *a, int64_t n) {
   for (; i < n; i += stride) a[i] = 0;
 }
 
-// blocks [first[f], first[f+1]) belong to frame f; owner[b] = f
+// blocks [first[f], first[f+1]) belong to frame f; owner[b] = f.  With
+// LdsTab the sensor's cut tangents and edge vectors are first copied into
+// LDS (H + 1 + 2 W floats) and the row and column walks read them there.
+template <bool LdsTab>
 __global__ void __launch_bounds__(kBinBlock) k_batch_count(const FrameDescDev *__restrict__ d, const int *__restrict__ owner,
                                                            const int *__restrict__ first, int base) {
   __shared__ int hist[256];
+  extern __shared__ __align__(16) float tabs[];
   const int blk = base + blockIdx.x;
   const int fidx = __builtin_amdgcn_readfirstlane(owner[blk]);
   const FrameDescDev &D = d[fidx];
   const int th = D.p.th, thl = __ffs(th) - 1, TR = D.f.TR;     // tile heights are powers of two
   for (int t = threadIdx.x; t < TR; t += kBinBlock) hist[t] = 0;
+  const int H = D.s.H, W = D.s.W;
+  if (LdsTab) {
+    for (int t = threadIdx.x; t <= H; t += kBinBlock) tabs[t] = gload(D.s.cut + t);
+    for (int t = threadIdx.x; t < W; t += kBinBlock) {
+      tabs[H + 1 + t] = gload(D.s.ebx + t);
+      tabs[H + 1 + W + t] = gload(D.s.eby + t);
+    }
+  }
+  typedef const __attribute__((address_space(3))) float lfloat;
+  const TabLds tl{(lfloat *)tabs, (lfloat *)(tabs + H + 1), (lfloat *)(tabs + H + 1 + W)};
+  const TabGlobal tg{D.s.cut, D.s.ebx, D.s.eby};
   __syncthreads();
   const int64_t p0 = (int64_t)(blk - first[fidx]) * kBinChunk;
   const auto *xyz = (const __attribute__((address_space(1))) float *)D.xyz;
@@ -87,7 +103,9 @@ __global__ void __launch_bounds__(kBinBlock) k_batch_count(const FrameDescDev *_
     int v, u;
     float r;
     uint64_t e = ~0ull;
-    if (project_point(D.s, D.M, D.hasM, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], v, u, r) == PROJ_KEPT) {
+    const int st = LdsTab ? project_point(D.s, tl, D.M, D.hasM, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], v, u, r)
+                          : project_point(D.s, tg, D.M, D.hasM, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], v, u, r);
+    if (st == PROJ_KEPT) {
       const int strip = v >> thl;
       const uint32_t x = ((uint32_t)strip << 16) | (uint32_t)strip_slot(v & (th - 1), u, th, D.twl);
       e = (uint64_t)x | ((uint64_t)__float_as_uint(r) << 32);
@@ -267,6 +285,7 @@ struct BatchPlan {
   int *d_counters = nullptr;     // queue counters (64), then the frames' strip counts
   int64_t ncounters = 0;
   int bin_blocks = 0;
+  size_t count_smem = 0;     // LDS of the binning pass's sensor tables (0: read from device memory)
   std::vector<Group> groups;
   int persistent = 1;
   // seed network (key frames with 4x8 tiles)
@@ -335,7 +354,12 @@ static void bin_frames(BatchPlan &P, bool key, hipStream_t st, Mark mark) {
   const int nf = key ? P.nkey : P.npred;
   if (!nf) return;
   if (nb) {
-    hipLaunchKernelGGL(k_batch_count, dim3(nb), dim3(kBinBlock), 0, st, P.d_desc, P.d_bin_owner, P.d_bin_first, base);
+    if (P.count_smem)
+      hipLaunchKernelGGL(k_batch_count<true>, dim3(nb), dim3(kBinBlock), P.count_smem, st, P.d_desc, P.d_bin_owner,
+                         P.d_bin_first, base);
+    else
+      hipLaunchKernelGGL(k_batch_count<false>, dim3(nb), dim3(kBinBlock), 0, st, P.d_desc, P.d_bin_owner,
+                         P.d_bin_first, base);
     mark(PC_LAUNCH_COUNT);
   }
   hipLaunchKernelGGL(k_batch_offsets, dim3((nf + 3) / 4), dim3(256), 0, st, P.d_desc,
@@ -584,6 +608,12 @@ pc_status pc_batch_create(pc_ctx *ctx, const pc_frame_desc *frames, int32_t nfra
   P.nframes = nframes;
   P.persistent = o.persistent;
   P.use_graph = o.graph;
+  {
+    size_t tab = 0;
+    for (int i = 0; i < nframes; i++)
+      tab = std::max(tab, sizeof(float) * (size_t)(desc[i].s.H + 1 + 2 * desc[i].s.W));
+    P.count_smem = tab <= kCountTabMax ? tab : 0;
+  }
   std::vector<int2> items;
   items.reserve(B.nitems);
   int cus = 0;

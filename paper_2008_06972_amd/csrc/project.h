@@ -19,6 +19,22 @@ __device__ __forceinline__ T gload(const T *p) {
   return *(const __attribute__((address_space(1))) T *)p;
 }
 
+// Where the row and column walks read the sensor's cut tangents and edge
+// vectors: device memory, or a copy of the tables in LDS.
+struct TabGlobal {
+  const float *cut, *ebx, *eby;
+  __device__ __forceinline__ float c(int v) const { return gload(cut + v); }
+  __device__ __forceinline__ float ex(int u) const { return gload(ebx + u); }
+  __device__ __forceinline__ float ey(int u) const { return gload(eby + u); }
+};
+struct TabLds {
+  typedef const __attribute__((address_space(3))) float lfloat;
+  lfloat *cut, *ebx, *eby;
+  __device__ __forceinline__ float c(int v) const { return cut[v]; }
+  __device__ __forceinline__ float ex(int u) const { return ebx[u]; }
+  __device__ __forceinline__ float ey(int u) const { return eby[u]; }
+};
+
 // atan on [-1, 1] to about 1e-5 rad: the odd polynomial of Abramowitz &
 // Stegun 4.4.49.
 __device__ __forceinline__ float atan_unit_as(float x) {
@@ -43,14 +59,15 @@ __device__ __forceinline__ float atan2_as(float y, float x) {
 // Row: the v with cut[v] > q >= cut[v + 1] (cuts descend; the caller has
 // checked cut[0] > q >= cut[H]), i.e. the number of interior cuts above q.
 // Start at the beam nearest the point's elevation and walk.
-__device__ __forceinline__ int row_of(const SensorDev &s, float q) {
+template <class Tab>
+__device__ __forceinline__ int row_of(const SensorDev &s, const Tab &tab, float q) {
   const int H = s.H;
   const float e = fabsf(q) <= 1.0f ? atan_unit_as(q)
                                     : copysignf(1.57079632679f, q) - atan_unit_as(__builtin_amdgcn_rcpf(q));
   int v = (int)fmaf(s.elev0 - e, s.inv_de, 0.5f);
   v = min(max(v, 0), H - 1);
   for (int step = 0; step <= H; step++) {
-    const float above = gload(s.cut + v), below = gload(s.cut + v + 1);
+    const float above = tab.c(v), below = tab.c(v + 1);
     if (above <= q) v--;
     else if (below > q) v++;
     else return v;
@@ -58,15 +75,17 @@ __device__ __forceinline__ int row_of(const SensorDev &s, float q) {
   return -1;
 }
 
-__device__ __forceinline__ float edge_side(const SensorDev &s, int u, float x, float y) {
-  float t = gload(s.eby + u) * x;
-  return fmaf(gload(s.ebx + u), y, -t);
+template <class Tab>
+__device__ __forceinline__ float edge_side(const Tab &tab, int u, float x, float y) {
+  float t = tab.ey(u) * x;
+  return fmaf(tab.ex(u), y, -t);
 }
 
 // Column: the unique u with side(u) <= 0 < side(u + 1); start from the
 // azimuth's bin and walk (the walk ends within one step for any estimate
 // error below a bin; it is bounded by W steps in any case).
-__device__ __forceinline__ int column_of(const SensorDev &s, float x, float y) {
+template <class Tab>
+__device__ __forceinline__ int column_of(const SensorDev &s, const Tab &tab, float x, float y) {
   const int W = s.W;
   const float rel = s.beta0 - atan2_as(y, x);      // within (-2 pi, 2 pi]
   int u = (int)floorf(rel * s.inv_dth);
@@ -77,7 +96,7 @@ __device__ __forceinline__ int column_of(const SensorDev &s, float x, float y) {
   u = min(max(u, 0), W - 1);
   for (int step = 0; step <= W + 2; step++) {
     const int un = (u + 1 == W) ? 0 : u + 1;
-    const float lead = edge_side(s, u, x, y), next = edge_side(s, un, x, y);
+    const float lead = edge_side(tab, u, x, y), next = edge_side(tab, un, x, y);
     if (lead > 0.0f) u = (u == 0) ? W - 1 : u - 1;
     else if (next <= 0.0f) u = un;
     else return u;
@@ -91,8 +110,9 @@ enum { PROJ_KEPT = 0, PROJ_NONFINITE = 1, PROJ_FOV = 2 };
 // PROJ_KEPT with v, u, r set, or why the point is dropped: non-finite
 // coordinates or a zero range, or outside the field of view (on the axis,
 // above the top or below the bottom edge).
-__device__ __forceinline__ int project_point(const SensorDev &s, const Mat12 &M, int hasM, float x, float y, float z,
-                                             int &v, int &u, float &r) {
+template <class Tab>
+__device__ __forceinline__ int project_point(const SensorDev &s, const Tab &tab, const Mat12 &M, int hasM, float x,
+                                             float y, float z, int &v, int &u, float &r) {
   if (hasM) {
     const float xx = fmaf(M.m[0], x, fmaf(M.m[1], y, fmaf(M.m[2], z, M.m[3])));
     const float yy = fmaf(M.m[4], x, fmaf(M.m[5], y, fmaf(M.m[6], z, M.m[7])));
@@ -107,10 +127,15 @@ __device__ __forceinline__ int project_point(const SensorDev &s, const Mat12 &M,
   if (!isfinite(r) || r == 0.0f) return PROJ_NONFINITE;
   if (rho2 < 1e-12f) return PROJ_FOV;
   const float q = z / sqrtf(rho2);
-  if (!(q < gload(s.cut)) || q < gload(s.cut + s.H)) return PROJ_FOV;
-  v = row_of(s, q);
-  u = column_of(s, x, y);
+  if (!(q < tab.c(0)) || q < tab.c(s.H)) return PROJ_FOV;
+  v = row_of(s, tab, q);
+  u = column_of(s, tab, x, y);
   return (v < 0 || u < 0) ? PROJ_FOV : PROJ_KEPT;
+}
+
+__device__ __forceinline__ int project_point(const SensorDev &s, const Mat12 &M, int hasM, float x, float y, float z,
+                                             int &v, int &u, float &r) {
+  return project_point(s, TabGlobal{s.cut, s.ebx, s.eby}, M, hasM, x, y, z, v, u, r);
 }
 
 }  // namespace pcc

@@ -96,7 +96,7 @@ __global__ void __launch_bounds__(kBinBlock) k_batch_count(const FrameDescDev *_
   const int64_t p0 = (int64_t)(blk - first[fidx]) * kBinChunk;
   const auto *xyz = (const __attribute__((address_space(1))) float *)D.xyz;
   auto *stage = (__attribute__((address_space(1))) uint64_t *)D.stage;    // x | y << 32
-#pragma unroll 2
+#pragma unroll 4
   for (int q = 0; q < kBinPts; q++) {
     const int64_t i = p0 + q * kBinBlock + threadIdx.x;
     if (i >= D.n) break;
@@ -147,12 +147,13 @@ __global__ void __launch_bounds__(256) k_batch_offsets(const FrameDescDev *__res
 __global__ void __launch_bounds__(kBinBlock) k_batch_scatter(const FrameDescDev *__restrict__ d,
                                                              const int *__restrict__ owner, const int *__restrict__ first,
                                                              int bbase) {
-  __shared__ int cnt[256], base[256], lim[256];
+  __shared__ int cnt[256], base[256], lim[256], loff[256];
+  __shared__ uint64_t sorted[kBinChunk];       // the block's entries, grouped by strip
   const int blk = bbase + blockIdx.x;
   const int fidx = __builtin_amdgcn_readfirstlane(owner[blk]);
   const FrameDescDev &D = d[fidx];
-  const int TR = D.f.TR;
-  for (int t = threadIdx.x; t < TR; t += kBinBlock) cnt[t] = 0;
+  const int TR = D.f.TR, tid = threadIdx.x, lane = tid & 63;
+  for (int t = tid; t < TR; t += kBinBlock) cnt[t] = 0;
   __syncthreads();
   const int64_t b0 = (int64_t)(blk - first[fidx]) * kBinChunk;
   // entries are x | y << 32: x = strip << 16 | slot (~0 dropped), y = range bits
@@ -162,29 +163,50 @@ __global__ void __launch_bounds__(kBinBlock) k_batch_scatter(const FrameDescDev 
   int slot[kBinPts];
 #pragma unroll
   for (int q = 0; q < kBinPts; q++) {
-    const int64_t i = b0 + q * kBinBlock + threadIdx.x;
+    const int64_t i = b0 + q * kBinBlock + tid;
     e[q] = i < D.n ? (uint64_t)stage[i] : ~0ull;
   }
 #pragma unroll
   for (int q = 0; q < kBinPts; q++)
     slot[q] = (uint32_t)e[q] != 0xffffffffu ? atomicAdd(&cnt[(uint32_t)e[q] >> 16], 1) : 0;
   __syncthreads();
-  for (int t = threadIdx.x; t < TR; t += kBinBlock)
+  // the block's strip offsets (exclusive prefix sum, first wavefront) and
+  // its place in each strip's bucket
+  if (tid < 64) {
+    int carry = 0;
+    for (int t0 = 0; t0 < TR; t0 += 64) {
+      const int t = t0 + lane;
+      const int c = t < TR ? cnt[t] : 0;
+      int x = c;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+      }
+      if (t < TR) loff[t] = carry + x - c;
+      carry += __shfl(x, 63, 64);
+    }
+  }
+  for (int t = tid; t < TR; t += kBinBlock)
     if (cnt[t]) {
       base[t] = atomicAdd(&D.bcur[t], cnt[t]);
       lim[t] = D.boff[t] + D.bcount[t];
     }
   __syncthreads();
-  // Both passes see the same staged entries, so every entry fits its
-  // strip's range; the limit only keeps a bucket from spilling into its
-  // neighbour.
 #pragma unroll
   for (int q = 0; q < kBinPts; q++)
-    if ((uint32_t)e[q] != 0xffffffffu) {
-      const int strip = (uint32_t)e[q] >> 16;
-      const int at = base[strip] + slot[q];
-      if (at < lim[strip]) bucket[at] = e[q] & 0xffffffff0000ffffull;
-    }
+    if ((uint32_t)e[q] != 0xffffffffu) sorted[loff[(uint32_t)e[q] >> 16] + slot[q]] = e[q];
+  __syncthreads();
+  // consecutive entries of a strip go to consecutive bucket slots.  Both
+  // passes see the same staged entries, so every entry fits its strip's
+  // range; the limit only keeps a bucket from spilling into its neighbour.
+  const int total = loff[TR - 1] + cnt[TR - 1];
+  for (int k = tid; k < total; k += kBinBlock) {
+    const uint64_t x = sorted[k];
+    const int strip = (uint32_t)x >> 16;
+    const int at = base[strip] + (k - loff[strip]);
+    if (at < lim[strip]) bucket[at] = x & 0xffffffff0000ffffull;
+  }
 }
 
 __device__ __forceinline__ StripSrc src_of(const FrameDescDev &D) {

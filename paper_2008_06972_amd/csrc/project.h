@@ -58,7 +58,8 @@ __device__ __forceinline__ float atan2_as(float y, float x) {
 
 // Row: the v with cut[v] > q >= cut[v + 1] (cuts descend; the caller has
 // checked cut[0] > q >= cut[H]), i.e. the number of interior cuts above q.
-// Start at the beam nearest the point's elevation and walk.
+// Start at the beam nearest the point's elevation and walk; the answer is
+// unique, so the path taken does not change it.
 template <class Tab>
 __device__ __forceinline__ int row_of(const SensorDev &s, const Tab &tab, float q) {
   const int H = s.H;
@@ -66,6 +67,16 @@ __device__ __forceinline__ int row_of(const SensorDev &s, const Tab &tab, float 
                                     : copysignf(1.57079632679f, q) - atan_unit_as(__builtin_amdgcn_rcpf(q));
   int v = (int)fmaf(s.elev0 - e, s.inv_de, 0.5f);
   v = min(max(v, 0), H - 1);
+  // one branch-free step settles almost every point (the caller's range
+  // check keeps v inside [0, H - 1]); the walk below finishes the rest
+  {
+    const float above = tab.c(v), below = tab.c(v + 1);
+    v += (below > q ? 1 : 0) - (above <= q ? 1 : 0);
+  }
+  {
+    const float above = tab.c(v), below = tab.c(v + 1);
+    if (above > q && !(below > q)) return v;
+  }
   for (int step = 0; step <= H; step++) {
     const float above = tab.c(v), below = tab.c(v + 1);
     if (above <= q) v--;
@@ -94,6 +105,17 @@ __device__ __forceinline__ int column_of(const SensorDev &s, const Tab &tab, flo
   u = u >= W ? u - W : u;
   u = u >= W ? u - W : u;
   u = min(max(u, 0), W - 1);
+  // one branch-free step, then the walk for the rare rest
+  {
+    const int un = (u + 1 == W) ? 0 : u + 1;
+    const float lead = edge_side(tab, u, x, y), next = edge_side(tab, un, x, y);
+    u = lead > 0.0f ? ((u == 0) ? W - 1 : u - 1) : (next <= 0.0f ? un : u);
+  }
+  {
+    const int un = (u + 1 == W) ? 0 : u + 1;
+    const float lead = edge_side(tab, u, x, y), next = edge_side(tab, un, x, y);
+    if (!(lead > 0.0f) && !(next <= 0.0f)) return u;
+  }
   for (int step = 0; step <= W + 2; step++) {
     const int un = (u + 1 == W) ? 0 : u + 1;
     const float lead = edge_side(tab, u, x, y), next = edge_side(tab, un, x, y);

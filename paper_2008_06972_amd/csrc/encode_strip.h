@@ -148,7 +148,7 @@ __host__ __device__ inline int strip_slot(int i, int u, int th, int tw_log2) {
 }
 
 // misc[] slots
-constexpr int M_SRUNS = 0, M_PRUNS = 1, M_SEEDED = 2, M_FALLBACK = 3, M_LIST = 8, M_F64 = 10;
+constexpr int M_SRUNS = 0, M_PRUNS = 1, M_SEEDED = 2, M_FALLBACK = 3, M_LIST = 8, M_F64 = 10, M_NEXT = 12;
 
 __device__ __forceinline__ float4 pack_plane(const Plane &P) { return make_float4(P.a, P.b, P.c, (float)P.k); }
 __device__ __forceinline__ Plane unpack_plane(float4 v) { return Plane{(int)v.w, v.x, v.y, v.z}; }
@@ -700,40 +700,85 @@ __device__ __forceinline__ int grow_runs(StripSmem<TH, TW> &sm, const EncParams 
   for (int tc = tid; tc < TC; tc += kBlock)
     if (start(tc)) sm.nx[tc] = (int16_t)next_start(sm.acc, tc + 1 + sm.reach[tc], TC);
   __syncthreads();
-  if (tid < 64) {
-    // the walk proper: only the chain of run starts; lane k % 64 holds
-    // run k's start and length until 64 runs are stored at once
-    const int lane = tid;
-    int nr = 0, s = next_start(sm.acc, 0, TC), win = -1;
-    uint32_t note = 0;      // this lane's tile of the current window: reach | (nx & 0xffff) << 8
-    int my_s = 0, my_l = 0;
-    while (s >= 0) {
-      if ((s >> 6) != win) {
-        win = s >> 6;
-        const int tc = win * 64 + lane;
-        note = tc < TC ? (uint32_t)sm.reach[tc] | ((uint32_t)(uint16_t)sm.nx[tc] << 8) : 0u;
+  // The chain of run starts, by pointer jumping: from the first start,
+  // every marked start marks the start 2^k links further on (level k), so
+  // about log2(runs) levels mark the whole chain; the marked starts in tile
+  // order are the runs.  A start whose reach hit kReach has an unknown
+  // successor (its run may go on), so the chain is cut there: that run is
+  // continued by extend_beyond and the marking restarts after it.
+  {
+    int16_t *ja = reinterpret_cast<int16_t *>(sm.cur()), *jb = ja + TC;
+    uint8_t *on = reinterpret_cast<uint8_t *>(jb + TC);
+    __shared__ int wcnt[kBlock / 64];
+    const int lane = tid & 63, wv = tid >> 6;
+    int nr = 0;
+    int s0 = next_start(sm.acc, 0, TC);
+    while (s0 >= 0) {
+      for (int t = tid; t < TC; t += kBlock) {
+        const bool st = (sm.acc[t >> 6] >> (t & 63)) & 1ull;
+        const bool capped = st && sm.reach[t] == kReach && t + 1 + kReach < TC;
+        ja[t] = !st ? (int16_t)-1 : (capped ? (int16_t)-2 : sm.nx[t]);
+        on[t] = t == s0;
       }
-      const uint32_t x = __builtin_amdgcn_readlane(note, s & 63);
-      int len = 1 + (int)(x & 255u);
-      int nxt = (int)(int16_t)(x >> 8);
-      if (len == 1 + kReach && s + len < TC) {
-        len += extend_beyond<TH, TW>(sm, p, plane_of(s), s, s + len, TC, allowed);
-        nxt = next_start(sm.acc, s + len, TC);
+      __syncthreads();
+      for (;;) {
+        // ja = J_k: 2^k links on (-1: none, -2: a capped start on the way)
+        for (int t = tid; t < TC; t += kBlock) {
+          const int j = ja[t];
+          if (on[t] && j >= 0) on[j] = 1;
+        }
+        for (int t = tid; t < TC; t += kBlock) {
+          const int j = ja[t];
+          jb[t] = j >= 0 ? ja[j] : (int16_t)j;
+        }
+        __syncthreads();
+        // all links within 2^(k+1) of s0 are marked; done when s0 has no
+        // start 2^(k+1) links on
+        const bool more = jb[s0] >= 0;
+        int16_t *x = ja;
+        ja = jb;
+        jb = x;
+        if (!more) break;
+        __syncthreads();     // the next level overwrites jb, read above
       }
-      my_s = lane == (nr & 63) ? s : my_s;
-      my_l = lane == (nr & 63) ? len : my_l;
-      nr++;
-      if ((nr & 63) == 0) {
-        sm.rs[nr - 64 + lane] = (int16_t)my_s;
-        sm.rl[nr - 64 + lane] = (int16_t)my_l;
+      // marked starts, in tile order, appended to the runs
+      for (int t0 = 0; t0 < TC; t0 += kBlock) {
+        const int t = t0 + tid;
+        const bool m = t < TC && on[t];
+        const uint64_t b = __ballot(m);
+        if (lane == 0) wcnt[wv] = __popcll(b);
+        __syncthreads();
+        int base = nr, tot = 0;
+        for (int q = 0; q < kBlock / 64; q++) {
+          base += q < wv ? wcnt[q] : 0;
+          tot += wcnt[q];
+        }
+        if (m) {
+          const int at = base + __popcll(b & ((1ull << lane) - 1ull));
+          sm.rs[at] = (int16_t)t;
+          sm.rl[at] = (int16_t)(1 + sm.reach[t]);
+        }
+        nr += tot;
+        __syncthreads();
       }
-      s = nxt;
+      // the chain's last start: continue its run if its reach was capped
+      const int last = sm.rs[nr - 1];
+      if (sm.reach[last] == kReach && last + 1 + kReach < TC) {
+        if (tid < 64) {
+          const int len = 1 + kReach + extend_beyond<TH, TW>(sm, p, plane_of(last), last, last + 1 + kReach, TC, allowed);
+          if (lane == 0) {
+            sm.rl[nr - 1] = (int16_t)len;
+            sm.misc[M_NEXT] = next_start(sm.acc, last + len, TC);
+          }
+        }
+        __syncthreads();
+        s0 = sm.misc[M_NEXT];
+        __syncthreads();     // every thread has read M_NEXT and the marks before they are reset
+      } else {
+        s0 = -1;
+      }
     }
-    if (lane < (nr & 63)) {
-      sm.rs[(nr & ~63) + lane] = (int16_t)my_s;
-      sm.rl[(nr & ~63) + lane] = (int16_t)my_l;
-    }
-    if (lane == 0) *nr_out = nr;
+    if (tid == 0) *nr_out = nr;
   }
   __syncthreads();
   {

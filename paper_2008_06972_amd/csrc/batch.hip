@@ -645,11 +645,17 @@ pc_status pc_batch_create(pc_ctx *ctx, const pc_frame_desc *frames, int32_t nfra
     for (auto &sh : shapes) {
       Group g{sh[0], sh[1], kind, (int)items.size(), 0, 0, 0};
       int maxW = 0;
+      int maxTR = 0;
       for (int i = 0; i < nframes; i++) {
         if (desc[i].kind != kind || desc[i].p.th != sh[0] || desc[i].p.tw != sh[1]) continue;
-        for (int tr = 0; tr < desc[i].f.TR; tr++) items.push_back(make_int2(i, tr));
+        maxTR = std::max(maxTR, desc[i].f.TR);
         maxW = std::max(maxW, desc[i].s.W);
       }
+      for (int tr = 0; tr < maxTR; tr++)
+        for (int i = 0; i < nframes; i++) {
+          if (desc[i].kind != kind || desc[i].p.th != sh[0] || desc[i].p.tw != sh[1] || tr >= desc[i].f.TR) continue;
+          items.push_back(make_int2(i, tr));
+        }
       g.count = (int)items.size() - g.first;
       if (!g.count) continue;
       g.smem = group_smem(sh[0], sh[1], maxW, kind == 1);

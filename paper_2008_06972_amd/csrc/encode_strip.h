@@ -1187,32 +1187,34 @@ __device__ uint64_t huffman_cost_wave(const uint32_t *h, int lane) {
   if (m <= 0) return 0;
   if (m == 1) return (uint32_t)__builtin_amdgcn_readlane((int)pick4(v, i >> 6), i & 63);
   // lv: block of leaf i; qw: block being written (node qt); qr: block of
-  // node qh when that is an older block; done: finished node blocks
+  // node qh when that is an older block; done: finished node blocks.  lf
+  // and nd are the next leaf and the queue head (~0: none).
   uint32_t lv = pick4(v, i >> 6), qw = 0u, qr = 0u;
   uint32_t done[4] = {0u, 0u, 0u, 0u};
   int qh = 0, qt = 0;
   uint64_t cost = 0;
+  uint32_t lf = (uint32_t)__builtin_amdgcn_readlane((int)lv, i & 63), nd = ~0u;
   for (int step = 0; step < m - 1; step++) {
     uint32_t ab[2];
 #pragma unroll
     for (int z = 0; z < 2; z++) {
-      const uint32_t lf = (uint32_t)__builtin_amdgcn_readlane((int)lv, i & 63);
-      const uint32_t nw = (uint32_t)__builtin_amdgcn_readlane((int)qw, qh & 63);
-      const uint32_t nr = (uint32_t)__builtin_amdgcn_readlane((int)qr, qh & 63);
-      const uint32_t nd = ((qh ^ qt) >> 6) == 0 ? nw : nr;
-      const bool take_leaf = i < 256 && (qh == qt || lf <= nd);
-      ab[z] = take_leaf ? lf : nd;
-      if (take_leaf) {
+      if (lf <= nd) {             // ties go to the leaf; an exhausted side reads ~0
+        ab[z] = lf;
         i++;
         if ((i & 63) == 0 && i < 256) lv = pick4(v, i >> 6);
+        lf = i < 256 ? (uint32_t)__builtin_amdgcn_readlane((int)lv, i & 63) : ~0u;
       } else {
+        ab[z] = nd;
         qh++;
         if ((qh & 63) == 0) qr = pick4(done, qh >> 6);
+        const uint32_t x = (uint32_t)__builtin_amdgcn_readlane((int)((((qh ^ qt) >> 6) == 0) ? qw : qr), qh & 63);
+        nd = qh < qt ? x : ~0u;
       }
     }
     const uint32_t wsum = ab[0] + ab[1];
     cost += wsum;
     qw = lane == (qt & 63) ? wsum : qw;
+    if (qh == qt) nd = wsum;      // the queue was empty: the new node is its head
     qt++;
     if ((qt & 63) == 0) {
       const int b = (qt >> 6) - 1;

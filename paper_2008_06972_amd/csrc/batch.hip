@@ -319,7 +319,7 @@ struct BatchPlan {
   size_t net_smem = 0;
   NetInputJob *d_net_in = nullptr;
   ConvJob *d_net_conv = nullptr;
-  int net_px[5] = {0, 0, 0, 0, 0};
+  int net_hw[2] = {0, 0};      // largest seeded frame's H and W
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   int use_graph = 0;
@@ -416,7 +416,7 @@ static hipError_t batch_launches(BatchPlan &P, hipStream_t st, Mark mark, bool c
     hipLaunchKernelGGL((k_batch_keyimage<4, 8>), dim3(P.n_net_items), dim3(kBlock), P.net_smem, st, P.d_desc,
                        P.d_net_items);
     mark(PC_LAUNCH_KEYIMAGE);
-    net_forward_batch(P.net_params, P.net_wpk, P.d_net_in, P.d_net_conv, P.nnet, P.net_px, st);
+    net_forward_batch(P.net_params, P.net_wpk, P.d_net_in, P.d_net_conv, P.nnet, P.net_hw[0], P.net_hw[1], st);
     mark(PC_LAUNCH_NET);
   }
   for (int pass = 0; pass < 2; pass++) {      // key groups, then predicted groups
@@ -544,7 +544,7 @@ pc_status pc_batch_create(pc_ctx *ctx, const pc_frame_desc *frames, int32_t nfra
   std::vector<NetInputJob> net_in;
   std::vector<ConvJob> net_conv[4];
   std::vector<int2> net_items;
-  int net_px[5] = {0, 0, 0, 0, 0};
+  int net_hw[2] = {0, 0};
   int net_maxW = 0;
   if (B.nnet) {
     net_wpk = (uint16_t *)net_ws;
@@ -614,11 +614,8 @@ pc_status pc_batch_create(pc_ctx *ctx, const pc_frame_desc *frames, int32_t nfra
       net_conv[1].push_back(ConvJob{a1, H / 2, W / 2, a2, H / 4, W / 4});
       net_conv[2].push_back(ConvJob{a2, H / 4, W / 4, a3, H / 4, W / 8});
       net_conv[3].push_back(ConvJob{a3, H / 4, W / 8, seedbuf, H / 4, W / 8});
-      net_px[0] = std::max(net_px[0], H * W);
-      net_px[1] = std::max(net_px[1], (H / 2) * (W / 2));
-      net_px[2] = std::max(net_px[2], (H / 4) * (W / 4));
-      net_px[3] = std::max(net_px[3], (H / 4) * (W / 8));
-      net_px[4] = std::max(net_px[4], (H / 4) * (W / 8));
+      net_hw[0] = std::max(net_hw[0], H);
+      net_hw[1] = std::max(net_hw[1], W);
       net_maxW = std::max(net_maxW, W);
       for (int tr = 0; tr < L.TR; tr++) net_items.push_back(make_int2(i, tr));
     }
@@ -680,7 +677,8 @@ pc_status pc_batch_create(pc_ctx *ctx, const pc_frame_desc *frames, int32_t nfra
     P.net_smem = sizeof(float) * (size_t)(net_maxW / 8) * StripSmem<4, 8>::N;
     P.d_net_in = d_net_in;
     P.d_net_conv = d_net_conv;
-    for (int q = 0; q < 5; q++) P.net_px[q] = net_px[q];
+    P.net_hw[0] = net_hw[0];
+    P.net_hw[1] = net_hw[1];
     if (hipFuncSetAttribute((const void *)k_batch_keyimage<4, 8>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)P.net_smem) != hipSuccess) {
       delete b;

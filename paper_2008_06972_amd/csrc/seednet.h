@@ -25,8 +25,8 @@ size_t net_packed_bytes();
 size_t net_forward_act_bytes(int H, int W, size_t *a0, size_t *a1, size_t *a2, size_t *a3);
 
 // Forward pass over n frames: in_jobs[n] and conv_jobs[4][n] in device
-// memory; max_px[0] = largest H*W, max_px[1 + l] = largest output of layer l.
+// memory; max_h, max_w: the largest frame height and width.
 void net_forward_batch(const float *params, uint16_t *wpk, const NetInputJob *in_jobs, const ConvJob *conv_jobs, int n,
-                       const int *max_px, hipStream_t st);
+                       int max_h, int max_w, hipStream_t st);
 
 }  // namespace pcc

@@ -156,6 +156,121 @@ __global__ void __launch_bounds__(256) k_net_conv(ConvJob job, const ConvJob *__
   }
 }
 
+// The same convolution with the input staged in LDS: a block computes BW
+// consecutive output pixels of R consecutive output rows; it first copies
+// the input rows they read (zero outside the image) into LDS with coalesced
+// loads, PS bf16 per input pixel (CI + 4, so that the 16 pixels of an MFMA
+// group hit different banks), and then forms every A operand from LDS; each
+// wavefront keeps the weights in registers for R * BW / 64 pixels.  With
+// RANGE the input channels are computed from the range image while staging
+// (the first layer of the batched forward).  The operands and the MFMA order
+// are those of k_net_conv, so the results are the same.
+template <int CI, int CO, int SY, int SX, bool LAST, bool RANGE, int BW, int R>
+__global__ void __launch_bounds__(256) k_net_conv_lds(ConvJob job, const ConvJob *__restrict__ jobs,
+                                                      const NetInputJob *__restrict__ in_jobs,
+                                                      const uint16_t *__restrict__ wpk, const float *__restrict__ bias) {
+  constexpr int KPAD = net_kpad(CI), KSTEPS = KPAD / 16, NB = (CO + 15) / 16;
+  constexpr int IW = (BW - 1) * SX + 3, IH = (R - 1) * SY + 3, PS = RANGE ? CI : CI + 4;
+  __shared__ __align__(16) uint16_t tile[IH * IW * PS];
+  const ConvJob J = jobs ? jobs[blockIdx.y] : job;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, m = lane & 15;
+  const int nseg = (J.Wo + BW - 1) / BW;
+  const int oy0 = (blockIdx.x / nseg) * R, ox0 = (blockIdx.x % nseg) * BW;
+  if (oy0 >= J.Ho) return;
+  const int iy0 = oy0 * SY - 1, ix0 = ox0 * SX - 1;
+  // staging: U elements' loads in flight per thread before their stores
+  constexpr int U = 8;
+  if (RANGE) {
+    const NetInputJob I = in_jobs[blockIdx.y];
+    constexpr int NE = IH * IW;
+    for (int e0 = tid; e0 < NE; e0 += 256 * U) {
+      float r[U], ce[U], se[U], ca[U], sa[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int e = e0 + 256 * u, dy = e / IW, c = e - dy * IW, iy = iy0 + dy, ix = ix0 + c;
+        const bool ok = e < NE && iy >= 0 && iy < I.H && ix >= 0 && ix < I.W;
+        const int cy = ok ? iy : 0, cx = ok ? ix : 0;
+        r[u] = ok ? I.range[(size_t)cy * I.W + cx] : 0.0f;
+        ce[u] = I.ce[cy]; se[u] = I.se[cy]; ca[u] = I.ca[cx]; sa[u] = I.sa[cx];
+      }
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int e = e0 + 256 * u;
+        if (e >= NE) break;
+        const float dx = ce[u] * ca[u], dyy = ce[u] * sa[u];
+        bf16x4 v;
+        v[0] = (short)bf16_rne(r[u] * 0.0625f);
+        v[1] = (short)bf16_rne((r[u] * dx) * 0.0625f);
+        v[2] = (short)bf16_rne((r[u] * dyy) * 0.0625f);
+        v[3] = (short)bf16_rne((r[u] * se[u]) * 0.0625f);
+        *reinterpret_cast<bf16x4 *>(tile + (size_t)e * PS) = v;
+      }
+    }
+  } else {
+    constexpr int NQ = CI / 4, NE = IH * IW * NQ;   // 8-byte pieces per pixel
+    for (int e0 = tid; e0 < NE; e0 += 256 * U) {
+      bf16x4 v[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int e = e0 + 256 * u, px = e / NQ, q = e - px * NQ, dy = px / IW, c = px - dy * IW;
+        const int iy = iy0 + dy, ix = ix0 + c;
+        v[u] = bf16x4{0, 0, 0, 0};
+        if (e < NE && iy >= 0 && iy < J.Hi && ix >= 0 && ix < J.Wi)
+          v[u] = *reinterpret_cast<const bf16x4 *>(J.in + ((size_t)iy * J.Wi + ix) * CI + 4 * q);
+      }
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int e = e0 + 256 * u, px = e / NQ, q = e - px * NQ;
+        if (e < NE) *reinterpret_cast<bf16x4 *>(tile + (size_t)px * PS + 4 * q) = v[u];
+      }
+    }
+  }
+  bf16x4 b[KSTEPS][NB];
+#pragma unroll
+  for (int s = 0; s < KSTEPS; s++)
+#pragma unroll
+    for (int nb = 0; nb < NB; nb++)
+      b[s][nb] = *reinterpret_cast<const bf16x4 *>(wpk + (size_t)(nb * 16 + m) * KPAD + 16 * s + 4 * g);
+  float bv[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; nb++) bv[nb] = nb * 16 + m < CO ? bias[nb * 16 + m] : 0.0f;
+  __syncthreads();
+  for (int t = wave; t < R * (BW / 16); t += 4) {
+    const int r = t / (BW / 16), tc = t - r * (BW / 16), oy = oy0 + r;
+    if (oy >= J.Ho) break;
+    const int pl = 16 * tc + m;
+    bf16x4 a[KSTEPS];
+#pragma unroll
+    for (int s = 0; s < KSTEPS; s++) {
+      const int k0 = 16 * s + 4 * g, pos = k0 / CI, ci0 = k0 % CI;
+      a[s] = pos < 9 ? *reinterpret_cast<const bf16x4 *>(tile + ((r * SY + pos / 3) * IW + pl * SX + pos % 3) * PS + ci0)
+                     : bf16x4{0, 0, 0, 0};
+    }
+    f32x4 acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; nb++) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < KSTEPS; s++)
+#pragma unroll
+      for (int nb = 0; nb < NB; nb++) acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[s], b[s][nb], acc[nb], 0, 0, 0);
+    // lane holds D[pixel 4g + i][channel nb*16 + m]
+#pragma unroll
+    for (int nb = 0; nb < NB; nb++) {
+      const int ch = nb * 16 + m;
+      if (ch >= CO) continue;
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        const int ox = ox0 + 16 * tc + 4 * g + i;
+        if (ox >= J.Wo) continue;
+        const size_t pix = (size_t)oy * J.Wo + ox;
+        const float v = acc[nb][i] + bv[nb];
+        if (LAST) static_cast<float *>(J.out)[pix * 4 + ch] = v;
+        else static_cast<uint16_t *>(J.out)[pix * CO + ch] = bf16_rne(fmaxf(v, 0.0f));
+      }
+    }
+  }
+}
+
 // The first layer straight from the range image (batched forward only):
 // a lane's four K values are the four input channels of one pixel, computed
 // as k_net_input computes them, so the result equals input + first layer.
@@ -235,6 +350,16 @@ static void launch_conv(const ConvJob &j, const ConvJob *jobs, int njobs, int ma
   hipLaunchKernelGGL((k_net_conv<CI, CO, SY, SX, LAST>), dim3(blocks, njobs), dim3(256), 0, st, j, jobs, wpk, bias);
 }
 
+// LDS-staged convolution over output rows of at most max_ho rows and max_wo
+// columns (per frame: j; or the table jobs[njobs]).
+template <int CI, int CO, int SY, int SX, bool LAST, bool RANGE, int BW, int R>
+static void launch_conv_lds(const ConvJob &j, const ConvJob *jobs, const NetInputJob *in_jobs, int njobs, int max_ho,
+                            int max_wo, const uint16_t *wpk, const float *bias, hipStream_t st) {
+  const int blocks = ((max_ho + R - 1) / R) * ((max_wo + BW - 1) / BW);
+  hipLaunchKernelGGL((k_net_conv_lds<CI, CO, SY, SX, LAST, RANGE, BW, R>), dim3(blocks, njobs), dim3(256), 0, st, j,
+                     jobs, in_jobs, wpk, bias);
+}
+
 // Layers 1-4 given a0: per frame (jobs == NULL, j* used) or a table of frames.
 void net_layers(const float *params, const uint16_t *wpk, const ConvJob *j, const ConvJob *jobs, int njobs,
                 const int *max_px, hipStream_t st) {
@@ -242,10 +367,10 @@ void net_layers(const float *params, const uint16_t *wpk, const ConvJob *j, cons
                                   params + net_layer(0).boff, st);
   launch_conv<16, 32, 2, 2, false>(j[1], jobs ? jobs + njobs : nullptr, njobs, max_px[1], wpk + net_layer(1).poff,
                                    params + net_layer(1).boff, st);
-  launch_conv<32, 32, 1, 2, false>(j[2], jobs ? jobs + 2 * njobs : nullptr, njobs, max_px[2],
-                                   wpk + net_layer(2).poff, params + net_layer(2).boff, st);
-  launch_conv<32, 4, 1, 1, true>(j[3], jobs ? jobs + 3 * njobs : nullptr, njobs, max_px[3], wpk + net_layer(3).poff,
-                                 params + net_layer(3).boff, st);
+  launch_conv_lds<32, 32, 1, 2, false, false, 64, 4>(j[2], jobs ? jobs + 2 * njobs : nullptr, nullptr, njobs, j[2].Ho,
+                                                  j[2].Wo, wpk + net_layer(2).poff, params + net_layer(2).boff, st);
+  launch_conv_lds<32, 4, 1, 1, true, false, 128, 2>(j[3], jobs ? jobs + 3 * njobs : nullptr, nullptr, njobs, j[3].Ho,
+                                                 j[3].Wo, wpk + net_layer(3).poff, params + net_layer(3).boff, st);
 }
 
 void net_pack(const float *params, uint16_t *wpk, hipStream_t st) {
@@ -263,16 +388,18 @@ void net_input(const float *range, const SensorDev &s, uint16_t *a0, hipStream_t
 // conv_jobs[4][n] (device tables); max_px[0] = largest H*W, max_px[1 + l] =
 // largest output of layer l.
 void net_forward_batch(const float *params, uint16_t *wpk, const NetInputJob *in_jobs, const ConvJob *conv_jobs, int n,
-                       const int *max_px, hipStream_t st) {
+                       int max_h, int max_w, hipStream_t st) {
   net_pack(params, wpk, st);
-  hipLaunchKernelGGL(k_net_conv1_range, dim3((max_px[1] + 63) / 64, n), dim3(256), 0, st, in_jobs, conv_jobs,
-                     wpk + net_layer(0).poff, params + net_layer(0).boff);
-  launch_conv<16, 32, 2, 2, false>(ConvJob{}, conv_jobs + n, n, max_px[2], wpk + net_layer(1).poff,
+  launch_conv_lds<4, 16, 2, 2, false, true, 128, 2>(ConvJob{}, conv_jobs, in_jobs, n, max_h / 2, max_w / 2,
+                                                 wpk + net_layer(0).poff, params + net_layer(0).boff, st);
+  // the second layer reads each input pixel about twice (stride 2): direct
+  // gathers beat staging it in LDS
+  launch_conv<16, 32, 2, 2, false>(ConvJob{}, conv_jobs + n, n, (max_h / 4) * (max_w / 4), wpk + net_layer(1).poff,
                                    params + net_layer(1).boff, st);
-  launch_conv<32, 32, 1, 2, false>(ConvJob{}, conv_jobs + 2 * n, n, max_px[3], wpk + net_layer(2).poff,
-                                   params + net_layer(2).boff, st);
-  launch_conv<32, 4, 1, 1, true>(ConvJob{}, conv_jobs + 3 * n, n, max_px[4], wpk + net_layer(3).poff,
-                                 params + net_layer(3).boff, st);
+  launch_conv_lds<32, 32, 1, 2, false, false, 64, 4>(ConvJob{}, conv_jobs + 2 * n, nullptr, n, max_h / 4, max_w / 8,
+                                                  wpk + net_layer(2).poff, params + net_layer(2).boff, st);
+  launch_conv_lds<32, 4, 1, 1, true, false, 128, 2>(ConvJob{}, conv_jobs + 3 * n, nullptr, n, max_h / 4, max_w / 8,
+                                                 wpk + net_layer(3).poff, params + net_layer(3).boff, st);
 }
 
 size_t net_packed_bytes() { return 2 * (size_t)net_packed_elems(); }

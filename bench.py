@@ -169,17 +169,20 @@ def main():
         for _ in range(a.warmup):
             batch.run()
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(a.steps):
+        # events between the replays: the mean over the K steps is the
+        # result; the median replay is reported beside it
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps + 1)]
+        ev[0].record(stream)
+        for k in range(a.steps):
             batch.run()
-        e1.record(stream)
+            ev[k + 1].record(stream)
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / a.steps
+        ms = ev[0].elapsed_time(ev[-1]) / a.steps
+        ms_median = float(np.median([ev[k].elapsed_time(ev[k + 1]) for k in range(a.steps)]))
         infos = [o.info() for o in outs]
         key_infos = [infos[i] for i in range(nfr) if i == key_of(i)]
         tiles = sum(sum(i.tiles) for i in infos)
-        st = {"ms_per_step": ms, "frames_per_s": nfr / (ms / 1e3),
+        st = {"ms_per_step": ms, "frames_per_s": nfr / (ms / 1e3), "ms_per_step_median": ms_median,
               "mapping": "default 4x8 persistent" if cfg is None else cfg.key(),
               "fits_per_tile": sum(i.fits for i in infos) / max(1, tiles),
               "key_fits_per_tile": sum(i.fits for i in key_infos) / max(1, sum(sum(i.tiles) for i in key_infos)),
@@ -311,6 +314,22 @@ def main():
                               "frac": ach / 8000.0, "traffic": traffic_from_profiles(dom, 1),
                               "bytes_per_launch": alg[dom], "ms_per_launch": dur[dom]}
         result["launch_ms"] = {k: round(v, 4) for k, v in dur.items()}
+        # a plain device copy of 1 GiB (read once, written once): the
+        # bandwidth a kernel on this device can reach in practice
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record(stream)
+        for _ in range(5):
+            dst.copy_(src)
+        c1.record(stream)
+        torch.cuda.synchronize()
+        copy_gbps = 5 * 2 * (4 << 28) / (c0.elapsed_time(c1) / 1e3) / 1e9
+        del src, dst
+        result["copy_ceiling"] = {"GB/s": copy_gbps, "bytes": 2 * (4 << 28), "what": "1 GiB device copy, read + write"}
+        result["roofline"]["frac_of_copy"] = ach / copy_gbps
 
     # ------------------------------------------------------- CPU baseline
     if not a.no_cpu:
@@ -331,6 +350,23 @@ def main():
             rel = abs(int(sz[: nq * N_FRAMES].sum()) - total) / total
             result["cpu_baseline"][f"size_rel_diff_{name}"] = rel
         log(f"oracle: {len(sample) / dt:.1f} frames/s on {oracle.num_threads()} threads")
+        # one core, on the first sequence
+        nt = oracle.num_threads()
+        oracle.set_num_threads(1)
+        t1 = time.time()
+        oracle.encode_sequences(frames_np[:N_FRAMES], transforms[:N_FRAMES], KEY_INDEX, 1, N_FRAMES, tb, oprm)
+        dt1 = time.time() - t1
+        oracle.set_num_threads(nt)
+        model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+        except OSError:
+            pass
+        result["cpu_baseline"]["one_core"] = {"value": N_FRAMES / dt1, "unit": "frames/s",
+                                              "sample": f"first sequence ({N_FRAMES} frames), {dt1:.2f}s wall"}
+        result["cpu_baseline"]["host"] = {"cpu": model, "logical_cpus": os.cpu_count()}
+        log(f"oracle: {N_FRAMES / dt1:.1f} frames/s on one core ({model})")
     print(json.dumps(result), flush=True)
     for b in batches.values():
         b.close()

@@ -43,6 +43,7 @@ def lib():
         L.orc_encode_sequences.restype = C.c_uint64
         L.orc_tls.restype = C.c_int
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -260,3 +261,8 @@ def encode_sequences(frames, transforms, key_index: int, nseq: int, nf: int, tab
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the frame-parallel loops (OpenMP)."""
+    lib().orc_set_num_threads(C.c_int(int(n)))

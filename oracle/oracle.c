@@ -846,3 +846,12 @@ int orc_num_threads(void) {
   return 1;
 #endif
 }
+
+/* Threads of the parallel loops over frames (n >= 1). */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? n : 1);
+#else
+  (void)n;
+#endif
+}

@@ -121,6 +121,7 @@ uint64_t orc_encode_sequences(int nseq, int nf, int key_index, const float *cons
                               const orc_params *prm, uint64_t *sizes, int64_t *finite_points);
 
 int orc_num_threads(void);
+void orc_set_num_threads(int n);
 
 #ifdef __cplusplus
 }

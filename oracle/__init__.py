@@ -44,6 +44,8 @@ def lib():
         L.orc_tls.restype = C.c_int
         L.orc_num_threads.restype = C.c_int
         L.orc_set_num_threads.restype = None
+        L.orc_pack.restype = C.c_uint64
+        L.orc_unpack.restype = C.c_int
         _lib = L
     return _lib
 
@@ -82,7 +84,8 @@ class _Frame(C.Structure):
                 + [(n, C.c_void_p) for n, _, _ in _PRUN]
                 + [("occ", C.c_void_p), ("n_res", C.c_int64), ("codes", C.c_void_p), ("hist", C.c_void_p),
                    ("stream_bytes", C.c_uint64 * 4), ("coded_bits", C.c_uint64 * 4),
-                   ("size_bytes", C.c_uint64), ("range_error", C.c_int32), ("seeded", C.c_void_p)])
+                   ("size_bytes", C.c_uint64), ("range_error", C.c_int32), ("seeded", C.c_void_p),
+                   ("sbuf", C.c_void_p * 4), ("scap", C.c_uint64 * 4)])
 
 
 @dataclass
@@ -167,6 +170,14 @@ class Frame:
         self.arrays["seeded"] = np.zeros(T, np.int8)
         kw = {n: _p(a).value for n, a in self.arrays.items()}
         self.c = _Frame(TR=self.TR, TC=self.TC, **kw)
+        # captured stream bytes (OCC, RUN, MASK, RES), capacities from the
+        # stream formats: a row's runs cover at most TC tiles, at most 23
+        # bytes each, plus two varint counts
+        caps = [(H * W + 7) // 8, self.TR * (10 + 23 * self.TC), 8 * T, 2 * H * W]
+        self.sbufs = [np.zeros(c, np.uint8) for c in caps]
+        for q in range(4):
+            self.c.sbuf[q] = _p(self.sbufs[q]).value
+            self.c.scap[q] = caps[q]
 
     def __getattr__(self, name):
         arrays = self.__dict__.get("arrays")
@@ -207,6 +218,10 @@ class Frame:
     def range_error(self):
         return int(self.c.range_error)
 
+    def streams(self):
+        """The serialized OCC, RUN, MASK and RES bytes, in emission order."""
+        return [self.sbufs[q][: int(self.c.stream_bytes[q])].copy() for q in range(4)]
+
 
 def encode_key(range_img: np.ndarray, tables: Tables, prm: Params, seed: np.ndarray | None = None) -> Frame:
     """Key-frame encoding; ``seed`` (T x 4 FP32: normal, planarity logit) turns
@@ -235,6 +250,46 @@ def decode(frame: Frame, tables: Tables, prm: Params, key: Frame | None = None) 
     lib().orc_decode(C.byref(key.c) if key is not None else None, C.byref(frame.c), C.byref(tables.s),
                      C.byref(pc), _p(out))
     return out
+
+
+def code_lengths(hist) -> np.ndarray:
+    """Code lengths (uint8[256], at most 15) of one stream's byte histogram."""
+    h = np.ascontiguousarray(hist, dtype=np.uint32).reshape(256)
+    out = np.zeros(256, np.uint8)
+    lib().orc_code_lengths(_p(h), _p(out))
+    return out
+
+
+def canonical_codes(lengths) -> np.ndarray:
+    ln = np.ascontiguousarray(lengths, dtype=np.uint8).reshape(256)
+    out = np.zeros(256, np.uint32)
+    lib().orc_canonical_codes(_p(ln), _p(out))
+    return out
+
+
+def pack(frame: Frame, kind: int, prm: Params) -> bytes:
+    """Entropy-coded bitstream of an encoded frame (kind 0 key, 1 predicted)."""
+    cap = 64 + sum(128 + 2 * int(n) + 8 for n in frame.stream_bytes)
+    out = np.zeros(cap, np.uint8)
+    n = lib().orc_pack(C.byref(frame.c), C.c_int(kind), C.c_int(frame.H), C.c_int(frame.W), C.c_int(prm.th),
+                       C.c_int(prm.tw), _p(out), C.c_uint64(cap))
+    if n == 0:
+        raise ValueError("pack failed")
+    return out[:n].tobytes()
+
+
+def unpack(data: bytes, caps=None):
+    """The four streams' bytes back from a bitstream."""
+    buf = np.frombuffer(data, np.uint8).copy()
+    if caps is None:
+        caps = [8 * len(buf) + 64] * 4     # at least one bit per symbol
+    arrs = [np.zeros(int(c), np.uint8) for c in caps]
+    ptrs = (C.c_void_p * 4)(*[_p(a).value for a in arrs])
+    capv = (C.c_uint64 * 4)(*[int(c) for c in caps])
+    nb = (C.c_uint64 * 4)()
+    if lib().orc_unpack(_p(buf), C.c_uint64(len(buf)), ptrs, capv, nb) != 0:
+        raise ValueError("malformed bitstream")
+    return [arrs[q][: nb[q]].copy() for q in range(4)]
 
 
 def huffman_bits(hist) -> int:

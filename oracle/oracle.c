@@ -394,6 +394,7 @@ enum { S_OCC = 0, S_RUN = 1, S_MASK = 2, S_RES = 3 };
 
 static void put_byte(orc_frame *f, int stream, unsigned v) {
   f->hist[stream * 256 + (v & 255u)]++;
+  if (f->sbuf[stream] && f->stream_bytes[stream] < f->scap[stream]) f->sbuf[stream][f->stream_bytes[stream]] = (uint8_t)v;
   f->stream_bytes[stream]++;
 }
 static void put_varint(orc_frame *f, uint32_t v) {   /* LEB128 */
@@ -837,6 +838,169 @@ uint64_t orc_encode_sequences(int nseq, int nf, int key_index, const float *cons
   free(fin);
   free(ranges);
   return total;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Entropy-coded bitstream: canonical Huffman codes of at most 15 bits.      */
+/* ------------------------------------------------------------------------ */
+#define PACK_MAXLEN 15
+#define PACK_MAGIC 0x31434350u   /* "PCC1" */
+
+static const uint32_t *g_sort_hist;
+static int by_count_then_symbol(const void *a, const void *b) {
+  int x = *(const int *)a, y = *(const int *)b;
+  if (g_sort_hist[x] != g_sort_hist[y]) return g_sort_hist[x] < g_sort_hist[y] ? -1 : 1;
+  return x - y;
+}
+static int by_count_desc_then_symbol(const void *a, const void *b) {
+  int x = *(const int *)a, y = *(const int *)b;
+  if (g_sort_hist[x] != g_sort_hist[y]) return g_sort_hist[x] > g_sort_hist[y] ? -1 : 1;
+  return x - y;
+}
+
+void orc_code_lengths(const uint32_t *hist, uint8_t *len) {
+  memset(len, 0, 256);
+  int sym[256], m = 0;
+  for (int i = 0; i < 256; i++)
+    if (hist[i]) sym[m++] = i;
+  if (m == 0) return;
+  if (m == 1) { len[sym[0]] = 1; return; }
+  g_sort_hist = hist;
+  qsort(sym, (size_t)m, sizeof(int), by_count_then_symbol);
+  /* two queues: leaves 0..m-1 in sorted order, internal nodes from m on */
+  uint64_t w[512];
+  int parent[512];
+  for (int i = 0; i < m; i++) w[i] = hist[sym[i]];
+  int li = 0, qh = m, qt = m;
+  for (int step = 0; step < m - 1; step++) {
+    int pick[2];
+    for (int z = 0; z < 2; z++) pick[z] = (li < m && (qh == qt || w[li] <= w[qh])) ? li++ : qh++;
+    w[qt] = w[pick[0]] + w[pick[1]];
+    parent[pick[0]] = parent[pick[1]] = qt;
+    qt++;
+  }
+  int depth[512], bl[512];
+  memset(bl, 0, sizeof(bl));
+  depth[qt - 1] = 0;
+  for (int n = qt - 2; n >= 0; n--) depth[n] = depth[parent[n]] + 1;
+  int maxl = 0;
+  for (int i = 0; i < m; i++) {
+    bl[depth[i]]++;
+    if (depth[i] > maxl) maxl = depth[i];
+  }
+  /* at most PACK_MAXLEN bits: move pairs of the deepest codes up, keeping
+   * the Kraft sum (the adjustment of JPEG, ITU T.81 Annex K.3) */
+  for (int i = maxl; i > PACK_MAXLEN; i--)
+    while (bl[i] > 0) {
+      int j = i - 2;
+      while (bl[j] == 0) j--;
+      bl[i] -= 2;
+      bl[i - 1] += 1;
+      bl[j + 1] += 2;
+      bl[j] -= 1;
+    }
+  qsort(sym, (size_t)m, sizeof(int), by_count_desc_then_symbol);
+  int L = 1;
+  for (int i = 0; i < m; i++) {
+    while (bl[L] == 0) L++;
+    len[sym[i]] = (uint8_t)L;
+    bl[L]--;
+  }
+}
+
+void orc_canonical_codes(const uint8_t *len, uint32_t *code) {
+  uint32_t next = 0;
+  memset(code, 0, 256 * sizeof(uint32_t));
+  for (int L = 1; L <= PACK_MAXLEN; L++) {
+    for (int s = 0; s < 256; s++)
+      if (len[s] == L) code[s] = next++;
+    next <<= 1;
+  }
+}
+
+static void put_u16(uint8_t *p, uint32_t v) { p[0] = (uint8_t)v; p[1] = (uint8_t)(v >> 8); }
+static void put_u32(uint8_t *p, uint32_t v) { for (int i = 0; i < 4; i++) p[i] = (uint8_t)(v >> (8 * i)); }
+static void put_u64(uint8_t *p, uint64_t v) { for (int i = 0; i < 8; i++) p[i] = (uint8_t)(v >> (8 * i)); }
+static uint32_t get_u16(const uint8_t *p) { return (uint32_t)p[0] | ((uint32_t)p[1] << 8); }
+static uint32_t get_u32(const uint8_t *p) { uint32_t v = 0; for (int i = 0; i < 4; i++) v |= (uint32_t)p[i] << (8 * i); return v; }
+static uint64_t get_u64(const uint8_t *p) { uint64_t v = 0; for (int i = 0; i < 8; i++) v |= (uint64_t)p[i] << (8 * i); return v; }
+
+/* header: magic u32, kind u8, th u8, tw u8, 0 u8, H u16, W u16,
+ * stream bytes u64[4], payload bytes u32[4], 4 zero bytes */
+uint64_t orc_pack(const orc_frame *f, int kind, int H, int W, int th, int tw, uint8_t *out, uint64_t cap) {
+  if (cap < HEADER_BYTES) return 0;
+  memset(out, 0, HEADER_BYTES);
+  put_u32(out, PACK_MAGIC);
+  out[4] = (uint8_t)kind; out[5] = (uint8_t)th; out[6] = (uint8_t)tw;
+  put_u16(out + 8, (uint32_t)H); put_u16(out + 10, (uint32_t)W);
+  uint64_t at = HEADER_BYTES;
+  for (int s = 0; s < 4; s++) {
+    const uint64_t n = f->stream_bytes[s];
+    put_u64(out + 12 + 8 * s, n);
+    if (n == 0) continue;
+    if (!f->sbuf[s] || n > f->scap[s]) return 0;
+    uint8_t len[256];
+    uint32_t code[256];
+    orc_code_lengths(f->hist + 256 * s, len);
+    orc_canonical_codes(len, code);
+    if (at + TABLE_BYTES > cap) return 0;
+    for (int i = 0; i < 128; i++) out[at + i] = (uint8_t)(len[2 * i] | (len[2 * i + 1] << 4));
+    at += TABLE_BYTES;
+    uint64_t bits = 0;
+    for (uint64_t q = 0; q < n; q++) bits += len[f->sbuf[s][q]];
+    const uint64_t pb = (bits + 7) / 8;
+    if (at + pb > cap) return 0;
+    memset(out + at, 0, pb);
+    uint64_t bp = 0;
+    for (uint64_t q = 0; q < n; q++) {
+      const int L = len[f->sbuf[s][q]];
+      const uint32_t c = code[f->sbuf[s][q]];
+      for (int b = L - 1; b >= 0; b--, bp++)
+        if ((c >> b) & 1u) out[at + bp / 8] |= (uint8_t)(0x80u >> (bp % 8));
+    }
+    put_u32(out + 44 + 4 * s, (uint32_t)pb);
+    at += pb;
+  }
+  return at;
+}
+
+int orc_unpack(const uint8_t *in, uint64_t n, uint8_t *const *streams, const uint64_t *caps, uint64_t *nbytes) {
+  if (n < HEADER_BYTES || get_u32(in) != PACK_MAGIC) return -1;
+  uint64_t at = HEADER_BYTES;
+  for (int s = 0; s < 4; s++) {
+    const uint64_t cnt = get_u64(in + 12 + 8 * s);
+    const uint64_t pb = get_u32(in + 44 + 4 * s);
+    nbytes[s] = cnt;
+    if (cnt == 0) continue;
+    if (cnt > caps[s] || at + TABLE_BYTES + pb > n) return -1;
+    uint8_t len[256];
+    for (int i = 0; i < 128; i++) { len[2 * i] = in[at + i] & 15u; len[2 * i + 1] = in[at + i] >> 4; }
+    at += TABLE_BYTES;
+    /* canonical decoding: first code and first index per length */
+    int count[PACK_MAXLEN + 2] = {0}, sorted[256], ns = 0;
+    for (int L = 1; L <= PACK_MAXLEN; L++)
+      for (int v = 0; v < 256; v++)
+        if (len[v] == L) { sorted[ns++] = v; count[L]++; }
+    const uint8_t *p = in + at;
+    uint64_t bp = 0;
+    for (uint64_t q = 0; q < cnt; q++) {
+      uint32_t code = 0, first = 0;
+      int index = 0, L;
+      for (L = 1; L <= PACK_MAXLEN; L++) {
+        if (bp >= 8 * pb) return -1;
+        code |= (p[bp / 8] >> (7 - bp % 8)) & 1u;
+        bp++;
+        if (code - first < (uint32_t)count[L]) break;
+        index += count[L];
+        first = (first + (uint32_t)count[L]) << 1;
+        code <<= 1;
+      }
+      if (L > PACK_MAXLEN) return -1;
+      streams[s][q] = (uint8_t)sorted[index + (int)(code - first)];
+    }
+    at += pb;
+  }
+  return 0;
 }
 
 int orc_num_threads(void) {

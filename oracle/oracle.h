@@ -19,6 +19,8 @@
  *                                "parity unpinned" against the paper's own numbers
  *                                (the paper prints no worked example)
  *   orc_huffman_bits             pinned (textbook heap construction, entropy bound)
+ *   orc_code_lengths, orc_pack   pinned (brute-force optimal codes on small alphabets, the
+ *                                heap cost, Kraft equality, round trips)
  *   orc_decode                   pinned (closed-form ray-plane intersection)
  */
 #ifndef PCC_ORACLE_H
@@ -84,6 +86,10 @@ typedef struct {
   int32_t range_error;             /* set if a residual cannot be coded within eps */
   /* learned plane seeding (key frames): 0 no seed, 1 seed accepted, 2 seed fell back */
   int8_t *seeded;                  /* T entries, may be NULL */
+  /* optional capture of the serialized streams' bytes, in emission order
+   * (OCC, RUN, MASK, RES; NULL = not captured; scap = capacity in bytes) */
+  uint8_t *sbuf[4];
+  uint64_t scap[4];
 } orc_frame;
 
 void orc_tables(int H, int W, const float *elev, float az0, float *cut, float *ebx, float *eby,
@@ -119,6 +125,25 @@ uint64_t orc_huffman_bits(const uint32_t *hist256);
 uint64_t orc_encode_sequences(int nseq, int nf, int key_index, const float *const *xyz,
                               const int64_t *count, const float *M, const orc_sensor *s,
                               const orc_params *prm, uint64_t *sizes, int64_t *finite_points);
+
+/* ---- entropy-coded bitstream (Sec. III-A) ----
+ * Code lengths of one stream from its byte histogram: Huffman code lengths
+ * (two-queue construction over leaves sorted by (count, symbol), ties taking
+ * the leaf), limited to 15 bits by the JPEG bit-count adjustment when the
+ * tree is deeper, then given to the symbols by (count descending, symbol
+ * ascending), shortest first.  One used symbol gets length 1. */
+void orc_code_lengths(const uint32_t *hist256, uint8_t *len256);
+/* Canonical code words (by length, then symbol), value right-aligned. */
+void orc_canonical_codes(const uint8_t *len256, uint32_t *code256);
+/* Bitstream of a frame whose streams were captured (sbuf): 64-byte header,
+ * then per non-empty stream a 128-byte table of 4-bit lengths (symbol 2i in
+ * the low nibble of byte i) and the code words MSB first, byte aligned.
+ * kind: 0 key, 1 predicted.  Returns the byte count (0 if cap is too small
+ * or a stream was not captured). */
+uint64_t orc_pack(const orc_frame *f, int kind, int H, int W, int th, int tw, uint8_t *out, uint64_t cap);
+/* Inverse of orc_pack down to the streams' bytes; nbytes[4] receives the
+ * stream lengths.  Returns 0, or -1 on a malformed or too large input. */
+int orc_unpack(const uint8_t *in, uint64_t n, uint8_t *const *streams, const uint64_t *caps, uint64_t *nbytes);
 
 int orc_num_threads(void);
 void orc_set_num_threads(int n);

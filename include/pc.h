@@ -351,6 +351,76 @@ pc_status pc_batch_destroy(pc_batch *batch);
  * errors.  Returns PC_ERR_RANGE if any frame has PC_STATUS_RANGE set. */
 pc_status pc_check(pc_ctx *ctx, void *stream, const void *const *frames, int32_t nframes);
 
+/* ---- entropy-coded bitstream (Sec. III-A) -----------------------------------
+ * The frame's four byte streams, in the order the size model counts them:
+ *   OCC  the occupancy bits, H*W/8 bytes (bit v*W+u of the little-endian
+ *        bytes: pixel (v, u) not empty);
+ *   RUN  per tile row: for a predicted frame first LEB128(count) and per
+ *        temporal run LEB128(gap), LEB128(len), FP32 c' (gap = first tile
+ *        column minus the previous run's end in the row, from 0); then for
+ *        every frame LEB128(count) and per spatial run LEB128(gap),
+ *        LEB128(len), axis u8, FP32 a, b, c (little-endian);
+ *   MASK per plane-coded tile in tile raster order, the mask bits of its
+ *        non-empty pixels (tile raster order), LSB first, byte aligned;
+ *   RES  the residual codes of the pixels no plane reproduces, frame raster
+ *        order, u16 little-endian.
+ * Each non-empty stream is coded with a canonical Huffman code limited to 15
+ * bits (Huffman construction on the counts sorted by (count, symbol), ties
+ * taking the leaf, depths limited by the bit-count adjustment of ITU T.81
+ * Annex K.3, lengths given shortest first by (count descending, symbol
+ * ascending); code words by (length, symbol)).  Container: 64-byte header
+ * (magic "PCC1" u32, kind u8 (0 key, 1 predicted), tile_h u8, tile_w u8,
+ * 0 u8, H u16, W u16, stream bytes u64[4], payload bytes u32[4], 4 zero
+ * bytes), then per non-empty stream a 128-byte table of 4-bit code lengths
+ * (symbol 2i in the low nibble of byte i) and the payload: the code words MSB
+ * first, padded to a byte.  Whenever no optimal code word exceeds 15 bits the
+ * container's size equals pc_frame_info.size_bytes. */
+
+/* Largest container of one frame (a multiple of 256 bytes). */
+size_t pc_pack_bound(const pc_sensor *sensor, const pc_params *params);
+
+/* Device workspace of pc_pack and pc_unpack for this sensor and tile shape. */
+size_t pc_pack_workspace_size(const pc_sensor *sensor, const pc_params *params);
+
+/* Pack an encoded frame stream buffer (device) into `out` (device, 4-byte
+ * aligned, cap >= pc_pack_bound bytes).  The container's byte count is
+ * written to *nbytes (device u64; 0 on an internal inconsistency).
+ * streams: NULL, or a host array of 4 device buffers (capacities in the host
+ * array stream_caps) that receive the frame's raw stream bytes.
+ * Asynchronous on `stream`; nothing is allocated. */
+pc_status pc_pack(pc_ctx *ctx, const void *frame, const pc_sensor *sensor, const pc_params *params, void *work,
+                  size_t work_bytes, void *out, uint64_t cap, uint64_t *nbytes, uint8_t *const *streams,
+                  const uint64_t *stream_caps, void *stream);
+
+/* Unpack a container (device bytes, n_in exactly its size) into a frame
+ * stream buffer that pc_decode reads: occupancy, tile classes, runs, masks
+ * and residual codes (the encoder's fit records and strip histograms are not
+ * reproduced).  A predicted frame needs its key frame's stream buffer (the
+ * temporal runs take the normals of the key frame's runs).  *kind_out (host,
+ * may be NULL) receives the frame kind.  Synchronises `stream`; returns
+ * PC_ERR_ARG on a malformed container or one for another sensor size or
+ * tile shape. */
+pc_status pc_unpack(pc_ctx *ctx, const void *data, uint64_t n_in, const void *key, const pc_sensor *sensor,
+                    const pc_params *params, void *work, size_t work_bytes, void *frame_out, int32_t *kind_out,
+                    void *stream);
+
+/* The same coder on four raw device byte streams of n[4] bytes each (below
+ * 2^28), with the header fields given; `out` needs pc_stream_pack_bound(n)
+ * bytes and `work` pc_stream_pack_workspace_size(n). */
+uint64_t pc_stream_pack_bound(const uint64_t *n);
+size_t pc_stream_pack_workspace_size(const uint64_t *n);
+pc_status pc_pack_streams(pc_ctx *ctx, const uint8_t *const *streams, const uint64_t *n, int32_t kind, int32_t H,
+                          int32_t W, int32_t tile_h, int32_t tile_w, void *work, size_t work_bytes, void *out,
+                          uint64_t cap, uint64_t *nbytes, void *stream);
+
+/* Decode a container's streams into 4 device buffers of host-given
+ * capacities; n_out (host u64[4]) receives the stream lengths.  The
+ * workspace needs pc_stream_pack_workspace_size of any sizes.  Synchronises
+ * `stream`; PC_ERR_ARG on a malformed container or a stream above its
+ * capacity. */
+pc_status pc_unpack_streams(pc_ctx *ctx, const void *data, uint64_t n_in, void *work, size_t work_bytes,
+                            uint8_t *const *streams, const uint64_t *caps, uint64_t *n_out, void *stream);
+
 /* Thread-local message for the last error returned on this thread. */
 const char *pc_last_error(void);
 

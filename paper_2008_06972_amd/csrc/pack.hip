@@ -1,0 +1,1212 @@
+// Entropy-coded bitstream of a frame (Sec. III-A) and its inverse.
+//
+// The four byte streams of a frame stream buffer (OCC, RUN, MASK, RES, in
+// the order the encoder accounts them) are each coded with a canonical
+// Huffman code limited to 15 bits.  Container: a 64-byte header (magic
+// "PCC1" u32, kind u8, tile_h u8, tile_w u8, 0 u8, H u16, W u16, stream
+// bytes u64[4], payload bytes u32[4], 4 zero bytes), then for each non-empty
+// stream a 128-byte table of 4-bit code lengths (symbol 2i in the low nibble
+// of byte i) and the code words, MSB first, padded to a byte.
+//
+// Packing: one work-group sums the per-strip histograms the encoder already
+// wrote, builds the code (sorted two-queue Huffman construction, ties going
+// to the leaf; the bit-count adjustment of ITU T.81 Annex K.3 when the tree
+// is deeper than 15; lengths handed out by descending count, then symbol)
+// and places every strip's bits from the histograms alone.  Then one
+// work-group per strip regenerates its bytes of each stream in LDS and
+// writes its code words at their known bit offsets: interior 32-bit words
+// with plain stores, words shared with a neighbour with atomicOr into a
+// container zeroed beforehand.
+//
+// Unpacking: canonical decoding by per-length limits.  Each stream's
+// payload is cut into subsequences decoded in parallel from guessed starts;
+// a subsequence whose start differs from its predecessor's end is decoded
+// again until no start changes (Huffman codes resynchronise after a few
+// code words), then every subsequence writes its symbols at the prefix of
+// the counts.  The streams are then parsed back into a frame stream buffer
+// that the decoder reads.
+#include <algorithm>
+
+#include "encode_strip.h"
+
+namespace pcc {
+namespace {
+
+constexpr int kMaxLen = 15;
+constexpr uint32_t kMagic = 0x31434350u;   // bytes "PCC1"
+constexpr int kPackBlock = 256;
+constexpr int kChunk = 16384;              // stream bytes per segment when packing raw streams
+constexpr int kUnpackBlock = 1024;
+constexpr int kMaxSub = 8192;              // decode subsequences per stream
+constexpr int kMinSubBits = 1024;
+
+struct PackPlan {
+  uint32_t hist[4][256];
+  uint32_t code[4][256];
+  uint8_t len[4][256];
+  uint8_t head[kHeaderBytes];
+  uint8_t table[4][kTableBytes];
+  uint64_t nbytes[4];       // stream bytes
+  uint64_t bits[4];         // payload bits
+  uint64_t table_at[4];     // container offset of the stream's table; its payload follows
+  uint64_t total;           // container bytes (0: does not fit)
+  uint32_t err;             // 1: capacity, 2: a strip's bytes disagree with its histogram
+  uint32_t pad;
+};
+
+struct SegInfo {
+  uint64_t bit;             // container bit of the segment's first code word
+  uint64_t byte;            // offset of the segment's first byte in its stream
+  uint32_t n;               // bytes
+  uint32_t nbits;           // code bits
+};
+
+// Per-segment histograms: segment r of stream q at base + q*stride_q + r*stride_s.
+struct HistSrc {
+  const uint32_t *base;
+  int64_t stride_q, stride_s;
+  int nseg[4];
+};
+
+struct HeadInfo {
+  int kind, th, tw, H, W;
+  int kind_from_frame;      // 1: read kind from the frame's info block
+  const pc_frame_info *info;
+};
+
+struct StreamPtrs {
+  uint8_t *p[4];
+  uint64_t cap[4];
+};
+
+struct UnpackPlan {
+  uint64_t nbytes[4];       // symbols (stream bytes)
+  uint64_t bit0[4];         // container bit of the payload
+  uint64_t nbits[4];        // payload bits (8 x payload bytes)
+  uint32_t limit[4][kMaxLen + 1];   // left-aligned end of the codes of each length
+  uint32_t first[4][kMaxLen + 1];   // first code of each length
+  uint32_t index[4][kMaxLen + 1];   // position of that code's symbol in sorted[]
+  uint8_t sorted[4][256];           // symbols by (length, symbol)
+  int32_t kind, th, tw, H, W;
+  uint32_t err;             // 1: malformed container, 2: malformed payload, 4: malformed streams
+};
+
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *red, uint32_t *total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t y = (uint32_t)__shfl_up((int)x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) red[wave] = x;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+  for (int w = 0; w < nw; w++) {
+    uint32_t r = red[w];
+    off += w < wave ? r : 0u;
+    tot += r;
+  }
+  __syncthreads();
+  if (total) *total = tot;
+  return off + x - v;
+}
+
+__device__ __forceinline__ int varint_len(uint32_t v) {
+  return v < (1u << 7) ? 1 : (v < (1u << 14) ? 2 : (v < (1u << 21) ? 3 : (v < (1u << 28) ? 4 : 5)));
+}
+__device__ __forceinline__ int put_varint(uint8_t *b, uint32_t v) {
+  int k = 0;
+  while (v >= 128u) {
+    b[k++] = (uint8_t)((v & 127u) | 128u);
+    v >>= 7;
+  }
+  b[k++] = (uint8_t)v;
+  return k;
+}
+__device__ __forceinline__ void put_f32(uint8_t *b, float x) {
+  const uint32_t u = __float_as_uint(x);
+  b[0] = (uint8_t)u;
+  b[1] = (uint8_t)(u >> 8);
+  b[2] = (uint8_t)(u >> 16);
+  b[3] = (uint8_t)(u >> 24);
+}
+
+// ------------------------------------------------------------------ the code
+// Code lengths of one stream by wavefront `q`: the wave sorts the counts,
+// lane 0 merges the two queues and derives the leaves' depths, then the
+// depth counts are limited to 15 bits.  bl[0..63] receives the number of
+// codes of each length.
+struct LenScratch {
+  uint32_t w[256];          // leaf weights, ascending
+  uint32_t nw[256];         // internal node weights
+  uint8_t lp[256];          // parent of leaf k (internal index)
+  uint8_t np[256];          // parent of internal node k
+  uint8_t dn[256];          // depth of internal node k
+  int32_t bl[64];
+};
+
+__device__ void depth_counts_wave(const uint32_t *h, LenScratch &sc, int lane) {
+  uint32_t v[4];
+#pragma unroll
+  for (int R = 0; R < 4; R++) v[R] = h[64 * R + lane];
+  wave_sort256(v, lane);
+  int zeros = 0;
+#pragma unroll
+  for (int R = 0; R < 4; R++) {
+    sc.w[64 * R + lane] = v[R];
+    zeros += __popcll(__ballot(v[R] == 0u));
+  }
+  sc.bl[lane] = 0;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  if (lane != 0) return;
+  const int m = 256 - zeros;
+  if (m == 0) return;
+  if (m == 1) {
+    sc.bl[1] = 1;
+    return;
+  }
+  int li = zeros, qh = 0, qt = 0;
+  for (int step = 0; step < m - 1; step++) {
+    uint32_t s = 0;
+    for (int z = 0; z < 2; z++) {
+      if (li < 256 && (qh == qt || sc.w[li] <= sc.nw[qh])) {     // ties take the leaf
+        s += sc.w[li];
+        sc.lp[li - zeros] = (uint8_t)qt;
+        li++;
+      } else {
+        s += sc.nw[qh];
+        sc.np[qh] = (uint8_t)qt;
+        qh++;
+      }
+    }
+    sc.nw[qt++] = s;
+  }
+  // depths top-down: the root is the last internal node
+  sc.dn[qt - 1] = 0;
+  for (int k = qt - 2; k >= 0; k--) sc.dn[k] = (uint8_t)(sc.dn[sc.np[k]] + 1);
+  int maxd = 0;
+  for (int k = 0; k < m; k++) {
+    int d = sc.dn[sc.lp[k]] + 1;
+    d = d > 63 ? 63 : d;
+    sc.bl[d]++;
+    maxd = d > maxd ? d : maxd;
+  }
+  // limit to 15 bits: a pair of the deepest codes becomes one code one
+  // level up plus, by splitting the deepest shorter code, two codes one
+  // level below that (the Kraft sum is kept)
+  for (int i = maxd; i > kMaxLen; i--) {
+    while (sc.bl[i] > 0) {
+      int j = i - 2;
+      while (j > 0 && sc.bl[j] == 0) j--;
+      if (j == 0) break;
+      sc.bl[i] -= 2;
+      sc.bl[i - 1] += 1;
+      sc.bl[j + 1] += 2;
+      sc.bl[j] -= 1;
+    }
+  }
+}
+
+// Builds the code of all four streams, the header and the tables, and the
+// bit offset of every segment.  One work-group of kPackBlock threads.
+__global__ void __launch_bounds__(kPackBlock) k_pack_plan(HistSrc hs, HeadInfo hi, PackPlan *plan, SegInfo *seg,
+                                                         int max_seg, uint64_t cap, uint64_t *nbytes_out) {
+  __shared__ uint32_t h[4][256];
+  __shared__ LenScratch sc[4];
+  __shared__ uint8_t len[4][256];
+  __shared__ uint32_t cum[4][kMaxLen + 1], first[4][kMaxLen + 1];
+  __shared__ uint64_t nb[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < 1024; e += kPackBlock) {
+    const int q = e >> 8, b = e & 255;
+    uint32_t s = 0;
+    for (int r = 0; r < hs.nseg[q]; r++) s += hs.base[q * hs.stride_q + r * hs.stride_s + b];
+    h[q][b] = s;
+    plan->hist[q][b] = s;
+  }
+  __syncthreads();
+  depth_counts_wave(h[wave], sc[wave], lane);
+  __syncthreads();
+  if (tid < 4) {
+    uint32_t c = 0, code = 0;
+    uint64_t n = 0;
+    for (int L = 1; L <= kMaxLen; L++) {
+      c += (uint32_t)sc[tid].bl[L];
+      cum[tid][L] = c;
+      first[tid][L] = code;
+      code = (code + (uint32_t)sc[tid].bl[L]) << 1;
+    }
+    for (int b = 0; b < 256; b++) n += h[tid][b];
+    nb[tid] = n;
+  }
+  __syncthreads();
+  // lengths: rank by (count descending, symbol ascending), shortest first
+  for (int e = tid; e < 1024; e += kPackBlock) {
+    const int q = e >> 8, s = e & 255;
+    const uint32_t c = h[q][s];
+    uint8_t L = 0;
+    if (c) {
+      uint32_t rank = 0;
+      for (int t = 0; t < 256; t++) {
+        const uint32_t o = h[q][t];
+        rank += (o > c || (o == c && t < s)) ? 1u : 0u;
+      }
+      L = 1;
+      while (L < kMaxLen && cum[q][L] <= rank) L++;
+    }
+    len[q][s] = L;
+    plan->len[q][s] = L;
+  }
+  __syncthreads();
+  // canonical codes: by length, then symbol
+  for (int e = tid; e < 1024; e += kPackBlock) {
+    const int q = e >> 8, s = e & 255, L = len[q][s];
+    uint32_t code = 0;
+    if (L) {
+      uint32_t k = 0;
+      for (int t = 0; t < s; t++) k += len[q][t] == L ? 1u : 0u;
+      code = first[q][L] + k;
+    }
+    plan->code[q][s] = code;
+  }
+  for (int e = tid; e < 4 * kTableBytes; e += kPackBlock) {
+    const int q = e / kTableBytes, i = e % kTableBytes;
+    plan->table[q][i] = (uint8_t)(len[q][2 * i] | (len[q][2 * i + 1] << 4));
+  }
+  // per segment: bytes and code bits (a wave per segment)
+  for (int p = wave; p < 4 * max_seg; p += kPackBlock / 64) {
+    const int q = p / max_seg, r = p % max_seg;
+    if (r >= hs.nseg[q]) continue;
+    const uint32_t *hp = hs.base + q * hs.stride_q + r * hs.stride_s;
+    uint32_t n = 0, bits = 0;
+#pragma unroll
+    for (int R = 0; R < 4; R++) {
+      const uint32_t c = hp[64 * R + lane];
+      n += c;
+      bits += c * len[q][64 * R + lane];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      n += (uint32_t)__shfl_xor((int)n, o, 64);
+      bits += (uint32_t)__shfl_xor((int)bits, o, 64);
+    }
+    if (lane == 0) {
+      seg[q * max_seg + r].n = n;
+      seg[q * max_seg + r].nbits = bits;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const int kind = hi.kind_from_frame ? hi.info->kind : hi.kind;
+    uint8_t *hd = plan->head;
+    for (int i = 0; i < kHeaderBytes; i++) hd[i] = 0;
+    for (int i = 0; i < 4; i++) hd[i] = (uint8_t)(kMagic >> (8 * i));
+    hd[4] = (uint8_t)kind;
+    hd[5] = (uint8_t)hi.th;
+    hd[6] = (uint8_t)hi.tw;
+    hd[8] = (uint8_t)hi.H;
+    hd[9] = (uint8_t)(hi.H >> 8);
+    hd[10] = (uint8_t)hi.W;
+    hd[11] = (uint8_t)(hi.W >> 8);
+    uint64_t at = kHeaderBytes;
+    for (int q = 0; q < 4; q++) {
+      uint64_t bits = 0;
+      for (int r = 0; r < hs.nseg[q]; r++) bits += seg[q * max_seg + r].nbits;
+      plan->nbytes[q] = nb[q];
+      plan->bits[q] = bits;
+      const uint64_t pb = (bits + 7) / 8;
+      for (int i = 0; i < 8; i++) hd[12 + 8 * q + i] = (uint8_t)(nb[q] >> (8 * i));
+      for (int i = 0; i < 4; i++) hd[44 + 4 * q + i] = (uint8_t)(pb >> (8 * i));
+      plan->table_at[q] = at;
+      if (nb[q] == 0) continue;
+      uint64_t bit = 8 * (at + kTableBytes), byte = 0;
+      for (int r = 0; r < hs.nseg[q]; r++) {
+        SegInfo &S = seg[q * max_seg + r];
+        S.bit = bit;
+        S.byte = byte;
+        bit += S.nbits;
+        byte += S.n;
+      }
+      at += kTableBytes + pb;
+    }
+    const bool fits = ((at + 3) & ~(uint64_t)3) <= cap;
+    plan->total = fits ? at : 0;
+    plan->err = fits ? 0u : 1u;
+    *nbytes_out = 0;
+  }
+}
+
+// Header, tables and zeroed payload words, one 32-bit word per thread.
+__global__ void __launch_bounds__(kPackBlock) k_pack_fill(const PackPlan *plan, uint32_t *out) {
+  const uint64_t total = plan->total;
+  if (plan->err || total == 0) return;
+  const uint64_t nw = (total + 3) / 4;
+  for (uint64_t w = (uint64_t)blockIdx.x * kPackBlock + threadIdx.x; w < nw; w += (uint64_t)gridDim.x * kPackBlock) {
+    uint32_t v = 0;
+    for (int j = 0; j < 4; j++) {
+      const uint64_t B = 4 * w + j;
+      uint32_t byte = 0;
+      if (B < kHeaderBytes) {
+        byte = plan->head[B];
+      } else {
+        for (int q = 0; q < 4; q++) {
+          const uint64_t t0 = plan->table_at[q];
+          if (plan->nbytes[q] && B >= t0 && B < t0 + kTableBytes) byte = plan->table[q][B - t0];
+        }
+      }
+      v |= byte << (8 * j);
+    }
+    out[w] = v;
+  }
+}
+
+// Code words of buf[0..n) from container bit `bit0`, never past `bit_end`.
+// Each thread codes a contiguous share of the bytes at the prefix of the
+// shares' bit counts.
+__device__ void encode_bytes(const uint8_t *buf, uint32_t n, uint64_t bit0, uint64_t bit_end, const uint8_t *len,
+                             const uint32_t *code, uint32_t *out, uint32_t *red, uint32_t *err) {
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  const uint32_t per = (n + nt - 1) / nt;
+  const uint32_t b0 = min(n, tid * per), b1 = min(n, b0 + per);
+  uint32_t nb = 0;
+  for (uint32_t i = b0; i < b1; i++) nb += len[buf[i]];
+  const uint32_t ex = block_excl_scan(nb, red, nullptr);
+  const uint64_t start = bit0 + ex;
+  uint64_t pos = start;
+  const uint64_t stop = min(start + nb, bit_end);
+  auto flush = [&](uint64_t w, uint32_t acc) {
+    const uint32_t v = __builtin_bswap32(acc);
+    if ((w << 5) >= start && ((w + 1) << 5) <= stop)
+      out[w] = v;
+    else
+      atomicOr(&out[w], v);
+  };
+  uint64_t cw = pos >> 5;
+  uint32_t acc = 0;
+  for (uint32_t i = b0; i < b1; i++) {
+    const uint32_t s = buf[i], L = len[s], c = code[s];
+    if (pos + L > stop) {
+      atomicOr(err, 2u);
+      break;
+    }
+    const uint32_t o = (uint32_t)(pos & 31);
+    if (o + L <= 32) {
+      acc |= c << (32 - o - L);
+      pos += L;
+      if ((pos & 31) == 0) {
+        flush(cw, acc);
+        cw++;
+        acc = 0;
+      }
+    } else {
+      const uint32_t sp = o + L - 32;
+      acc |= c >> sp;
+      flush(cw, acc);
+      cw++;
+      acc = c << (32 - sp);
+      pos += L;
+    }
+  }
+  if ((pos & 31) && pos > start) flush(cw, acc);
+}
+
+// One work-group per tile-row strip: regenerate the strip's bytes of each
+// stream from the frame stream buffer, optionally copy them out, and code
+// them.
+__global__ void __launch_bounds__(kPackBlock) k_pack_frame(FrameDev f, int th, int tw, int W, PackPlan *plan,
+                                                          const SegInfo *seg, int max_seg, uint32_t *out,
+                                                          StreamPtrs so) {
+  extern __shared__ __align__(16) char smem[];
+  uint8_t *len = (uint8_t *)smem;                        // [4][256]
+  uint32_t *code = (uint32_t *)(smem + 1024);            // [4][256]
+  uint32_t *red = code + 1024;                           // [16]
+  uint8_t *buf = (uint8_t *)(red + 16);                  // the strip's bytes of one stream
+  __shared__ int skip;
+  const int tid = threadIdx.x, tr = blockIdx.x, TC = f.TC, TR = f.TR;
+  // other strips may raise plan->err meanwhile: decide once for the group
+  if (tid == 0) skip = (plan->err & 1u) || plan->total == 0;
+  __syncthreads();
+  if (skip) return;
+  for (int e = tid; e < 1024; e += kPackBlock) {
+    len[e] = plan->len[e >> 8][e & 255];
+    code[e] = plan->code[e >> 8][e & 255];
+  }
+  const int kind = f.info->kind;
+  const int nw = th * W / 32;
+  const uint32_t *occ = f.occ + (int64_t)tr * nw;
+  const uint32_t lowm = (uint32_t)((1ull << tw) - 1ull);
+  auto valid_bits = [&](int tc) {
+    uint64_t V = 0;
+    for (int i = 0; i < th; i++) {
+      const int bit = i * W + tc * tw;
+      V |= (uint64_t)((occ[bit >> 5] >> (bit & 31)) & lowm) << (i * tw);
+    }
+    return V;
+  };
+  for (int q = 0; q < 4; q++) {
+    __syncthreads();
+    uint32_t n = 0;
+    if (q == S_OCC) {
+      for (int w = tid; w < nw; w += kPackBlock) ((uint32_t *)buf)[w] = occ[w];
+      n = 4u * (uint32_t)nw;
+    } else if (q == S_RUN) {
+      const int np = kind ? min(max(f.nruns[TR + tr], 0), TC) : 0, ns = min(max(f.nruns[tr], 0), TC);
+      const pc_prun *pr = f.pruns + (int64_t)tr * TC;
+      const pc_run *sr = f.sruns + (int64_t)tr * TC;
+      const int head0 = kind ? varint_len((uint32_t)np) : 0;
+      // temporal runs: gap, length, c'
+      const int pp = (np + kPackBlock - 1) / kPackBlock, p0 = min(np, tid * pp), p1 = min(np, p0 + pp);
+      uint32_t mine = 0;
+      for (int k = p0; k < p1; k++) {
+        const int prev = k ? pr[k - 1].s + pr[k - 1].len : 0;
+        mine += varint_len((uint32_t)(pr[k].s - prev)) + varint_len((uint32_t)pr[k].len) + 4;
+      }
+      uint32_t P;
+      uint32_t at = head0 + block_excl_scan(mine, red, &P);
+      for (int k = p0; k < p1; k++) {
+        const int prev = k ? pr[k - 1].s + pr[k - 1].len : 0;
+        at += put_varint(buf + at, (uint32_t)(pr[k].s - prev));
+        at += put_varint(buf + at, (uint32_t)pr[k].len);
+        put_f32(buf + at, pr[k].c);
+        at += 4;
+      }
+      // spatial runs: gap, length, axis, a, b, c
+      const int hs = varint_len((uint32_t)ns);
+      const int sp = (ns + kPackBlock - 1) / kPackBlock, s0 = min(ns, tid * sp), s1 = min(ns, s0 + sp);
+      mine = 0;
+      for (int k = s0; k < s1; k++) {
+        const int prev = k ? sr[k - 1].s + sr[k - 1].len : 0;
+        mine += varint_len((uint32_t)(sr[k].s - prev)) + varint_len((uint32_t)sr[k].len) + 13;
+      }
+      uint32_t S;
+      at = head0 + P + hs + block_excl_scan(mine, red, &S);
+      for (int k = s0; k < s1; k++) {
+        const int prev = k ? sr[k - 1].s + sr[k - 1].len : 0;
+        at += put_varint(buf + at, (uint32_t)(sr[k].s - prev));
+        at += put_varint(buf + at, (uint32_t)sr[k].len);
+        buf[at++] = (uint8_t)sr[k].axis;
+        put_f32(buf + at, sr[k].a);
+        put_f32(buf + at + 4, sr[k].b);
+        put_f32(buf + at + 8, sr[k].c);
+        at += 12;
+      }
+      if (tid == 0) {
+        if (kind) put_varint(buf, (uint32_t)np);
+        put_varint(buf + head0 + P, (uint32_t)ns);
+      }
+      n = head0 + P + hs + S;
+    } else if (q == S_MASK) {
+      // per plane-coded tile: its valid pixels' mask bits, LSB first
+      const int tp = (TC + kPackBlock - 1) / kPackBlock, t0 = min(TC, tid * tp), t1 = min(TC, t0 + tp);
+      uint32_t mine = 0;
+      for (int tc = t0; tc < t1; tc++) {
+        const int c = f.cls[(int64_t)tr * TC + tc];
+        if (c == CLS_SPATIAL || c == CLS_TEMPORAL) mine += (__popcll(valid_bits(tc)) + 7) >> 3;
+      }
+      uint32_t tot;
+      uint32_t at = block_excl_scan(mine, red, &tot);
+      for (int tc = t0; tc < t1; tc++) {
+        const int64_t t = (int64_t)tr * TC + tc;
+        const int c = f.cls[t];
+        if (c != CLS_SPATIAL && c != CLS_TEMPORAL) continue;
+        const uint64_t V = valid_bits(tc), M = f.mask[t];
+        uint64_t bits = 0;
+        int k = 0;
+        for (uint64_t v = V; v; v &= v - 1, k++) bits |= ((M >> __builtin_ctzll(v)) & 1ull) << k;
+        for (int b = 0; b < (k + 7) >> 3; b++) buf[at++] = (uint8_t)(bits >> (8 * b));
+      }
+      n = tot;
+    } else {
+      const int nr = min(max(f.nres[tr], 0), th * W);
+      const uint16_t *rs = f.res + (int64_t)tr * th * W;
+      for (int i = tid; i < nr; i += kPackBlock) ((uint16_t *)buf)[i] = rs[i];
+      n = 2u * (uint32_t)nr;
+    }
+    __syncthreads();
+    const SegInfo S = seg[q * max_seg + tr];
+    if (n != S.n) {
+      if (tid == 0) atomicOr(&plan->err, 2u);
+      n = min(n, S.n);
+    }
+    if (so.p[q] && S.byte + n <= so.cap[q])
+      for (uint32_t i = tid; i < n; i += kPackBlock) so.p[q][S.byte + i] = buf[i];
+    encode_bytes(buf, n, S.bit, S.bit + S.nbits, len + 256 * q, code + 256 * q, out, red, &plan->err);
+  }
+}
+
+__global__ void k_pack_done(const PackPlan *plan, uint64_t *nbytes_out) {
+  *nbytes_out = plan->err ? 0 : plan->total;
+}
+
+// Raw streams: histogram and code of each kChunk-byte segment.
+struct StreamIn {
+  const uint8_t *p[4];
+  uint64_t n[4];
+};
+
+__global__ void __launch_bounds__(kPackBlock) k_pack_hist(StreamIn in, uint32_t *seg_hist, int max_seg) {
+  __shared__ uint32_t h[256];
+  const int q = blockIdx.x / max_seg, r = blockIdx.x % max_seg, tid = threadIdx.x;
+  const uint64_t b0 = (uint64_t)r * kChunk;
+  if (b0 >= in.n[q]) return;
+  const uint32_t n = (uint32_t)min((uint64_t)kChunk, in.n[q] - b0);
+  h[tid] = 0;
+  __syncthreads();
+  for (uint32_t i = tid; i < n; i += kPackBlock) atomicAdd(&h[in.p[q][b0 + i]], 1u);
+  __syncthreads();
+  seg_hist[((int64_t)q * max_seg + r) * 256 + tid] = h[tid];
+}
+
+__global__ void __launch_bounds__(kPackBlock) k_pack_chunks(StreamIn in, PackPlan *plan, const SegInfo *seg, int max_seg,
+                                                           uint32_t *out) {
+  __shared__ uint8_t len[256];
+  __shared__ uint32_t code[256];
+  __shared__ uint32_t red[16];
+  __shared__ __align__(16) uint8_t buf[kChunk];
+  __shared__ int skip;
+  const int q = blockIdx.x / max_seg, r = blockIdx.x % max_seg, tid = threadIdx.x;
+  const uint64_t b0 = (uint64_t)r * kChunk;
+  if (tid == 0) skip = (plan->err & 1u) || plan->total == 0;
+  __syncthreads();
+  if (skip || b0 >= in.n[q]) return;
+  const uint32_t n = (uint32_t)min((uint64_t)kChunk, in.n[q] - b0);
+  len[tid] = plan->len[q][tid];
+  code[tid] = plan->code[q][tid];
+  for (uint32_t i = tid; i < n; i += kPackBlock) buf[i] = in.p[q][b0 + i];
+  __syncthreads();
+  const SegInfo S = seg[q * max_seg + r];
+  encode_bytes(buf, min(n, S.n), S.bit, S.bit + S.nbits, len, code, out, red, &plan->err);
+}
+
+// ---------------------------------------------------------------- unpacking
+__device__ __forceinline__ uint32_t rd_u32(const uint8_t *p) {
+  return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
+}
+
+// Header and code tables.  One thread; the container is small at this point
+// of the check (header and four tables).
+__global__ void k_unpack_plan(const uint8_t *in, uint64_t n_in, UnpackPlan *up, const uint64_t *caps) {
+  if (threadIdx.x != 0) return;
+  uint32_t err = 0;
+  for (int q = 0; q < 4; q++) up->nbytes[q] = up->nbits[q] = up->bit0[q] = 0;
+  if (n_in < kHeaderBytes || rd_u32(in) != kMagic) {
+    up->err = 1;
+    return;
+  }
+  up->kind = in[4];
+  up->th = in[5];
+  up->tw = in[6];
+  up->H = in[8] | (in[9] << 8);
+  up->W = in[10] | (in[11] << 8);
+  uint64_t at = kHeaderBytes;
+  for (int q = 0; q < 4 && !err; q++) {
+    uint64_t nb = 0;
+    for (int i = 0; i < 8; i++) nb |= (uint64_t)in[12 + 8 * q + i] << (8 * i);
+    const uint64_t pb = rd_u32(in + 44 + 4 * q);
+    up->nbytes[q] = nb;
+    if (nb == 0) {
+      if (pb) err = 1;
+      continue;
+    }
+    if (nb > caps[q] || at + kTableBytes + pb > n_in) {
+      err = 1;
+      break;
+    }
+    uint32_t count[kMaxLen + 1] = {0};
+    uint64_t kraft = 0;
+    int used = 0;
+    for (int s = 0; s < 256; s++) {
+      const int L = (in[at + s / 2] >> (4 * (s & 1))) & 15;
+      if (L) {
+        count[L]++;
+        kraft += 1ull << (kMaxLen - L);
+        used++;
+      }
+    }
+    // a complete code, or one symbol coded with one bit
+    if (!(kraft == (1ull << kMaxLen) || (used == 1 && count[1] == 1))) err = 1;
+    uint32_t code = 0, idx = 0;
+    for (int L = 1; L <= kMaxLen; L++) {
+      up->first[q][L] = code;
+      up->index[q][L] = idx;
+      up->limit[q][L] = (code + count[L]) << (kMaxLen - L);
+      for (int s = 0; s < 256; s++)
+        if (((in[at + s / 2] >> (4 * (s & 1))) & 15) == L) up->sorted[q][idx++] = (uint8_t)s;
+      code = (code + count[L]) << 1;
+    }
+    up->limit[q][0] = 0;
+    at += kTableBytes;
+    up->bit0[q] = 8 * at;
+    up->nbits[q] = 8 * pb;
+    at += pb;
+  }
+  if (at != n_in) err = 1;
+  up->err = err;
+}
+
+struct DecTab {
+  uint32_t limit[kMaxLen + 1], first[kMaxLen + 1], index[kMaxLen + 1];
+  uint8_t sorted[256];
+};
+
+// The code word at payload bit p: 15 bits MSB first, zeros past the end.
+__device__ __forceinline__ uint32_t peek15(const uint8_t *pay, uint64_t nbytes, uint64_t p) {
+  const uint64_t B = p >> 3;
+  uint32_t x = 0;
+#pragma unroll
+  for (int j = 0; j < 3; j++) x = (x << 8) | (B + j < nbytes ? pay[B + j] : 0u);
+  return ((x << (p & 7)) >> 9) & 0x7fffu;
+}
+
+__device__ __forceinline__ int code_len(const DecTab &t, uint32_t win, uint32_t *bad) {
+  int L = 1;
+  while (L <= kMaxLen && win >= t.limit[L]) L++;
+  if (L > kMaxLen) {
+    *bad = 1;
+    return 1;
+  }
+  return L;
+}
+
+// Decodes subsequence j from payload bit `s`: code words starting before
+// min((j + 1) S, nbits).  Returns the end bit and the code word count.
+__device__ __forceinline__ void decode_sub(const DecTab &t, const uint8_t *pay, uint64_t pbytes, uint64_t lim, uint64_t s,
+                                           uint64_t *end, uint32_t *cnt, uint32_t *bad) {
+  uint64_t p = s;
+  uint32_t c = 0;
+  while (p < lim) {
+    p += code_len(t, peek15(pay, pbytes, p), bad);
+    c++;
+  }
+  *end = p;
+  *cnt = c;
+}
+
+// One work-group per stream.
+__global__ void __launch_bounds__(kUnpackBlock) k_unpack_streams(const uint8_t *in, UnpackPlan *up, uint64_t *sub,
+                                                                uint32_t *subc, StreamPtrs outp) {
+  __shared__ DecTab t;
+  __shared__ uint32_t red[16];
+  __shared__ int any, skip;
+  const int q = blockIdx.x, tid = threadIdx.x;
+  // other streams may raise up->err meanwhile: decide once for the group
+  if (tid == 0) skip = (up->err & 1u) != 0;
+  __syncthreads();
+  if (skip) return;
+  const uint64_t n = up->nbytes[q], nbits = up->nbits[q];
+  if (n == 0) return;
+  for (int L = tid; L <= kMaxLen; L += kUnpackBlock) {
+    t.limit[L] = up->limit[q][L];
+    t.first[L] = up->first[q][L];
+    t.index[L] = up->index[q][L];
+  }
+  for (int s = tid; s < 256; s += kUnpackBlock) t.sorted[s] = up->sorted[q][s];
+  __syncthreads();
+  const uint8_t *pay = in + up->bit0[q] / 8;
+  const uint64_t pbytes = nbits / 8;
+  uint64_t S = (nbits + kMaxSub - 1) / kMaxSub;
+  S = S < kMinSubBits ? kMinSubBits : S;
+  const uint32_t m = (uint32_t)((nbits + S - 1) / S);
+  uint64_t *st = sub + (int64_t)q * 2 * kMaxSub, *en = st + kMaxSub;
+  uint32_t *cnt = subc + (int64_t)q * kMaxSub;
+  const uint32_t per = (m + kUnpackBlock - 1) / kUnpackBlock;
+  const uint32_t j0 = min(m, tid * per), j1 = min(m, j0 + per);
+  uint32_t bad = 0;
+  for (uint32_t j = j0; j < j1; j++) {
+    st[j] = (uint64_t)j * S;
+    decode_sub(t, pay, pbytes, min((uint64_t)(j + 1) * S, nbits), st[j], &en[j], &cnt[j], &bad);
+  }
+  // a start that differs from its predecessor's end is decoded again; the
+  // verified prefix grows by at least one thread's share per round
+  for (uint32_t round = 0; round <= kUnpackBlock; round++) {
+    __syncthreads();
+    const uint64_t snap = (j0 > 0 && j0 < j1) ? en[j0 - 1] : 0;
+    if (tid == 0) any = 0;
+    __syncthreads();
+    int changed = 0;
+    for (uint32_t j = j0; j < j1; j++) {
+      const uint64_t s = j == 0 ? 0 : (j == j0 ? snap : en[j - 1]);
+      if (s != st[j]) {
+        st[j] = s;
+        decode_sub(t, pay, pbytes, min((uint64_t)(j + 1) * S, nbits), s, &en[j], &cnt[j], &bad);
+        changed = 1;
+      }
+    }
+    if (changed) any = 1;
+    __syncthreads();
+    if (!any) break;
+  }
+  uint32_t mine = 0;
+  for (uint32_t j = j0; j < j1; j++) mine += cnt[j];
+  uint32_t total;
+  uint64_t idx = block_excl_scan(mine, red, &total);
+  uint8_t *out = outp.p[q];
+  for (uint32_t j = j0; j < j1; j++) {
+    uint64_t p = st[j];
+    const uint64_t lim = min((uint64_t)(j + 1) * S, nbits);
+    while (p < lim) {
+      const uint32_t win = peek15(pay, pbytes, p);
+      const int L = code_len(t, win, &bad);
+      if (idx < n) out[idx] = t.sorted[t.index[L] + ((win >> (kMaxLen - L)) - t.first[L])];
+      idx++;
+      p += L;
+    }
+  }
+  if (tid == 0 && total < n) bad = 1;
+  if (bad) atomicOr(&up->err, 2u);
+}
+
+// Streams back into a frame stream buffer: occupancy words, runs and tile
+// classes, masks, residual codes per strip.  One work-group.
+__global__ void __launch_bounds__(kUnpackBlock) k_unpack_frame(UnpackPlan *up, StreamPtrs sp, FrameDev f,
+                                                              FrameDev key, int has_key, int th, int tw, int W) {
+  __shared__ uint32_t red[16];
+  __shared__ uint32_t err;
+  __shared__ uint32_t nres[256];
+  __shared__ uint32_t base;
+  if (up->err) return;
+  const int tid = threadIdx.x, TR = f.TR, TC = f.TC, T = f.T, H = TR * th;
+  const int kind = up->kind;
+  if (tid == 0) err = 0;
+  const int64_t nw = (int64_t)H * W / 32;
+  if (up->nbytes[S_OCC] != (uint64_t)nw * 4 || up->nbytes[S_RES] % 2) {
+    if (tid == 0) atomicOr(&up->err, 4u);
+    return;
+  }
+  const uint8_t *ob = sp.p[S_OCC];
+  for (int64_t w = tid; w < nw; w += kUnpackBlock) f.occ[w] = rd_u32(ob + 4 * w);
+  __syncthreads();
+  const uint32_t lowm = (uint32_t)((1ull << tw) - 1ull);
+  auto valid_bits = [&](int64_t t) {
+    const int tr = (int)(t / TC), tc = (int)(t % TC);
+    const uint32_t *occ = f.occ + (int64_t)tr * (th * W / 32);
+    uint64_t V = 0;
+    for (int i = 0; i < th; i++) {
+      const int bit = i * W + tc * tw;
+      V |= (uint64_t)((occ[bit >> 5] >> (bit & 31)) & lowm) << (i * tw);
+    }
+    return V;
+  };
+  for (int64_t t = tid; t < T; t += kUnpackBlock) {
+    f.cls[t] = valid_bits(t) ? CLS_UNFIT : CLS_EMPTY;
+    f.run_of[t] = -1;
+    f.mask[t] = 0;
+  }
+  __syncthreads();
+  // runs of each tile row, in stream order (one thread: variable-length)
+  if (tid == 0) {
+    const uint8_t *R = sp.p[S_RUN];
+    const uint64_t n = up->nbytes[S_RUN];
+    uint64_t p = 0;
+    uint32_t bad = 0;
+    auto byte = [&]() -> uint32_t {
+      if (p >= n) {
+        bad = 1;
+        return 0u;
+      }
+      return R[p++];
+    };
+    auto varint = [&]() -> uint32_t {
+      uint32_t v = 0;
+      for (int sh = 0; sh < 35; sh += 7) {
+        const uint32_t b = byte();
+        v |= (b & 127u) << sh;
+        if (!(b & 128u)) return v;
+      }
+      bad = 1;
+      return v;
+    };
+    auto f32 = [&]() -> float {
+      uint32_t u = byte();
+      u |= byte() << 8;
+      u |= byte() << 16;
+      u |= byte() << 24;
+      return __uint_as_float(u);
+    };
+    int nsr = 0, npr = 0;
+    for (int tr = 0; tr < TR && !bad; tr++) {
+      int np = 0;
+      if (kind) {
+        np = (int)varint();
+        if (np > TC) bad = 1;
+        int prev = 0;
+        for (int k = 0; k < np && !bad; k++) {
+          const uint32_t gap = varint(), len = varint();
+          const float c = f32();
+          if (gap > (uint32_t)TC || len < 1 || len > (uint32_t)TC || prev + (int)gap + (int)len > TC) {
+            bad = 1;
+            break;
+          }
+          const int s = prev + (int)gap;
+          const int64_t t0 = (int64_t)tr * TC + s;
+          const int kr = has_key ? key.run_of[t0] : -1;
+          if (kr < 0 || kr >= T) {
+            bad = 1;
+            break;
+          }
+          f.pruns[(int64_t)tr * TC + k] = pc_prun{s, (int)len, kr, c};
+          for (int e = 0; e < (int)len; e++) {
+            f.cls[t0 + e] = CLS_TEMPORAL;
+            f.run_of[t0 + e] = T + tr * TC + k;
+          }
+          prev = s + (int)len;
+        }
+      }
+      f.nruns[TR + tr] = np;
+      npr += np;
+      const int ns = (int)varint();
+      if (ns > TC) bad = 1;
+      int prev = 0;
+      for (int k = 0; k < ns && !bad; k++) {
+        const uint32_t gap = varint(), len = varint(), axis = byte();
+        const float a = f32(), b = f32(), c = f32();
+        if (gap > (uint32_t)TC || len < 1 || len > (uint32_t)TC || prev + (int)gap + (int)len > TC || axis > 2) {
+          bad = 1;
+          break;
+        }
+        const int s = prev + (int)gap;
+        const int64_t t0 = (int64_t)tr * TC + s;
+        f.sruns[(int64_t)tr * TC + k] = pc_run{s, (int)len, (int)axis, a, b, c};
+        for (int e = 0; e < (int)len; e++) {
+          if (f.cls[t0 + e] == CLS_TEMPORAL) bad = 1;
+          f.cls[t0 + e] = CLS_SPATIAL;
+          f.run_of[t0 + e] = tr * TC + k;
+        }
+        prev = s + (int)len;
+      }
+      f.nruns[tr] = ns;
+      nsr += ns;
+    }
+    if (p != n) bad = 1;
+    if (bad) err |= 4u;
+    for (int i = 0; i < (int)sizeof(pc_frame_info); i++) ((uint8_t *)f.info)[i] = 0;
+    f.info->kind = kind;
+    f.info->status = 0;
+    f.info->n_sruns = nsr;
+    f.info->n_pruns = npr;
+    for (int q = 0; q < 4; q++) f.info->stream_bytes[q] = up->nbytes[q];
+  }
+  __syncthreads();
+  if (err) {
+    if (tid == 0) atomicOr(&up->err, err);
+    return;
+  }
+  // masks of the plane-coded tiles, in tile order
+  const uint8_t *Mb = sp.p[S_MASK];
+  const uint64_t nmask = up->nbytes[S_MASK];
+  if (tid == 0) base = 0;
+  for (int64_t c0 = 0; c0 < T; c0 += kUnpackBlock) {
+    __syncthreads();
+    const int64_t t = c0 + tid;
+    uint64_t V = 0;
+    uint32_t nb = 0;
+    bool cov = false;
+    if (t < T) {
+      const int c = f.cls[t];
+      cov = c == CLS_SPATIAL || c == CLS_TEMPORAL;
+      if (cov) {
+        V = valid_bits(t);
+        nb = (__popcll(V) + 7) >> 3;
+      }
+    }
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan(nb, red, &tot);
+    const uint64_t at = (uint64_t)base + ex;
+    if (cov) {
+      if (at + nb > nmask) {
+        atomicOr(&err, 4u);
+      } else {
+        uint64_t bits = 0;
+        for (uint32_t b = 0; b < nb; b++) bits |= (uint64_t)Mb[at + b] << (8 * b);
+        uint64_t M = 0;
+        int k = 0;
+        for (uint64_t v = V; v; v &= v - 1, k++) M |= ((bits >> k) & 1ull) << __builtin_ctzll(v);
+        f.mask[t] = M;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) base += tot;
+  }
+  __syncthreads();
+  if (tid == 0 && base != nmask) err |= 4u;
+  // residual codes: uncovered valid pixels of each strip, raster order
+  for (int r = tid; r < TR; r += kUnpackBlock) nres[r] = 0;
+  __syncthreads();
+  for (int64_t t = tid; t < T; t += kUnpackBlock) {
+    const uint32_t c = (uint32_t)__popcll(valid_bits(t) & ~f.mask[t]);
+    if (c) atomicAdd(&nres[t / TC], c);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t s = 0;
+    for (int r = 0; r < TR; r++) {
+      const uint32_t c = nres[r];
+      f.nres[r] = (int32_t)c;
+      nres[r] = s;
+      s += c;
+    }
+    if ((uint64_t)s * 2 != up->nbytes[S_RES]) err |= 4u;
+    f.info->n_res = s;
+  }
+  __syncthreads();
+  if (err) {
+    if (tid == 0) atomicOr(&up->err, err);
+    return;
+  }
+  const uint8_t *Rb = sp.p[S_RES];
+  for (int r = 0; r < TR; r++) {
+    const int c = f.nres[r];
+    const uint32_t b = nres[r];
+    uint16_t *dst = f.res + (int64_t)r * th * W;
+    for (int i = tid; i < c; i += kUnpackBlock) dst[i] = (uint16_t)(Rb[2 * (b + i)] | (Rb[2 * (b + i) + 1] << 8));
+  }
+}
+
+// ------------------------------------------------------------------ sizing
+size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct FrameCaps {
+  uint64_t c[4];
+};
+FrameCaps frame_caps(const pc_layout &L) {
+  FrameCaps k;
+  k.c[S_OCC] = (uint64_t)L.H * L.W / 8;
+  k.c[S_RUN] = (uint64_t)L.TR * (4 + 17 * (uint64_t)L.TC);
+  k.c[S_MASK] = 8 * (uint64_t)L.T;
+  k.c[S_RES] = 2 * (uint64_t)L.H * L.W;
+  return k;
+}
+uint64_t bound_of(const uint64_t *n) {
+  uint64_t b = kHeaderBytes;
+  for (int q = 0; q < 4; q++)
+    if (n[q]) b += kTableBytes + (kMaxLen * n[q] + 7) / 8;
+  return (b + 255) & ~(uint64_t)255;
+}
+size_t pack_ws(int max_seg, bool raw) {
+  size_t b = a256(sizeof(PackPlan)) + a256(sizeof(SegInfo) * 4 * (size_t)max_seg);
+  if (raw) b += a256(sizeof(uint32_t) * 256 * 4 * (size_t)max_seg);
+  return b;
+}
+size_t unpack_ws() {
+  return a256(sizeof(UnpackPlan)) + a256(sizeof(uint64_t) * 8 * kMaxSub) + a256(sizeof(uint32_t) * 4 * kMaxSub) +
+         a256(sizeof(uint64_t) * 4);
+}
+size_t frame_ws(const pc_layout &L) {
+  FrameCaps k = frame_caps(L);
+  size_t u = unpack_ws();
+  for (int q = 0; q < 4; q++) u += a256(k.c[q]);
+  size_t p = pack_ws(L.TR, false);
+  return p > u ? p : u;
+}
+int raw_segs(const uint64_t *n) {
+  uint64_t m = 1;
+  for (int q = 0; q < 4; q++) {
+    uint64_t s = (n[q] + kChunk - 1) / kChunk;
+    m = s > m ? s : m;
+  }
+  return (int)m;
+}
+
+// Decode the streams of a container into `outp` (device).  Synchronises.
+pc_status unpack_to_streams(const uint8_t *in, uint64_t n_in, char *ws, const uint64_t *caps, const StreamPtrs &outp,
+                            UnpackPlan *host, hipStream_t st) {
+  UnpackPlan *up = (UnpackPlan *)ws;
+  char *w = ws + a256(sizeof(UnpackPlan));
+  uint64_t *sub = (uint64_t *)w;
+  w += a256(sizeof(uint64_t) * 8 * kMaxSub);
+  uint32_t *subc = (uint32_t *)w;
+  w += a256(sizeof(uint32_t) * 4 * kMaxSub);
+  uint64_t *dcaps = (uint64_t *)w;
+  if (hipMemcpyAsync(dcaps, caps, sizeof(uint64_t) * 4, hipMemcpyHostToDevice, st) != hipSuccess)
+    return set_error(PC_ERR_DEVICE, "caps upload failed");
+  hipLaunchKernelGGL(k_unpack_plan, dim3(1), dim3(64), 0, st, in, n_in, up, (const uint64_t *)dcaps);
+  hipLaunchKernelGGL(k_unpack_streams, dim3(4), dim3(kUnpackBlock), 0, st, in, up, sub, subc, outp);
+  if (hipGetLastError() != hipSuccess) return set_error(PC_ERR_DEVICE, "unpack launch failed");
+  if (hipMemcpyAsync(host, up, sizeof(UnpackPlan), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return set_error(PC_ERR_DEVICE, "unpack read-back failed");
+  if (host->err & 1u) return set_error(PC_ERR_ARG, "malformed container (header, tables or sizes)");
+  if (host->err) return set_error(PC_ERR_ARG, "malformed payload");
+  return PC_OK;
+}
+
+}  // namespace
+}  // namespace pcc
+
+using namespace pcc;
+
+extern "C" {
+
+size_t pc_pack_bound(const pc_sensor *sensor, const pc_params *params) {
+  pc_layout L;
+  if (pc_stream_layout(sensor, params, &L) != PC_OK) return 0;
+  FrameCaps k = frame_caps(L);
+  return bound_of(k.c);
+}
+
+size_t pc_pack_workspace_size(const pc_sensor *sensor, const pc_params *params) {
+  pc_layout L;
+  if (pc_stream_layout(sensor, params, &L) != PC_OK) return 0;
+  return frame_ws(L);
+}
+
+pc_status pc_pack(pc_ctx *ctx, const void *frame, const pc_sensor *sensor, const pc_params *params, void *work,
+                  size_t work_bytes, void *out, uint64_t cap, uint64_t *nbytes, uint8_t *const *streams,
+                  const uint64_t *stream_caps, void *stream) {
+  if (!ctx) return set_error(PC_ERR_ARG, "ctx is NULL");
+  pc_layout L;
+  pc_status stt = pc_stream_layout(sensor, params, &L);
+  if (stt) return stt;
+  if (!frame || !out || !nbytes || !work) return set_error(PC_ERR_ARG, "frame, output, size or workspace is NULL");
+  if ((uintptr_t)out & 3) return set_error(PC_ERR_ARG, "output must be 4-byte aligned");
+  if (L.TR > 1024) return set_error(PC_ERR_UNSUPPORTED, "more than 1024 tile rows");
+  if (work_bytes < frame_ws(L)) return set_error(PC_ERR_CAPACITY, "workspace %zu bytes < %zu", work_bytes, frame_ws(L));
+  if (cap < pc_pack_bound(sensor, params))
+    return set_error(PC_ERR_CAPACITY, "output %llu bytes < bound %zu", (unsigned long long)cap, pc_pack_bound(sensor, params));
+  if (streams && !stream_caps) return set_error(PC_ERR_ARG, "stream capacities are NULL");
+  hipStream_t st = (hipStream_t)stream;
+  FrameDev f = frame_dev((void *)frame, L);
+  char *ws = (char *)work;
+  PackPlan *plan = (PackPlan *)ws;
+  SegInfo *seg = (SegInfo *)(ws + a256(sizeof(PackPlan)));
+  HistSrc hs;
+  hs.base = f.strip;
+  hs.stride_q = 256;
+  hs.stride_s = PC_STRIP_WORDS;
+  for (int q = 0; q < 4; q++) hs.nseg[q] = L.TR;
+  HeadInfo hi{0, L.th, L.tw, L.H, L.W, 1, f.info};
+  StreamPtrs so{};
+  for (int q = 0; q < 4; q++) {
+    so.p[q] = streams ? streams[q] : nullptr;
+    so.cap[q] = streams ? stream_caps[q] : 0;
+  }
+  hipLaunchKernelGGL(k_pack_plan, dim3(1), dim3(kPackBlock), 0, st, hs, hi, plan, seg, L.TR, (uint64_t)cap, nbytes);
+  const int fill_blocks = (int)std::min<uint64_t>(2048, (cap / 4 + kPackBlock - 1) / kPackBlock);
+  hipLaunchKernelGGL(k_pack_fill, dim3(fill_blocks), dim3(kPackBlock), 0, st, (const PackPlan *)plan, (uint32_t *)out);
+  const size_t sh = 1024 + 4 * 1024 + 64 + 2 * (size_t)L.th * L.W + 64;
+  if (hipFuncSetAttribute((const void *)k_pack_frame, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh) != hipSuccess)
+    return set_error(PC_ERR_DEVICE, "pack shared-memory attribute failed");
+  hipLaunchKernelGGL(k_pack_frame, dim3(L.TR), dim3(kPackBlock), sh, st, f, L.th, L.tw, L.W, plan, (const SegInfo *)seg,
+                     L.TR, (uint32_t *)out, so);
+  hipLaunchKernelGGL(k_pack_done, dim3(1), dim3(1), 0, st, (const PackPlan *)plan, nbytes);
+  hipError_t he = hipGetLastError();
+  if (he != hipSuccess) return set_error(PC_ERR_DEVICE, "pack launch failed: %s", hipGetErrorString(he));
+  return PC_OK;
+}
+
+size_t pc_stream_pack_workspace_size(const uint64_t *n) {
+  if (!n) return 0;
+  size_t p = pack_ws(raw_segs(n), true), u = unpack_ws();
+  return p > u ? p : u;
+}
+
+uint64_t pc_stream_pack_bound(const uint64_t *n) { return n ? bound_of(n) : 0; }
+
+pc_status pc_pack_streams(pc_ctx *ctx, const uint8_t *const *streams, const uint64_t *n, int32_t kind, int32_t H,
+                          int32_t W, int32_t tile_h, int32_t tile_w, void *work, size_t work_bytes, void *out, uint64_t cap,
+                          uint64_t *nbytes, void *stream) {
+  if (!ctx) return set_error(PC_ERR_ARG, "ctx is NULL");
+  if (!streams || !n || !work || !out || !nbytes) return set_error(PC_ERR_ARG, "NULL argument");
+  if ((uintptr_t)out & 3) return set_error(PC_ERR_ARG, "output must be 4-byte aligned");
+  if (kind < 0 || kind > 255 || tile_h < 0 || tile_h > 255 || tile_w < 0 || tile_w > 255 || H < 0 || H > 65535 || W < 0 ||
+      W > 65535)
+    return set_error(PC_ERR_ARG, "header field out of range");
+  for (int q = 0; q < 4; q++) {
+    if (n[q] && !streams[q]) return set_error(PC_ERR_ARG, "stream %d is NULL", q);
+    if (n[q] >= (1ull << 28)) return set_error(PC_ERR_UNSUPPORTED, "stream %d longer than 2^28 bytes", q);
+  }
+  const int max_seg = raw_segs(n);
+  if (work_bytes < pc_stream_pack_workspace_size(n)) return set_error(PC_ERR_CAPACITY, "workspace too small");
+  if (cap < bound_of(n)) return set_error(PC_ERR_CAPACITY, "output smaller than the bound");
+  hipStream_t st = (hipStream_t)stream;
+  char *ws = (char *)work;
+  PackPlan *plan = (PackPlan *)ws;
+  SegInfo *seg = (SegInfo *)(ws + a256(sizeof(PackPlan)));
+  uint32_t *seg_hist = (uint32_t *)(ws + a256(sizeof(PackPlan)) + a256(sizeof(SegInfo) * 4 * (size_t)max_seg));
+  StreamIn in;
+  HistSrc hs;
+  for (int q = 0; q < 4; q++) {
+    in.p[q] = streams[q];
+    in.n[q] = n[q];
+    hs.nseg[q] = (int)((n[q] + kChunk - 1) / kChunk);
+  }
+  hs.base = seg_hist;
+  hs.stride_q = 256 * (int64_t)max_seg;
+  hs.stride_s = 256;
+  HeadInfo hi{kind, tile_h, tile_w, H, W, 0, nullptr};
+  hipLaunchKernelGGL(k_pack_hist, dim3(4 * max_seg), dim3(kPackBlock), 0, st, in, seg_hist, max_seg);
+  hipLaunchKernelGGL(k_pack_plan, dim3(1), dim3(kPackBlock), 0, st, hs, hi, plan, seg, max_seg, (uint64_t)cap, nbytes);
+  const int fill_blocks = (int)std::min<uint64_t>(2048, (cap / 4 + kPackBlock - 1) / kPackBlock);
+  hipLaunchKernelGGL(k_pack_fill, dim3(fill_blocks), dim3(kPackBlock), 0, st, (const PackPlan *)plan, (uint32_t *)out);
+  hipLaunchKernelGGL(k_pack_chunks, dim3(4 * max_seg), dim3(kPackBlock), 0, st, in, plan, (const SegInfo *)seg, max_seg,
+                     (uint32_t *)out);
+  hipLaunchKernelGGL(k_pack_done, dim3(1), dim3(1), 0, st, (const PackPlan *)plan, nbytes);
+  hipError_t he = hipGetLastError();
+  if (he != hipSuccess) return set_error(PC_ERR_DEVICE, "pack launch failed: %s", hipGetErrorString(he));
+  return PC_OK;
+}
+
+pc_status pc_unpack_streams(pc_ctx *ctx, const void *data, uint64_t n_in, void *work, size_t work_bytes,
+                            uint8_t *const *streams, const uint64_t *caps, uint64_t *n_out, void *stream) {
+  if (!ctx) return set_error(PC_ERR_ARG, "ctx is NULL");
+  if (!data || !work || !streams || !caps || !n_out) return set_error(PC_ERR_ARG, "NULL argument");
+  if (work_bytes < unpack_ws()) return set_error(PC_ERR_CAPACITY, "workspace too small");
+  StreamPtrs o{};
+  for (int q = 0; q < 4; q++) {
+    o.p[q] = streams[q];
+    o.cap[q] = caps[q];
+    if (caps[q] && !streams[q]) return set_error(PC_ERR_ARG, "stream %d is NULL", q);
+  }
+  UnpackPlan h;
+  pc_status s = unpack_to_streams((const uint8_t *)data, n_in, (char *)work, caps, o, &h, (hipStream_t)stream);
+  for (int q = 0; q < 4; q++) n_out[q] = s == PC_OK ? h.nbytes[q] : 0;
+  return s;
+}
+
+pc_status pc_unpack(pc_ctx *ctx, const void *data, uint64_t n_in, const void *key, const pc_sensor *sensor,
+                    const pc_params *params, void *work, size_t work_bytes, void *frame_out, int32_t *kind_out,
+                    void *stream) {
+  if (!ctx) return set_error(PC_ERR_ARG, "ctx is NULL");
+  pc_layout L;
+  pc_status stt = pc_stream_layout(sensor, params, &L);
+  if (stt) return stt;
+  if (!data || !work || !frame_out) return set_error(PC_ERR_ARG, "data, workspace or frame is NULL");
+  if (key == frame_out) return set_error(PC_ERR_ARG, "output frame must differ from the key frame");
+  if (L.TR > 256) return set_error(PC_ERR_UNSUPPORTED, "more than 256 tile rows");
+  if (work_bytes < frame_ws(L)) return set_error(PC_ERR_CAPACITY, "workspace too small");
+  hipStream_t st = (hipStream_t)stream;
+  FrameCaps k = frame_caps(L);
+  char *ws = (char *)work;
+  StreamPtrs sp{};
+  char *w = ws + unpack_ws();
+  for (int q = 0; q < 4; q++) {
+    sp.p[q] = (uint8_t *)w;
+    sp.cap[q] = k.c[q];
+    w += a256(k.c[q]);
+  }
+  UnpackPlan h;
+  pc_status s = unpack_to_streams((const uint8_t *)data, n_in, ws, k.c, sp, &h, st);
+  if (s) return s;
+  if (h.H != L.H || h.W != L.W || h.th != L.th || h.tw != L.tw)
+    return set_error(PC_ERR_ARG, "container is %dx%d with %dx%d tiles; sensor and params give %dx%d with %dx%d", h.H, h.W,
+                     h.th, h.tw, L.H, L.W, L.th, L.tw);
+  if (h.kind != 0 && h.kind != 1) return set_error(PC_ERR_ARG, "unknown frame kind %d", h.kind);
+  if (h.kind == 1 && !key) return set_error(PC_ERR_ARG, "a predicted frame needs its key frame");
+  FrameDev f = frame_dev(frame_out, L);
+  FrameDev kf = key ? frame_dev((void *)key, L) : f;
+  hipLaunchKernelGGL(k_unpack_frame, dim3(1), dim3(kUnpackBlock), 0, st, (UnpackPlan *)ws, sp, f, kf, key ? 1 : 0,
+                     L.th, L.tw, L.W);
+  uint32_t err = 0;
+  if (hipGetLastError() != hipSuccess ||
+      hipMemcpyAsync(&err, &((UnpackPlan *)ws)->err, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return set_error(PC_ERR_DEVICE, "unpack launch failed");
+  if (err) return set_error(PC_ERR_ARG, "malformed streams (runs, masks or residual count)");
+  if (kind_out) *kind_out = h.kind;
+  return PC_OK;
+}
+
+}  // extern "C"

@@ -87,10 +87,15 @@ def lib():
         for name in ("pc_stream_layout", "pc_ctx_create", "pc_ctx_destroy", "pc_sensor_register", "pc_sensor_tables",
                      "pc_project", "pc_fit_key", "pc_encode_pred", "pc_decode", "pc_check", "pc_batch_create",
                      "pc_batch_run", "pc_batch_info", "pc_batch_profile", "pc_batch_destroy", "pc_net_forward",
-                     "pc_net_backward", "pc_net_loss", "pc_net_adam"):
+                     "pc_net_backward", "pc_net_loss", "pc_net_adam", "pc_pack", "pc_unpack", "pc_pack_streams",
+                     "pc_unpack_streams"):
             getattr(L, name).restype = C.c_int
         L.pc_batch_workspace_size.restype = C.c_size_t
         L.pc_net_workspace_size.restype = C.c_size_t
+        L.pc_pack_bound.restype = C.c_size_t
+        L.pc_pack_workspace_size.restype = C.c_size_t
+        L.pc_stream_pack_bound.restype = C.c_uint64
+        L.pc_stream_pack_workspace_size.restype = C.c_size_t
         _lib = L
     return _lib
 
@@ -99,7 +104,9 @@ EXPORTED = ("pc_stream_layout", "pc_workspace_size", "pc_ctx_create", "pc_ctx_de
             "pc_sensor_tables", "pc_project", "pc_fit_key", "pc_encode_pred", "pc_decode", "pc_check",
             "pc_last_error", "pc_version", "pc_batch_workspace_size", "pc_batch_create", "pc_batch_run",
             "pc_batch_info", "pc_batch_profile", "pc_batch_destroy", "pc_net_workspace_size", "pc_net_forward",
-            "pc_net_backward", "pc_net_loss", "pc_net_adam")
+            "pc_net_backward", "pc_net_loss", "pc_net_adam", "pc_pack_bound", "pc_pack_workspace_size", "pc_pack",
+            "pc_unpack", "pc_stream_pack_bound", "pc_stream_pack_workspace_size", "pc_pack_streams",
+            "pc_unpack_streams")
 PC_NET_PARAMS = 15636
 LAUNCH_KINDS = {0: "reset", 1: "count", 2: "offsets", 3: "scatter", 4: "key", 5: "pred", 6: "finish",
                 7: "keyimage", 8: "net"}
@@ -270,6 +277,60 @@ def pc_batch_profile(batch, stream=None, cap=64):
 
 def pc_batch_destroy(batch):
     _check(lib().pc_batch_destroy(batch))
+
+
+def _u64x4(n):
+    return (C.c_uint64 * 4)(*[int(x) for x in n])
+
+
+def _ptrx4(ps):
+    return (C.c_void_p * 4)(*[(_ptr(p).value if p is not None else None) for p in ps])
+
+
+def pc_pack_bound(sensor: Sensor, prm: pc_params) -> int:
+    return int(lib().pc_pack_bound(C.byref(sensor.c), C.byref(prm)))
+
+
+def pc_pack_workspace_size(sensor: Sensor, prm: pc_params) -> int:
+    return int(lib().pc_pack_workspace_size(C.byref(sensor.c), C.byref(prm)))
+
+
+def pc_pack(ctx, frame, sensor: Sensor, prm: pc_params, work, work_bytes: int, out, cap: int, nbytes, streams=None,
+            stream_caps=None, stream=None):
+    sp = _ptrx4(streams) if streams is not None else None
+    sc = _u64x4(stream_caps) if stream_caps is not None else None
+    _check(lib().pc_pack(ctx, _ptr(frame), C.byref(sensor.c), C.byref(prm), _ptr(work), C.c_size_t(work_bytes),
+                         _ptr(out), C.c_uint64(cap), _ptr(nbytes), sp, sc, _stream(stream)))
+
+
+def pc_unpack(ctx, data, n_in: int, key, sensor: Sensor, prm: pc_params, work, work_bytes: int, frame_out,
+              stream=None) -> int:
+    kind = C.c_int32(-1)
+    _check(lib().pc_unpack(ctx, _ptr(data), C.c_uint64(n_in), _ptr(key), C.byref(sensor.c), C.byref(prm), _ptr(work),
+                           C.c_size_t(work_bytes), _ptr(frame_out), C.byref(kind), _stream(stream)))
+    return kind.value
+
+
+def pc_stream_pack_bound(n) -> int:
+    return int(lib().pc_stream_pack_bound(_u64x4(n)))
+
+
+def pc_stream_pack_workspace_size(n) -> int:
+    return int(lib().pc_stream_pack_workspace_size(_u64x4(n)))
+
+
+def pc_pack_streams(ctx, streams, n, kind: int, H: int, W: int, tile_h: int, tile_w: int, work, work_bytes: int, out,
+                    cap: int, nbytes, stream=None):
+    _check(lib().pc_pack_streams(ctx, _ptrx4(streams), _u64x4(n), C.c_int32(kind), C.c_int32(H), C.c_int32(W),
+                                 C.c_int32(tile_h), C.c_int32(tile_w), _ptr(work), C.c_size_t(work_bytes), _ptr(out),
+                                 C.c_uint64(cap), _ptr(nbytes), _stream(stream)))
+
+
+def pc_unpack_streams(ctx, data, n_in: int, work, work_bytes: int, streams, caps, stream=None):
+    n_out = (C.c_uint64 * 4)()
+    _check(lib().pc_unpack_streams(ctx, _ptr(data), C.c_uint64(n_in), _ptr(work), C.c_size_t(work_bytes),
+                                   _ptrx4(streams), _u64x4(caps), n_out, _stream(stream)))
+    return [int(x) for x in n_out]
 
 
 def pc_version() -> str:

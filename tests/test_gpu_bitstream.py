@@ -1,0 +1,350 @@
+"""GPU entropy-coded bitstream (Sec. III-A) through the C ABI.
+
+* The coder: the HIP packer on the same four byte streams must produce the
+  oracle's container byte for byte (code lengths, canonical codes, header,
+  tables, payload), including streams whose optimal code is deeper than 15
+  bits, single-symbol and empty streams, and streams spanning several
+  segments with a ragged tail; the HIP unpacker must return the streams of
+  the oracle's containers.
+* The serializer: the streams the HIP packer regenerates from an encoded
+  frame equal the stream format written out in Python from that frame's
+  own sections; their byte histograms equal the encoder's strip histograms.
+* The container's size is the header plus, per non-empty stream, the table
+  and the code bits of its histogram under the container's own code
+  lengths; it equals the encoder's size model wherever no optimal code word
+  exceeds 15 bits.
+* Decode from bytes: unpacking a container into a fresh frame stream buffer
+  and decoding it gives the decoder's output on the original buffer, bit
+  for bit, for key and predicted frames.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2008_06972_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2008_06972_amd import pcc  # noqa: E402
+import oracle  # noqa: E402
+from gpu_common import run_gpu_sequence  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    s = synth.SENSORS["c1"]
+    c = pcc.Context([pcc.Sensor.of(s)])
+    yield c
+    c.close()
+
+
+# ----------------------------------------------------------------- helpers
+def gpu_pack_streams(ctx, streams, kind, H, W, th, tw):
+    n = [len(s) for s in streams]
+    dev = [torch.from_numpy(np.ascontiguousarray(s, np.uint8)).to(DEV) if len(s) else None for s in streams]
+    ws = pcc.pc_stream_pack_workspace_size(n)
+    work = torch.empty(ws, dtype=torch.uint8, device=DEV)
+    cap = pcc.pc_stream_pack_bound(n)
+    out = torch.empty(cap, dtype=torch.uint8, device=DEV)
+    nb = torch.zeros(1, dtype=torch.int64, device=DEV)
+    pcc.pc_pack_streams(ctx.h, dev, n, kind, H, W, th, tw, work, ws, out, cap, nb)
+    torch.cuda.synchronize()
+    k = int(nb.item())
+    assert 0 < k <= cap
+    return out[:k].cpu().numpy().tobytes()
+
+
+def gpu_unpack_streams(ctx, data, caps):
+    d = torch.from_numpy(np.frombuffer(data, np.uint8).copy()).to(DEV)
+    ws = pcc.pc_stream_pack_workspace_size([0, 0, 0, 0])
+    work = torch.empty(ws, dtype=torch.uint8, device=DEV)
+    bufs = [torch.zeros(max(1, int(c)), dtype=torch.uint8, device=DEV) for c in caps]
+    n = pcc.pc_unpack_streams(ctx.h, d, len(data), work, ws, bufs, caps)
+    return [bufs[q][: n[q]].cpu().numpy() for q in range(4)]
+
+
+def oracle_pack(streams, kind, H, W, th, tw):
+    prm = oracle.Params(th=th, tw=tw)
+    f = oracle.Frame(H, W, prm)
+    for q, b in enumerate(streams):
+        b = np.asarray(b, np.uint8)
+        assert len(b) <= len(f.sbufs[q])
+        f.sbufs[q][: len(b)] = b
+        f.c.stream_bytes[q] = len(b)
+        f.arrays["hist"][256 * q: 256 * (q + 1)] = np.bincount(b, minlength=256)
+    return oracle.pack(f, kind, prm)
+
+
+def varint(v):
+    out = bytearray()
+    v = int(v)
+    while v >= 128:
+        out.append((v & 127) | 128)
+        v >>= 7
+    out.append(v)
+    return bytes(out)
+
+
+def expected_streams(h, L, kind):
+    """The stream format written out from a frame's own sections."""
+    H, W, th, tw, TR, TC = L.H, L.W, L.th, L.tw, L.TR, L.TC
+    occ = h["occ"].view(np.uint8)[: H * W // 8]
+    run = bytearray()
+    for tr in range(TR):
+        if kind:
+            npr = int(h["nruns"][TR + tr])
+            run += varint(npr)
+            prev = 0
+            for q in range(npr):
+                r = h["pruns"][tr * TC + q]
+                run += varint(r["s"] - prev) + varint(r["len"]) + np.float32(r["c"]).tobytes()
+                prev = int(r["s"] + r["len"])
+        ns = int(h["nruns"][tr])
+        run += varint(ns)
+        prev = 0
+        for q in range(ns):
+            r = h["sruns"][tr * TC + q]
+            run += varint(r["s"] - prev) + varint(r["len"]) + bytes([int(r["axis"])])
+            run += np.array([r["a"], r["b"], r["c"]], np.float32).tobytes()
+            prev = int(r["s"] + r["len"])
+    valid = np.unpackbits(occ, bitorder="little").reshape(H, W).astype(bool)
+    mask = bytearray()
+    for t in range(TR * TC):
+        if h["cls"][t] not in (2, 3):
+            continue
+        tr, tc = divmod(t, TC)
+        v = valid[tr * th:(tr + 1) * th, tc * tw:(tc + 1) * tw].ravel()
+        m = int(h["mask"][t])
+        bits = [(m >> j) & 1 for j in range(th * tw) if v[j]]
+        for b0 in range(0, len(bits), 8):
+            mask.append(sum(bit << k for k, bit in enumerate(bits[b0:b0 + 8])))
+    res = h["codes"].astype("<u2").tobytes()
+    return [occ.copy(), np.frombuffer(bytes(run), np.uint8), np.frombuffer(bytes(mask), np.uint8),
+            np.frombuffer(res, np.uint8)]
+
+
+def table_lengths(data, q):
+    """Code lengths of stream q read from a container (test-side parser)."""
+    at = 64
+    for s in range(q):
+        if int.from_bytes(data[12 + 8 * s: 20 + 8 * s], "little"):
+            at += 128 + int.from_bytes(data[44 + 4 * s: 48 + 4 * s], "little")
+    t = np.frombuffer(data[at: at + 128], np.uint8)
+    ln = np.zeros(256, np.int64)
+    ln[0::2] = t & 15
+    ln[1::2] = t >> 4
+    return ln
+
+
+def tile_valid_bits(valid, th, tw):
+    """uint64 per tile: bit i*tw+k set where pixel (i, k) of the tile is not empty."""
+    H, W = valid.shape
+    b = valid.reshape(H // th, th, W // tw, tw).transpose(0, 2, 1, 3).reshape(-1, th * tw).astype(np.uint64)
+    return (b << np.arange(th * tw, dtype=np.uint64)).sum(1).astype(np.uint64)
+
+
+def gpu_pack_frame(ctx, fs, S, prm):
+    L = fs.L
+    ws = pcc.pc_pack_workspace_size(S, prm)
+    work = torch.empty(ws, dtype=torch.uint8, device=DEV)
+    cap = pcc.pc_pack_bound(S, prm)
+    out = torch.empty(cap, dtype=torch.uint8, device=DEV)
+    nb = torch.zeros(1, dtype=torch.int64, device=DEV)
+    caps = [L.H * L.W // 8, L.TR * (4 + 17 * L.TC), 8 * L.T, 2 * L.H * L.W]
+    bufs = [torch.zeros(c, dtype=torch.uint8, device=DEV) for c in caps]
+    pcc.pc_pack(ctx.h, fs, S, prm, work, ws, out, cap, nb, bufs, caps)
+    torch.cuda.synchronize()
+    k = int(nb.item())
+    info = fs.info()
+    streams = [bufs[q][: int(info.stream_bytes[q])].cpu().numpy() for q in range(4)]
+    return out[:k].clone(), k, streams, work
+
+
+# ------------------------------------------------------------- the coder
+def _random_streams(rng, kind, sizes):
+    out = []
+    for n in sizes:
+        if kind == 0:
+            out.append(rng.integers(0, 256, n).astype(np.uint8))
+        elif kind == 1:
+            out.append(np.minimum(rng.geometric(0.08, n), 255).astype(np.uint8))
+        else:
+            out.append(rng.integers(0, rng.integers(1, 256), n).astype(np.uint8))
+    return out
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_pack_streams_match_oracle_bytes(ctx, case):
+    rng = np.random.default_rng(100 + case)
+    H, W, th, tw = 256, 2048, 4, 8
+    if case < 3:
+        # several 16 KiB segments with ragged tails, one empty stream
+        streams = _random_streams(rng, case, [rng.integers(1, 60000), rng.integers(1, 70000), 0,
+                                              rng.integers(1, 200000)])
+    elif case == 3:
+        # Fibonacci counts: the optimal tree is 24 deep, the code is limited to 15
+        f = [1, 1]
+        while len(f) < 25:
+            f.append(f[-1] + f[-2])
+        res = np.repeat(rng.permutation(256)[:25].astype(np.uint8), f)
+        streams = [np.full(5, 7, np.uint8), np.array([9], np.uint8), np.zeros(0, np.uint8), rng.permutation(res)]
+    elif case == 4:
+        # one symbol per stream, and an empty frame
+        streams = [np.full(1000, 0, np.uint8), np.full(17, 255, np.uint8), np.zeros(0, np.uint8),
+                   np.full(40000, 3, np.uint8)]
+    else:
+        streams = [np.zeros(0, np.uint8)] * 4
+    kind = case & 1
+    want = oracle_pack(streams, kind, H, W, th, tw)
+    got = gpu_pack_streams(ctx, streams, kind, H, W, th, tw)
+    say("case", case, "sizes", [len(s) for s in streams], "container", len(want), len(got))
+    assert len(got) == len(want)
+    assert got == want
+    back = gpu_unpack_streams(ctx, want, [max(1, len(s)) for s in streams])
+    for a, b in zip(streams, back):
+        assert np.array_equal(a, b)
+
+
+@pytest.fixture(scope="module")
+def oracle_frames():
+    """Oracle-encoded key and predicted frames of the 64 x 2048 sensor."""
+    s = synth.SENSORS["c2"]
+    tb = oracle.Tables.of(s)
+    prm = oracle.Params(eps=0.02, th=4, tw=8)
+    seq = synth.make_sequence(s, "c2", 4040, n_frames=2, key_index=0, shuffle=True)
+    rk, _, _ = oracle.project(seq.frames[0], tb)
+    key = oracle.encode_key(rk, tb, prm)
+    rp, _, _ = oracle.project(seq.frames[1], tb, seq.transforms[1])
+    pred = oracle.encode_pred(key, rp, tb, prm)
+    return dict(s=s, prm=prm, key=key, pred=pred)
+
+
+def test_pack_of_oracle_frame_streams(ctx, oracle_frames):
+    s, prm = oracle_frames["s"], oracle_frames["prm"]
+    for kind, name in ((0, "key"), (1, "pred")):
+        f = oracle_frames[name]
+        want = oracle.pack(f, kind, prm)
+        got = gpu_pack_streams(ctx, f.streams(), kind, s.H, s.W, prm.th, prm.tw)
+        say(name, "stream bytes", f.stream_bytes, "container", len(want), "model", f.size_bytes)
+        assert got == want
+        back = gpu_unpack_streams(ctx, want, [max(1, int(n)) for n in f.stream_bytes])
+        for a, b in zip(f.streams(), back):
+            assert np.array_equal(a, b)
+
+
+def test_unpack_rejects_malformed_containers(ctx, oracle_frames):
+    f = oracle_frames["key"]
+    data = oracle.pack(f, 0, oracle_frames["prm"])
+    caps = [max(1, int(n)) for n in f.stream_bytes]
+    with pytest.raises(pcc.PcError):
+        gpu_unpack_streams(ctx, data[:-1], caps)                 # truncated
+    with pytest.raises(pcc.PcError):
+        gpu_unpack_streams(ctx, b"XCC1" + data[4:], caps)         # magic
+    with pytest.raises(pcc.PcError):
+        gpu_unpack_streams(ctx, data, [c - 1 for c in caps])      # a stream above its capacity
+    t = bytearray(data)
+    t[64] = t[65] = 0x11                                          # four 1-bit codes: over-full table
+    with pytest.raises(pcc.PcError):
+        gpu_unpack_streams(ctx, bytes(t), caps)
+
+
+# -------------------------------------------------------- frames on the GPU
+@pytest.mark.parametrize("kind,seed,th,tw", [("c1", 5000, 4, 4), ("c2", 5001, 4, 8), ("c2", 5002, 8, 8)])
+def test_frame_pack_unpack_decode(kind, seed, th, tw):
+    s = synth.SENSORS[kind]
+    S = pcc.Sensor.of(s)
+    c = pcc.Context([S])
+    try:
+        prm = pcc.params(eps=0.02, tile_h=th, tile_w=tw)
+        tb = oracle.Tables.of(s)
+        seq = synth.make_sequence(s, kind, seed, n_frames=3, key_index=0, shuffle=True)
+        say("frames", kind, s.H, s.W, th, tw, [len(x) for x in seq.frames])
+        g = run_gpu_sequence(pcc, torch, c, S, prm, seq.frames, seq.transforms, 0, DEV)
+        key_unpacked = None
+        for i, gi in enumerate(g):
+            fs, h = gi["fs"], gi["host"]
+            info = h["info"]
+            frame_kind = 0 if i == 0 else 1
+            data, k, streams, work = gpu_pack_frame(c, fs, S, prm)
+            raw = data.cpu().numpy().tobytes()
+            # serializer: the format written out from the frame's own sections
+            exp = expected_streams(h, fs.L, frame_kind)
+            for q in range(4):
+                assert np.array_equal(streams[q], exp[q]), f"frame {i} stream {q}"
+                assert np.array_equal(np.bincount(streams[q], minlength=256),
+                                      h["strip"][:, 256 * q: 256 * (q + 1)].sum(0)), f"frame {i} hist {q}"
+            # OCC against the oracle's own projection of the same points
+            M = None if i == 0 else seq.transforms[i]
+            r_orc, _, _ = oracle.project(seq.frames[i], tb, M)
+            assert np.array_equal(streams[0], np.packbits((r_orc > 0).ravel(), bitorder="little"))
+            # container size: header, tables and the code bits of each stream
+            assert raw[:4] == b"PCC1" and raw[4] == frame_kind
+            want, deep = 64, False
+            for q in range(4):
+                if len(streams[q]) == 0:
+                    continue
+                ln = table_lengths(raw, q)
+                assert ln.max() <= 15
+                bits = int((np.bincount(streams[q], minlength=256) * ln).sum())
+                assert bits >= int(info.coded_bits[q])
+                deep |= bits != int(info.coded_bits[q])
+                want += 128 + (bits + 7) // 8
+            assert k == want
+            if not deep:
+                assert k == int(info.size_bytes)
+            assert k - int(info.size_bytes) <= 0.001 * k
+            # decode from bytes
+            out = pcc.FrameStream(S, prm, DEV)
+            kd = pcc.pc_unpack(c.h, data, k, None if i == 0 else key_unpacked, S, prm, work, work.numel(), out)
+            assert kd == frame_kind
+            dec = torch.empty(s.H, s.W, dtype=torch.float32, device=DEV)
+            pcc.pc_decode(c.h, None if i == 0 else key_unpacked, out, S, prm, dec)
+            torch.cuda.synchronize()
+            assert np.array_equal(dec.cpu().numpy(), gi["dec"]), f"frame {i} decode from bytes"
+            u = out.host()
+            for name in ("occ", "cls", "nres", "codes"):
+                assert np.array_equal(u[name], h[name]), f"frame {i} {name}"
+            assert np.array_equal(u["nruns"][:fs.L.TR], h["nruns"][:fs.L.TR])
+            assert np.array_equal(u["srun_list"], h["srun_list"])
+            if frame_kind:
+                assert np.array_equal(u["nruns"][fs.L.TR:], h["nruns"][fs.L.TR:])
+                assert np.array_equal(u["prun_list"], h["prun_list"])
+            cov = np.isin(h["cls"], (2, 3))
+            V = tile_valid_bits(r_orc > 0, th, tw)
+            assert not np.any(u["mask"] & ~V)
+            assert np.array_equal(u["mask"][cov], (h["mask"] & V)[cov])
+            say(i, "container", k, "model", int(info.size_bytes), "deep", deep, "stream bytes",
+                list(info.stream_bytes))
+            if i == 0:
+                key_unpacked = out
+    finally:
+        c.close()
+
+
+def test_empty_frame_round_trip(ctx):
+    s = synth.SENSORS["c1"]
+    S = pcc.Sensor.of(s)
+    prm = pcc.params(eps=0.02, tile_h=4, tile_w=8)
+    empty = np.zeros((0, 3), np.float32)
+    g = run_gpu_sequence(pcc, torch, ctx, S, prm, [empty], np.eye(4, dtype=np.float32)[None], 0, DEV)[0]
+    data, k, streams, work = gpu_pack_frame(ctx, g["fs"], S, prm)
+    assert len(streams[2]) == 0 and len(streams[3]) == 0 and not streams[0].any()
+    assert k == int(g["host"]["info"].size_bytes)
+    out = pcc.FrameStream(S, prm, DEV)
+    assert pcc.pc_unpack(ctx.h, data, k, None, S, prm, work, work.numel(), out) == 0
+    dec = torch.ones(s.H, s.W, dtype=torch.float32, device=DEV)
+    pcc.pc_decode(ctx.h, None, out, S, prm, dec)
+    torch.cuda.synchronize()
+    assert not dec.cpu().numpy().any()

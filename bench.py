@@ -91,6 +91,7 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--cpu-seqs", type=int, default=96, help="oracle sample (sequences)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-pack", action="store_true", help="skip packing the frames into containers")
     ap.add_argument("--procs", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -330,6 +331,42 @@ def main():
         del src, dst
         result["copy_ceiling"] = {"GB/s": copy_gbps, "bytes": 2 * (4 << 28), "what": "1 GiB device copy, read + write"}
         result["roofline"]["frac_of_copy"] = ach / copy_gbps
+
+    # ------------------------------------------- entropy-coded bitstream
+    # every frame of the head form packed into its container (Sec. III-A):
+    # the emitted bytes against the size model, and the packing rate
+    if batch is not None and not a.no_pack:
+        Lh = batch.outs[0].L
+        prm_h = pcc.params(eps=EPS, tile_h=Lh.th, tile_w=Lh.tw, max_iter=5, min_pts=4, min_inlier_frac=0.5)
+        cap = pcc.pc_pack_bound(S, prm_h)
+        wsb = pcc.pc_pack_batch_workspace_size(S, prm_h, nfr)
+        work = torch.empty(wsb, dtype=torch.uint8, device=dev)
+        cont = torch.empty(nfr, cap, dtype=torch.uint8, device=dev)
+        outs_c = [cont[i] for i in range(nfr)]
+        nbytes = torch.zeros(nfr, dtype=torch.int64, device=dev)
+        pcc.pc_pack_batch(ctx.h, batch.outs, S, prm_h, work, wsb, outs_c, cap, nbytes, stream=stream)
+        torch.cuda.synchronize()
+        p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        t_host = time.time()
+        p0.record(stream)
+        for _ in range(reps):
+            pcc.pc_pack_batch(ctx.h, batch.outs, S, prm_h, work, wsb, outs_c, cap, nbytes, stream=stream)
+        p1.record(stream)
+        torch.cuda.synchronize()
+        pms = p0.elapsed_time(p1) / reps
+        packed = nbytes.cpu().numpy().astype(np.int64)
+        model = sizes[head]
+        result["bitstream"] = {
+            "frames": nfr, "container_bytes": int(packed.sum()), "model_bytes": int(model.sum()),
+            "excess_over_model": float(packed.sum() / model.sum() - 1.0),
+            "frames_equal_to_model": int((packed == model).sum()),
+            "compression_ratio": 12.0 * finite_pts / float(packed.sum()),
+            "pack_ms": pms, "pack_frames_per_s": nfr / (pms / 1e3),
+            "pack_host_ms": (time.time() - t_host) * 1e3 / reps,
+            "what": "pc_pack_batch over every frame of the timed form (job-table upload included)"}
+        log(f"bitstream: {int(packed.sum())} bytes vs model {int(model.sum())}, {pms:.3f} ms per batch pack")
+        del cont, work
 
     # ------------------------------------------------------- CPU baseline
     if not a.no_cpu:

@@ -392,6 +392,17 @@ pc_status pc_pack(pc_ctx *ctx, const void *frame, const pc_sensor *sensor, const
                   size_t work_bytes, void *out, uint64_t cap, uint64_t *nbytes, uint8_t *const *streams,
                   const uint64_t *stream_caps, void *stream);
 
+/* pc_pack over n frames of one sensor and tile shape: outs[i] (host array of
+ * device pointers, each 4-byte aligned with cap >= pc_pack_bound bytes)
+ * receives frame i's container and nbytes[i] (device u64[n]) its size.  One
+ * planning work-group per frame and one work-group per strip and frame.  The
+ * per-frame job table is uploaded into the workspace first, which
+ * synchronises `stream`; nothing is allocated on the device. */
+size_t pc_pack_batch_workspace_size(const pc_sensor *sensor, const pc_params *params, int32_t n);
+pc_status pc_pack_batch(pc_ctx *ctx, int32_t n, const void *const *frames, const pc_sensor *sensor,
+                        const pc_params *params, void *work, size_t work_bytes, void *const *outs, uint64_t cap,
+                        uint64_t *nbytes, void *stream);
+
 /* Unpack a container (device bytes, n_in exactly its size) into a frame
  * stream buffer that pc_decode reads: occupancy, tile classes, runs, masks
  * and residual codes (the encoder's fit records and strip histograms are not

@@ -26,6 +26,7 @@
 // the counts.  The streams are then parsed back into a frame stream buffer
 // that the decoder reads.
 #include <algorithm>
+#include <vector>
 
 #include "encode_strip.h"
 
@@ -77,6 +78,23 @@ struct HeadInfo {
 struct StreamPtrs {
   uint8_t *p[4];
   uint64_t cap[4];
+};
+
+// Everything one frame's (or one raw stream set's) packing needs.  Kernels
+// take a job by value (one frame) or an array of jobs in device memory
+// (several frames, one per block row).
+struct PackJob {
+  HistSrc hs;
+  HeadInfo hi;
+  PackPlan *plan;
+  SegInfo *seg;
+  int max_seg;
+  int th, tw, W;
+  uint64_t cap;
+  uint64_t *nbytes;
+  uint32_t *out;
+  FrameDev f;
+  StreamPtrs so;
 };
 
 struct UnpackPlan {
@@ -212,8 +230,15 @@ __device__ void depth_counts_wave(const uint32_t *h, LenScratch &sc, int lane) {
 
 // Builds the code of all four streams, the header and the tables, and the
 // bit offset of every segment.  One work-group of kPackBlock threads.
-__global__ void __launch_bounds__(kPackBlock) k_pack_plan(HistSrc hs, HeadInfo hi, PackPlan *plan, SegInfo *seg,
-                                                         int max_seg, uint64_t cap, uint64_t *nbytes_out) {
+__global__ void __launch_bounds__(kPackBlock) k_pack_plan(PackJob j0, const PackJob *jobs) {
+  const PackJob *J = jobs ? jobs + blockIdx.x : &j0;
+  const HistSrc &hs = J->hs;
+  const HeadInfo &hi = J->hi;
+  PackPlan *plan = J->plan;
+  SegInfo *seg = J->seg;
+  const int max_seg = J->max_seg;
+  const uint64_t cap = J->cap;
+  uint64_t *nbytes_out = J->nbytes;
   __shared__ uint32_t h[4][256];
   __shared__ LenScratch sc[4];
   __shared__ uint8_t len[4][256];
@@ -340,7 +365,10 @@ __global__ void __launch_bounds__(kPackBlock) k_pack_plan(HistSrc hs, HeadInfo h
 }
 
 // Header, tables and zeroed payload words, one 32-bit word per thread.
-__global__ void __launch_bounds__(kPackBlock) k_pack_fill(const PackPlan *plan, uint32_t *out) {
+__global__ void __launch_bounds__(kPackBlock) k_pack_fill(PackJob j0, const PackJob *jobs) {
+  const PackJob *J = jobs ? jobs + blockIdx.y : &j0;
+  const PackPlan *plan = J->plan;
+  uint32_t *out = J->out;
   const uint64_t total = plan->total;
   if (plan->err || total == 0) return;
   const uint64_t nw = (total + 3) / 4;
@@ -416,9 +444,14 @@ __device__ void encode_bytes(const uint8_t *buf, uint32_t n, uint64_t bit0, uint
 // One work-group per tile-row strip: regenerate the strip's bytes of each
 // stream from the frame stream buffer, optionally copy them out, and code
 // them.
-__global__ void __launch_bounds__(kPackBlock) k_pack_frame(FrameDev f, int th, int tw, int W, PackPlan *plan,
-                                                          const SegInfo *seg, int max_seg, uint32_t *out,
-                                                          StreamPtrs so) {
+__global__ void __launch_bounds__(kPackBlock) k_pack_frame(PackJob j0, const PackJob *jobs) {
+  const PackJob *J = jobs ? jobs + blockIdx.y : &j0;
+  const FrameDev f = J->f;
+  const int th = J->th, tw = J->tw, W = J->W, max_seg = J->max_seg;
+  PackPlan *plan = J->plan;
+  const SegInfo *seg = J->seg;
+  uint32_t *out = J->out;
+  const StreamPtrs &so = J->so;
   extern __shared__ __align__(16) char smem[];
   uint8_t *len = (uint8_t *)smem;                        // [4][256]
   uint32_t *code = (uint32_t *)(smem + 1024);            // [4][256]
@@ -537,8 +570,11 @@ __global__ void __launch_bounds__(kPackBlock) k_pack_frame(FrameDev f, int th, i
   }
 }
 
-__global__ void k_pack_done(const PackPlan *plan, uint64_t *nbytes_out) {
-  *nbytes_out = plan->err ? 0 : plan->total;
+__global__ void k_pack_done(PackJob j0, const PackJob *jobs, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const PackJob *J = jobs ? jobs + i : &j0;
+  *J->nbytes = J->plan->err ? 0 : J->plan->total;
 }
 
 // Raw streams: histogram and code of each kChunk-byte segment.
@@ -1033,6 +1069,55 @@ pc_status unpack_to_streams(const uint8_t *in, uint64_t n_in, char *ws, const ui
   return PC_OK;
 }
 
+// One frame's packing job; `ws` holds its plan and segment table.
+PackJob frame_job(const pc_layout &L, const void *frame, char *ws, void *out, uint64_t cap, uint64_t *nbytes,
+                  const StreamPtrs &so) {
+  PackJob j{};
+  j.f = frame_dev((void *)frame, L);
+  j.hs.base = j.f.strip;
+  j.hs.stride_q = 256;
+  j.hs.stride_s = PC_STRIP_WORDS;
+  for (int q = 0; q < 4; q++) j.hs.nseg[q] = L.TR;
+  j.hi = HeadInfo{0, L.th, L.tw, L.H, L.W, 1, j.f.info};
+  j.plan = (PackPlan *)ws;
+  j.seg = (SegInfo *)(ws + a256(sizeof(PackPlan)));
+  j.max_seg = L.TR;
+  j.th = L.th;
+  j.tw = L.tw;
+  j.W = L.W;
+  j.cap = cap;
+  j.nbytes = nbytes;
+  j.out = (uint32_t *)out;
+  j.so = so;
+  return j;
+}
+
+// Plan (a work-group per frame), fill, strips (a work-group per strip and
+// frame), sizes.  jobs == NULL: the single job j0.
+hipError_t launch_frame_jobs(const PackJob &j0, const PackJob *jobs, int n, const pc_layout &L, uint64_t cap,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_pack_plan, dim3(n), dim3(kPackBlock), 0, st, j0, jobs);
+  const int fill_blocks = (int)std::min<uint64_t>(jobs ? 64 : 2048, (cap / 4 + kPackBlock - 1) / kPackBlock);
+  hipLaunchKernelGGL(k_pack_fill, dim3(fill_blocks, n), dim3(kPackBlock), 0, st, j0, jobs);
+  const size_t sh = 1024 + 4 * 1024 + 64 + 2 * (size_t)L.th * L.W + 64;
+  hipError_t e = hipFuncSetAttribute((const void *)k_pack_frame, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pack_frame, dim3(L.TR, n), dim3(kPackBlock), sh, st, j0, jobs);
+  hipLaunchKernelGGL(k_pack_done, dim3((n + 255) / 256), dim3(256), 0, st, j0, jobs, n);
+  return hipGetLastError();
+}
+
+pc_status check_frame_pack(const pc_sensor *sensor, const pc_params *params, uint64_t cap, pc_layout *L) {
+  pc_status stt = pc_stream_layout(sensor, params, L);
+  if (stt) return stt;
+  if (L->TR > 1024) return set_error(PC_ERR_UNSUPPORTED, "more than 1024 tile rows");
+  FrameCaps k = frame_caps(*L);
+  if (cap < bound_of(k.c))
+    return set_error(PC_ERR_CAPACITY, "output %llu bytes < bound %llu", (unsigned long long)cap,
+                     (unsigned long long)bound_of(k.c));
+  return PC_OK;
+}
+
 }  // namespace
 }  // namespace pcc
 
@@ -1058,41 +1143,54 @@ pc_status pc_pack(pc_ctx *ctx, const void *frame, const pc_sensor *sensor, const
                   const uint64_t *stream_caps, void *stream) {
   if (!ctx) return set_error(PC_ERR_ARG, "ctx is NULL");
   pc_layout L;
-  pc_status stt = pc_stream_layout(sensor, params, &L);
+  pc_status stt = check_frame_pack(sensor, params, cap, &L);
   if (stt) return stt;
   if (!frame || !out || !nbytes || !work) return set_error(PC_ERR_ARG, "frame, output, size or workspace is NULL");
   if ((uintptr_t)out & 3) return set_error(PC_ERR_ARG, "output must be 4-byte aligned");
-  if (L.TR > 1024) return set_error(PC_ERR_UNSUPPORTED, "more than 1024 tile rows");
   if (work_bytes < frame_ws(L)) return set_error(PC_ERR_CAPACITY, "workspace %zu bytes < %zu", work_bytes, frame_ws(L));
-  if (cap < pc_pack_bound(sensor, params))
-    return set_error(PC_ERR_CAPACITY, "output %llu bytes < bound %zu", (unsigned long long)cap, pc_pack_bound(sensor, params));
   if (streams && !stream_caps) return set_error(PC_ERR_ARG, "stream capacities are NULL");
-  hipStream_t st = (hipStream_t)stream;
-  FrameDev f = frame_dev((void *)frame, L);
-  char *ws = (char *)work;
-  PackPlan *plan = (PackPlan *)ws;
-  SegInfo *seg = (SegInfo *)(ws + a256(sizeof(PackPlan)));
-  HistSrc hs;
-  hs.base = f.strip;
-  hs.stride_q = 256;
-  hs.stride_s = PC_STRIP_WORDS;
-  for (int q = 0; q < 4; q++) hs.nseg[q] = L.TR;
-  HeadInfo hi{0, L.th, L.tw, L.H, L.W, 1, f.info};
   StreamPtrs so{};
   for (int q = 0; q < 4; q++) {
     so.p[q] = streams ? streams[q] : nullptr;
     so.cap[q] = streams ? stream_caps[q] : 0;
   }
-  hipLaunchKernelGGL(k_pack_plan, dim3(1), dim3(kPackBlock), 0, st, hs, hi, plan, seg, L.TR, (uint64_t)cap, nbytes);
-  const int fill_blocks = (int)std::min<uint64_t>(2048, (cap / 4 + kPackBlock - 1) / kPackBlock);
-  hipLaunchKernelGGL(k_pack_fill, dim3(fill_blocks), dim3(kPackBlock), 0, st, (const PackPlan *)plan, (uint32_t *)out);
-  const size_t sh = 1024 + 4 * 1024 + 64 + 2 * (size_t)L.th * L.W + 64;
-  if (hipFuncSetAttribute((const void *)k_pack_frame, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh) != hipSuccess)
-    return set_error(PC_ERR_DEVICE, "pack shared-memory attribute failed");
-  hipLaunchKernelGGL(k_pack_frame, dim3(L.TR), dim3(kPackBlock), sh, st, f, L.th, L.tw, L.W, plan, (const SegInfo *)seg,
-                     L.TR, (uint32_t *)out, so);
-  hipLaunchKernelGGL(k_pack_done, dim3(1), dim3(1), 0, st, (const PackPlan *)plan, nbytes);
-  hipError_t he = hipGetLastError();
+  PackJob j = frame_job(L, frame, (char *)work, out, cap, nbytes, so);
+  hipError_t he = launch_frame_jobs(j, nullptr, 1, L, cap, (hipStream_t)stream);
+  if (he != hipSuccess) return set_error(PC_ERR_DEVICE, "pack launch failed: %s", hipGetErrorString(he));
+  return PC_OK;
+}
+
+size_t pc_pack_batch_workspace_size(const pc_sensor *sensor, const pc_params *params, int32_t n) {
+  pc_layout L;
+  if (n < 1 || pc_stream_layout(sensor, params, &L) != PC_OK) return 0;
+  return a256(sizeof(PackJob) * (size_t)n) + (size_t)n * pack_ws(L.TR, false);
+}
+
+pc_status pc_pack_batch(pc_ctx *ctx, int32_t n, const void *const *frames, const pc_sensor *sensor,
+                        const pc_params *params, void *work, size_t work_bytes, void *const *outs, uint64_t cap,
+                        uint64_t *nbytes, void *stream) {
+  if (!ctx) return set_error(PC_ERR_ARG, "ctx is NULL");
+  if (n < 1 || n > 65535) return set_error(PC_ERR_ARG, "frame count %d out of range 1..65535", n);
+  pc_layout L;
+  pc_status stt = check_frame_pack(sensor, params, cap, &L);
+  if (stt) return stt;
+  if (!frames || !outs || !nbytes || !work) return set_error(PC_ERR_ARG, "NULL argument");
+  const size_t need = pc_pack_batch_workspace_size(sensor, params, n);
+  if (work_bytes < need) return set_error(PC_ERR_CAPACITY, "workspace %zu bytes < %zu", work_bytes, need);
+  std::vector<PackJob> jobs((size_t)n);
+  char *ws = (char *)work + a256(sizeof(PackJob) * (size_t)n);
+  for (int i = 0; i < n; i++) {
+    if (!frames[i] || !outs[i]) return set_error(PC_ERR_ARG, "frame or output %d is NULL", i);
+    if ((uintptr_t)outs[i] & 3) return set_error(PC_ERR_ARG, "output %d must be 4-byte aligned", i);
+    jobs[i] = frame_job(L, frames[i], ws + (size_t)i * pack_ws(L.TR, false), outs[i], cap, nbytes + i, StreamPtrs{});
+  }
+  hipStream_t st = (hipStream_t)stream;
+  PackJob *dj = (PackJob *)work;
+  // the job table is read by every launch; the host copy must outlive the upload
+  if (hipMemcpyAsync(dj, jobs.data(), sizeof(PackJob) * (size_t)n, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return set_error(PC_ERR_DEVICE, "job table upload failed");
+  hipError_t he = launch_frame_jobs(jobs[0], dj, n, L, cap, st);
   if (he != hipSuccess) return set_error(PC_ERR_DEVICE, "pack launch failed: %s", hipGetErrorString(he));
   return PC_OK;
 }
@@ -1136,14 +1234,23 @@ pc_status pc_pack_streams(pc_ctx *ctx, const uint8_t *const *streams, const uint
   hs.base = seg_hist;
   hs.stride_q = 256 * (int64_t)max_seg;
   hs.stride_s = 256;
-  HeadInfo hi{kind, tile_h, tile_w, H, W, 0, nullptr};
+  PackJob j{};
+  j.hs = hs;
+  j.hi = HeadInfo{kind, tile_h, tile_w, H, W, 0, nullptr};
+  j.plan = plan;
+  j.seg = seg;
+  j.max_seg = max_seg;
+  j.cap = cap;
+  j.nbytes = nbytes;
+  j.out = (uint32_t *)out;
+  const PackJob *none = nullptr;
   hipLaunchKernelGGL(k_pack_hist, dim3(4 * max_seg), dim3(kPackBlock), 0, st, in, seg_hist, max_seg);
-  hipLaunchKernelGGL(k_pack_plan, dim3(1), dim3(kPackBlock), 0, st, hs, hi, plan, seg, max_seg, (uint64_t)cap, nbytes);
+  hipLaunchKernelGGL(k_pack_plan, dim3(1), dim3(kPackBlock), 0, st, j, none);
   const int fill_blocks = (int)std::min<uint64_t>(2048, (cap / 4 + kPackBlock - 1) / kPackBlock);
-  hipLaunchKernelGGL(k_pack_fill, dim3(fill_blocks), dim3(kPackBlock), 0, st, (const PackPlan *)plan, (uint32_t *)out);
+  hipLaunchKernelGGL(k_pack_fill, dim3(fill_blocks), dim3(kPackBlock), 0, st, j, none);
   hipLaunchKernelGGL(k_pack_chunks, dim3(4 * max_seg), dim3(kPackBlock), 0, st, in, plan, (const SegInfo *)seg, max_seg,
                      (uint32_t *)out);
-  hipLaunchKernelGGL(k_pack_done, dim3(1), dim3(1), 0, st, (const PackPlan *)plan, nbytes);
+  hipLaunchKernelGGL(k_pack_done, dim3(1), dim3(1), 0, st, j, none, 1);
   hipError_t he = hipGetLastError();
   if (he != hipSuccess) return set_error(PC_ERR_DEVICE, "pack launch failed: %s", hipGetErrorString(he));
   return PC_OK;

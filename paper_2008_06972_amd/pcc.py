@@ -88,12 +88,13 @@ def lib():
                      "pc_project", "pc_fit_key", "pc_encode_pred", "pc_decode", "pc_check", "pc_batch_create",
                      "pc_batch_run", "pc_batch_info", "pc_batch_profile", "pc_batch_destroy", "pc_net_forward",
                      "pc_net_backward", "pc_net_loss", "pc_net_adam", "pc_pack", "pc_unpack", "pc_pack_streams",
-                     "pc_unpack_streams"):
+                     "pc_unpack_streams", "pc_pack_batch"):
             getattr(L, name).restype = C.c_int
         L.pc_batch_workspace_size.restype = C.c_size_t
         L.pc_net_workspace_size.restype = C.c_size_t
         L.pc_pack_bound.restype = C.c_size_t
         L.pc_pack_workspace_size.restype = C.c_size_t
+        L.pc_pack_batch_workspace_size.restype = C.c_size_t
         L.pc_stream_pack_bound.restype = C.c_uint64
         L.pc_stream_pack_workspace_size.restype = C.c_size_t
         _lib = L
@@ -106,7 +107,7 @@ EXPORTED = ("pc_stream_layout", "pc_workspace_size", "pc_ctx_create", "pc_ctx_de
             "pc_batch_info", "pc_batch_profile", "pc_batch_destroy", "pc_net_workspace_size", "pc_net_forward",
             "pc_net_backward", "pc_net_loss", "pc_net_adam", "pc_pack_bound", "pc_pack_workspace_size", "pc_pack",
             "pc_unpack", "pc_stream_pack_bound", "pc_stream_pack_workspace_size", "pc_pack_streams",
-            "pc_unpack_streams")
+            "pc_unpack_streams", "pc_pack_batch_workspace_size", "pc_pack_batch")
 PC_NET_PARAMS = 15636
 LAUNCH_KINDS = {0: "reset", 1: "count", 2: "offsets", 3: "scatter", 4: "key", 5: "pred", 6: "finish",
                 7: "keyimage", 8: "net"}
@@ -301,6 +302,19 @@ def pc_pack(ctx, frame, sensor: Sensor, prm: pc_params, work, work_bytes: int, o
     sc = _u64x4(stream_caps) if stream_caps is not None else None
     _check(lib().pc_pack(ctx, _ptr(frame), C.byref(sensor.c), C.byref(prm), _ptr(work), C.c_size_t(work_bytes),
                          _ptr(out), C.c_uint64(cap), _ptr(nbytes), sp, sc, _stream(stream)))
+
+
+def pc_pack_batch_workspace_size(sensor: Sensor, prm: pc_params, n: int) -> int:
+    return int(lib().pc_pack_batch_workspace_size(C.byref(sensor.c), C.byref(prm), C.c_int32(n)))
+
+
+def pc_pack_batch(ctx, frames, sensor: Sensor, prm: pc_params, work, work_bytes: int, outs, cap: int, nbytes,
+                  stream=None):
+    n = len(frames)
+    fa = (C.c_void_p * n)(*[_ptr(f).value for f in frames])
+    oa = (C.c_void_p * n)(*[_ptr(o).value for o in outs])
+    _check(lib().pc_pack_batch(ctx, C.c_int32(n), fa, C.byref(sensor.c), C.byref(prm), _ptr(work),
+                               C.c_size_t(work_bytes), oa, C.c_uint64(cap), _ptr(nbytes), _stream(stream)))
 
 
 def pc_unpack(ctx, data, n_in: int, key, sensor: Sensor, prm: pc_params, work, work_bytes: int, frame_out,

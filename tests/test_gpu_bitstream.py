@@ -348,3 +348,30 @@ def test_empty_frame_round_trip(ctx):
     pcc.pc_decode(ctx.h, None, out, S, prm, dec)
     torch.cuda.synchronize()
     assert not dec.cpu().numpy().any()
+
+
+def test_pack_batch_equals_single_packs():
+    s = synth.SENSORS["c2"]
+    S = pcc.Sensor.of(s)
+    c = pcc.Context([S])
+    try:
+        prm = pcc.params(eps=0.02, tile_h=4, tile_w=8)
+        seq = synth.make_sequence(s, "c2", 5100, n_frames=5, key_index=2, shuffle=True)
+        g = run_gpu_sequence(pcc, torch, c, S, prm, seq.frames, seq.transforms, 2, DEV)
+        singles = [gpu_pack_frame(c, gi["fs"], S, prm)[0].cpu().numpy() for gi in g]
+        n = len(g)
+        cap = pcc.pc_pack_bound(S, prm)
+        ws = pcc.pc_pack_batch_workspace_size(S, prm, n)
+        work = torch.empty(ws, dtype=torch.uint8, device=DEV)
+        outs = [torch.zeros(cap, dtype=torch.uint8, device=DEV) for _ in range(n)]
+        nb = torch.zeros(n, dtype=torch.int64, device=DEV)
+        for _ in range(2):                 # twice: the workspace keeps nothing between calls
+            pcc.pc_pack_batch(c.h, [gi["fs"] for gi in g], S, prm, work, ws, outs, cap, nb)
+            torch.cuda.synchronize()
+            sizes = nb.cpu().numpy()
+            for i in range(n):
+                assert sizes[i] == len(singles[i])
+                assert np.array_equal(outs[i][: sizes[i]].cpu().numpy(), singles[i]), f"frame {i}"
+        say("batch sizes", sizes.tolist())
+    finally:
+        c.close()

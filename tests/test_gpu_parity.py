@@ -28,6 +28,16 @@ def say(*a):
     sys.stdout.flush()
 
 
+def own_range(tb, pts, M, g):
+    """The oracle's own projection of the points a GPU frame was made from;
+    the projection parity makes it bit-identical to the GPU's range image, so
+    both encoders start from the same input without GPU output entering the
+    oracle."""
+    r, _, _ = oracle.project(np.asarray(pts, np.float32), tb, M)
+    assert np.array_equal(r, g["range"])
+    return r
+
+
 @pytest.fixture(scope="module")
 def ctx_factory():
     made = []
@@ -108,9 +118,10 @@ def _key_parity(ctx_factory, s, kind, seed, th, tw, report):
     pts, _, _ = synth.make_frame(s, kind, seed)
     say("key frame", kind, s.H, s.W, th, tw, len(pts))
     g = run_gpu_sequence(pcc, torch, ctx, S, prm, [pts], np.eye(4, dtype=np.float32)[None], 0, DEV)[0]
-    o = oracle.encode_key(g["range"], tb, oprm)
-    st = compare_frame(oracle, g["host"], o, g["range"])
-    ok, nboth, ndiff = residual_codes_agree(g["host"], o, g["range"], th, tw)
+    r_o = own_range(tb, pts, None, g)
+    o = oracle.encode_key(r_o, tb, oprm)
+    st = compare_frame(oracle, g["host"], o, r_o)
+    ok, nboth, ndiff = residual_codes_agree(g["host"], o, r_o, th, tw)
     st.update(codes_equal=ok, res_both=nboth, res_differ=ndiff)
     report(st)
     v = g["range"] > 0
@@ -146,7 +157,7 @@ def test_noiseless_planes_exact_structure(ctx_factory):
     pts, _, _ = synth.render(s, scene, np.eye(3), np.zeros(3), 0, rng)
     prm = pcc.params(eps=0.02, tile_h=4, tile_w=4)
     g = run_gpu_sequence(pcc, torch, ctx, S, prm, [pts], np.eye(4, dtype=np.float32)[None], 0, DEV)[0]
-    o = oracle.encode_key(g["range"], tb, oracle.Params(eps=0.02, th=4, tw=4))
+    o = oracle.encode_key(own_range(tb, pts, None, g), tb, oracle.Params(eps=0.02, th=4, tw=4))
     h = g["host"]
     agree = np.mean(h["cls"] == o.cls)
     say("noiseless cls agreement", agree, "runs", len(h["srun_list"]), o.c.n_sruns)
@@ -164,10 +175,12 @@ def test_sequence_parity_and_invariant(ctx_factory):
     oprm = oracle.Params(eps=0.02, th=4, tw=4)
     say("sequence c3", [len(f) for f in seq.frames])
     g = run_gpu_sequence(pcc, torch, ctx, S, prm, seq.frames, seq.transforms, seq.key_index, DEV)
-    ok_key = oracle.encode_key(g[seq.key_index]["range"], tb, oprm)
+    ki = seq.key_index
+    ok_key = oracle.encode_key(own_range(tb, seq.frames[ki], None, g[ki]), tb, oprm)
     tot_g = tot_o = 0
     for i, gi in enumerate(g):
-        o = ok_key if i == seq.key_index else oracle.encode_pred(ok_key, gi["range"], tb, oprm)
+        o = ok_key if i == ki else oracle.encode_pred(ok_key, own_range(tb, seq.frames[i], seq.transforms[i], gi),
+                                                      tb, oprm)
         v = gi["range"] > 0
         err = np.abs(gi["dec"].astype(np.float64) - gi["range"].astype(np.float64))
         assert np.all(gi["dec"][~v] == 0) and err[v].max() <= 0.02, f"frame {i} eps invariant"
@@ -203,13 +216,14 @@ def test_empty_and_ragged_frames(ctx_factory):
     oprm = oracle.Params(eps=0.02, th=4, tw=8)
     empty = np.zeros((0, 3), np.float32)
     g = run_gpu_sequence(pcc, torch, ctx, S, prm, [empty], np.eye(4, dtype=np.float32)[None], 0, DEV)[0]
-    o = oracle.encode_key(g["range"], tb, oprm)
+    o = oracle.encode_key(own_range(tb, empty, None, g), tb, oprm)
     assert g["host"]["info"].size_bytes == o.size_bytes
     assert not g["dec"].any()
     pts, _, _ = synth.make_frame(s, "c1", 1010)
     g = run_gpu_sequence(pcc, torch, ctx, S, prm, [pts], np.eye(4, dtype=np.float32)[None], 0, DEV)[0]
-    o = oracle.encode_key(g["range"], tb, oprm)
-    st = compare_frame(oracle, g["host"], o, g["range"])
+    r_o = own_range(tb, pts, None, g)
+    o = oracle.encode_key(r_o, tb, oprm)
+    st = compare_frame(oracle, g["host"], o, r_o)
     say("ragged", st)
     assert st["size_rel"] <= 0.005
     v = g["range"] > 0

@@ -48,7 +48,11 @@ def frame():
     pcc.pc_project(ctx.h, xyz, len(pts), None, S, rng)
     torch.cuda.synchronize()
     tb = oracle.Tables.of(s)
-    yield dict(s=s, S=S, ctx=ctx, rng=rng, tb=tb, rng_np=rng.cpu().numpy())
+    # the oracle works from its own projection of the same points, which the
+    # projection parity makes bit-identical to the GPU's
+    rng_np, _, _ = oracle.project(pts, tb)
+    assert np.array_equal(rng.cpu().numpy(), rng_np)
+    yield dict(s=s, S=S, ctx=ctx, rng=rng, tb=tb, rng_np=rng_np)
     ctx.close()
 
 
@@ -108,15 +112,21 @@ def test_net_backward_matches_oracle(frame):
 def test_net_loss_and_adam_match_oracle(frame):
     S, s = frame["S"], frame["s"]
     prm = pcc.params(eps=0.02, tile_h=4, tile_w=8)
+    # labels from the oracle's plain fit, given to both sides
+    plain = oracle.encode_key(frame["rng_np"], frame["tb"], oracle.Params(eps=0.02, th=4, tw=8))
+    rec = np.zeros(len(plain.own_status), pcc.TILE_DTYPE)
+    rec["status"], rec["axis"] = plain.own_status, plain.own_axis
+    rec["a"], rec["b"], rec["c"] = plain.own_abc[:, 0], plain.own_abc[:, 1], plain.own_abc[:, 2]
     labels = pcc.FrameStream(S, prm, DEV)
-    pcc.pc_fit_key(frame["ctx"].h, frame["rng"], S, prm, None, labels)
+    off = labels.L.off_tiles
+    labels.buf[off:off + rec.nbytes] = torch.from_numpy(rec.view(np.uint8).copy()).to(DEV)
     p = _params(13)
     pt, work, seed = _gpu_forward(frame, p)
     dseed = torch.zeros_like(seed)
     loss = torch.zeros(1, dtype=torch.float32, device=DEV)
     pcc.pc_net_loss(frame["ctx"].h, seed, labels, S, prm, dseed, loss)
     torch.cuda.synchronize()
-    tiles = labels.host()["tiles"].reshape(s.H // 4, s.W // 8)
+    tiles = rec.reshape(s.H // 4, s.W // 8)
     planar, nrm, valid = sn.labels_from_tiles(tiles["status"], tiles["axis"],
                                               np.stack([tiles["a"], tiles["b"], tiles["c"]], -1))
     sg = seed.cpu().numpy().transpose(2, 0, 1).astype(np.float64)

@@ -364,7 +364,9 @@ __global__ void __launch_bounds__(kPackBlock) k_pack_plan(PackJob j0, const Pack
   }
 }
 
-// Header, tables and zeroed payload words, one 32-bit word per thread.
+// Header, tables and zeroed payload words.  16-byte units that lie inside
+// payloads (all but a few) are zeroed with one vector store; the units that
+// touch the header or a table are built byte by byte.
 __global__ void __launch_bounds__(kPackBlock) k_pack_fill(PackJob j0, const PackJob *jobs) {
   const PackJob *J = jobs ? jobs + blockIdx.y : &j0;
   const PackPlan *plan = J->plan;
@@ -372,7 +374,9 @@ __global__ void __launch_bounds__(kPackBlock) k_pack_fill(PackJob j0, const Pack
   const uint64_t total = plan->total;
   if (plan->err || total == 0) return;
   const uint64_t nw = (total + 3) / 4;
-  for (uint64_t w = (uint64_t)blockIdx.x * kPackBlock + threadIdx.x; w < nw; w += (uint64_t)gridDim.x * kPackBlock) {
+  uint64_t t0[4];
+  for (int q = 0; q < 4; q++) t0[q] = plan->nbytes[q] ? plan->table_at[q] : ~0ull - kTableBytes;
+  auto word = [&](uint64_t w) {
     uint32_t v = 0;
     for (int j = 0; j < 4; j++) {
       const uint64_t B = 4 * w + j;
@@ -380,27 +384,48 @@ __global__ void __launch_bounds__(kPackBlock) k_pack_fill(PackJob j0, const Pack
       if (B < kHeaderBytes) {
         byte = plan->head[B];
       } else {
-        for (int q = 0; q < 4; q++) {
-          const uint64_t t0 = plan->table_at[q];
-          if (plan->nbytes[q] && B >= t0 && B < t0 + kTableBytes) byte = plan->table[q][B - t0];
-        }
+        for (int q = 0; q < 4; q++)
+          if (B >= t0[q] && B < t0[q] + kTableBytes) byte = plan->table[q][B - t0[q]];
       }
       v |= byte << (8 * j);
     }
-    out[w] = v;
+    return v;
+  };
+  const uint64_t stride = (uint64_t)gridDim.x * kPackBlock, first = (uint64_t)blockIdx.x * kPackBlock + threadIdx.x;
+  if (((uintptr_t)out & 15) == 0) {
+    const uint64_t nu = nw / 4;                // whole 16-byte units
+    for (uint64_t u = first; u < nu; u += stride) {
+      const uint64_t B0 = 16 * u, B1 = B0 + 16;
+      bool special = B0 < kHeaderBytes;
+      for (int q = 0; q < 4; q++) special |= B0 < t0[q] + kTableBytes && B1 > t0[q];
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (special) v = make_uint4(word(4 * u), word(4 * u + 1), word(4 * u + 2), word(4 * u + 3));
+      reinterpret_cast<uint4 *>(out)[u] = v;
+    }
+    for (uint64_t w = 4 * nu + first; w < nw; w += stride) out[w] = word(w);
+  } else {
+    for (uint64_t w = first; w < nw; w += stride) out[w] = word(w);
   }
 }
 
 // Code words of buf[0..n) from container bit `bit0`, never past `bit_end`.
 // Each thread codes a contiguous share of the bytes at the prefix of the
-// shares' bit counts.
+// shares' bit counts.  buf is 4-byte aligned; a share is a whole number of
+// 32-bit words, an odd number of them, so that the lanes of a wavefront
+// reading their shares' k-th words hit distinct LDS banks.
 __device__ void encode_bytes(const uint8_t *buf, uint32_t n, uint64_t bit0, uint64_t bit_end, const uint8_t *len,
                              const uint32_t *code, uint32_t *out, uint32_t *red, uint32_t *err) {
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
-  const uint32_t per = (n + nt - 1) / nt;
+  uint32_t per = (((n + nt - 1) / nt) + 3) & ~3u;
+  if (((per >> 2) & 1u) == 0 && per) per += 4;
   const uint32_t b0 = min(n, tid * per), b1 = min(n, b0 + per);
+  const uint32_t *bw = reinterpret_cast<const uint32_t *>(buf);
   uint32_t nb = 0;
-  for (uint32_t i = b0; i < b1; i++) nb += len[buf[i]];
+  for (uint32_t i = b0; i < b1; i += 4) {
+    const uint32_t w = bw[i >> 2];
+    const uint32_t m = min(4u, b1 - i);
+    for (uint32_t k = 0; k < m; k++) nb += len[(w >> (8 * k)) & 255u];
+  }
   const uint32_t ex = block_excl_scan(nb, red, nullptr);
   const uint64_t start = bit0 + ex;
   uint64_t pos = start;
@@ -414,8 +439,10 @@ __device__ void encode_bytes(const uint8_t *buf, uint32_t n, uint64_t bit0, uint
   };
   uint64_t cw = pos >> 5;
   uint32_t acc = 0;
+  uint32_t w = 0;
   for (uint32_t i = b0; i < b1; i++) {
-    const uint32_t s = buf[i], L = len[s], c = code[s];
+    if (((i - b0) & 3u) == 0) w = bw[i >> 2];
+    const uint32_t s = (w >> (8 * ((i - b0) & 3u))) & 255u, L = len[s], c = code[s];
     if (pos + L > stop) {
       atomicOr(err, 2u);
       break;

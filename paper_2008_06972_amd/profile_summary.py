@@ -26,7 +26,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KINDS = (("k_batch_count", "count"), ("k_batch_scatter", "scatter"), ("k_batch_keyimage", "keyimage"),
          ("k_net_", "net"), ("k_batch_key", "key"),
          ("k_batch_pred", "pred"), ("k_batch_finish", "finish"), ("k_batch_offsets", "offsets"),
-         ("k_batch_reset", "reset"))
+         ("k_batch_reset", "reset"), ("k_pack_", "pack"))
 
 
 def kernel_source_hash() -> str:
@@ -46,7 +46,7 @@ def kind_of(name: str):
 
 
 def short(name: str, n: int = 60) -> str:
-    name = name.split("(")[0]
+    name = name.replace("(anonymous namespace)::", "").split("(")[0]
     return name if len(name) <= n else name[: n - 3] + "..."
 
 

@@ -297,16 +297,20 @@ class Sequence:
 
 def make_sequence(sensor: Sensor, kind: str, seed: int, n_frames: int = 10,
                   key_index: int | None = None, moving: int = 5, shuffle: bool = False,
-                  imu_noise: bool = False) -> Sequence:
+                  imu_noise: float = 0.0, corridor_frames: int | None = None) -> Sequence:
     """A group of consecutive frames with ego-motion 0.8-1.2 m forward and a
     yaw change of U(-0.5, 0.5) deg per frame, plus ``moving`` independently
     moving car-sized boxes.  The transform of frame i into the key frame is
-    ``pose_K^-1 pose_i`` in FP64, rounded to FP32; with ``imu_noise`` it is
-    perturbed by N(0, 5 cm) translation and N(0, 0.1 deg) yaw."""
+    ``pose_K^-1 pose_i`` in FP64, rounded to FP32; with ``imu_noise`` = s > 0
+    it is perturbed by N(0, s x 5 cm) translation (a fifth of that in z) and
+    N(0, s x 0.1 deg) yaw (True counts as s = 1).  The track's obstacle-free
+    corridor is sized for ``corridor_frames`` frames (default ``n_frames``), so
+    sequences of different lengths can share one scene distribution."""
     if key_index is None:
         key_index = n_frames // 2
     rng = _rng(seed, 0)
-    corridor = (-2.0 * n_frames - 5, 2.0 * n_frames + 5, -3.0, 3.0)
+    nc = n_frames if corridor_frames is None else max(n_frames, corridor_frames)
+    corridor = (-2.0 * nc - 5, 2.0 * nc + 5, -3.0, 3.0)
     scene = make_scene(kind, rng, moving=moving, corridor=corridor)
     poses = []
     heading, pos = 0.0, np.zeros(3)
@@ -334,8 +338,9 @@ def make_sequence(sensor: Sensor, kind: str, seed: int, n_frames: int = 10,
         M[:3, :3] = RK.T @ R
         M[:3, 3] = RK.T @ (P - PK)
         if imu_noise and i != key_index:
+            sc = float(imu_noise)
             nr = _rng(seed, 20_000 + i)
-            M[:3, :3] = rotz(nr.normal(0, 0.1 * DEG)) @ M[:3, :3]
-            M[:3, 3] += nr.normal(0, 0.05, size=3) * np.array([1, 1, 0.2])
+            M[:3, :3] = rotz(nr.normal(0, 0.1 * DEG) * sc) @ M[:3, :3]
+            M[:3, 3] += nr.normal(0, 0.05, size=3) * np.array([1, 1, 0.2]) * sc
         Ms[i] = M.astype(np.float32)
     return Sequence(sensor, frames, Ms, key_index, poses)

@@ -351,6 +351,23 @@ pc_status pc_batch_destroy(pc_batch *batch);
  * errors.  Returns PC_ERR_RANGE if any frame has PC_STATUS_RANGE set. */
 pc_status pc_check(pc_ctx *ctx, void *stream, const void *const *frames, int32_t nframes);
 
+/* ---- IMU front end (Sec. III-D, Eq. (4)-(5)) ---------------------------------
+ * The transform M of a predicted frame into its key frame from n equally
+ * spaced IMU samples (host arrays): acc[n][3] translational acceleration and
+ * gyro[n][3] rotational rate about the body x, y, z axes, dt the sample
+ * spacing, v0[3] the velocity at the first sample (NULL = 0).  Per sample
+ * (explicit Euler, the first-order Runge-Kutta method) the position advances
+ * by the velocity times dt, then the velocity by the acceleration times dt,
+ * and each rotational displacement by its rate times dt; T = the position
+ * (Eq. (4)), R = the printed product of the planar rotations by the
+ * accumulated z, y and x rotations (Eq. (5)).  M (host, 16 FP32, row-major
+ * [R | T; 0 0 0 1]) is the transform pc_encode_pred and the batch take;
+ * v_end (host, 3 FP32, may be NULL) receives the velocity after the last
+ * sample.  FP64 accumulation.  PC_ERR_ARG on n < 0, dt <= 0, NULL or
+ * non-finite input. */
+pc_status pc_imu_transform(const float *acc, const float *gyro, int32_t n, float dt, const float *v0, float *M,
+                           float *v_end);
+
 /* ---- entropy-coded bitstream (Sec. III-A) -----------------------------------
  * The frame's four byte streams, in the order the size model counts them:
  *   OCC  the occupancy bits, H*W/8 bytes (bit v*W+u of the little-endian

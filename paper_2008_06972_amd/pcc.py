@@ -88,7 +88,7 @@ def lib():
                      "pc_project", "pc_fit_key", "pc_encode_pred", "pc_decode", "pc_check", "pc_batch_create",
                      "pc_batch_run", "pc_batch_info", "pc_batch_profile", "pc_batch_destroy", "pc_net_forward",
                      "pc_net_backward", "pc_net_loss", "pc_net_adam", "pc_pack", "pc_unpack", "pc_pack_streams",
-                     "pc_unpack_streams", "pc_pack_batch"):
+                     "pc_unpack_streams", "pc_pack_batch", "pc_imu_transform"):
             getattr(L, name).restype = C.c_int
         L.pc_batch_workspace_size.restype = C.c_size_t
         L.pc_net_workspace_size.restype = C.c_size_t
@@ -107,7 +107,7 @@ EXPORTED = ("pc_stream_layout", "pc_workspace_size", "pc_ctx_create", "pc_ctx_de
             "pc_batch_info", "pc_batch_profile", "pc_batch_destroy", "pc_net_workspace_size", "pc_net_forward",
             "pc_net_backward", "pc_net_loss", "pc_net_adam", "pc_pack_bound", "pc_pack_workspace_size", "pc_pack",
             "pc_unpack", "pc_stream_pack_bound", "pc_stream_pack_workspace_size", "pc_pack_streams",
-            "pc_unpack_streams", "pc_pack_batch_workspace_size", "pc_pack_batch")
+            "pc_unpack_streams", "pc_pack_batch_workspace_size", "pc_pack_batch", "pc_imu_transform")
 PC_NET_PARAMS = 15636
 LAUNCH_KINDS = {0: "reset", 1: "count", 2: "offsets", 3: "scatter", 4: "key", 5: "pred", 6: "finish",
                 7: "keyimage", 8: "net"}
@@ -345,6 +345,19 @@ def pc_unpack_streams(ctx, data, n_in: int, work, work_bytes: int, streams, caps
     _check(lib().pc_unpack_streams(ctx, _ptr(data), C.c_uint64(n_in), _ptr(work), C.c_size_t(work_bytes),
                                    _ptrx4(streams), _u64x4(caps), n_out, _stream(stream)))
     return [int(x) for x in n_out]
+
+
+def pc_imu_transform(acc, gyro, dt: float, v0=None):
+    """(M 4x4 FP32, velocity after the last sample) from host IMU samples."""
+    a = np.ascontiguousarray(acc, dtype=np.float32).reshape(-1, 3)
+    g = np.ascontiguousarray(gyro, dtype=np.float32).reshape(-1, 3)
+    if len(a) != len(g):
+        raise ValueError("acc and gyro need the same number of samples")
+    v = None if v0 is None else np.ascontiguousarray(v0, dtype=np.float32).reshape(3)
+    M = np.zeros(16, np.float32)
+    ve = np.zeros(3, np.float32)
+    _check(lib().pc_imu_transform(_ptr(a), _ptr(g), C.c_int32(len(a)), C.c_float(dt), _ptr(v), _ptr(M), _ptr(ve)))
+    return M.reshape(4, 4), ve
 
 
 def pc_version() -> str:

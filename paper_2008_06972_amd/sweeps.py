@@ -2,7 +2,7 @@
 
     python -m paper_2008_06972_amd.sweeps frames  [--frames 960] [--ns 1,3,5,9,19]
     python -m paper_2008_06972_amd.sweeps denoise [--seqs 4]
-    python -m paper_2008_06972_amd.sweeps imu     [--scales 0,0.5,1,2,4,8]
+    python -m paper_2008_06972_amd.sweeps imu     [--scales 0,0.5,1,2,4,8] [--model pose|imu]
 
 ``frames``: for each number N of consecutive frames encoded together (key
 frame in the middle), about --frames frames of the 64x2048 sensor in
@@ -16,8 +16,10 @@ same dropout), and the decoded range's error against that noiseless truth
 is compared with the input's error against it, split by how the pixel was
 coded: the paper's observation that plane fitting smooths sensor noise.
 
-``imu``: pose errors of the kind IMU integration leaves (translation and
-yaw, scaled) are injected into the transforms; the sweep reports the
+``imu``: pose errors of the kind IMU integration leaves are injected into
+the transforms, either directly (translation and yaw, scaled) or by
+integrating IMU sensor noise with the library's front end
+(``pc_imu_transform``, Eq. (4)-(5)); the sweep reports the
 compression ratio, the temporal share, and the share of temporally coded
 pixels whose run needed its offset moved by more than eps, 2 eps from the
 key plane's: pixels that the fixed-normal offset relaxation (Sec. III-D)
@@ -137,6 +139,35 @@ def cmd_frames(a, pcc, torch):
     ctx.close()
 
 
+IMU_RATE = 100.0        # samples per second
+FRAME_DT = 0.1          # seconds between frames
+
+
+def imu_pose_errors(pcc, transforms, n, seed0, scale):
+    """Apply to each predicted frame's exact transform the pose error that the
+    IMU front end (pc_imu_transform) makes from sensor noise alone over the
+    samples between the frame and its key frame: white accelerometer noise
+    (0.05 s m/s^2 per sample), white gyro noise (0.002 s rad/s) plus a gyro
+    bias per sequence (0.002 s rad/s per axis), and an unknown velocity at
+    the first sample (0.1 s m/s per horizontal axis, a fifth of it in z)."""
+    out = transforms.copy()
+    for i in range(len(transforms)):
+        q, j = divmod(i, n)
+        k = n // 2
+        if j == k or scale == 0:
+            continue
+        rb = np.random.default_rng([seed0 + q, 1])
+        bias = rb.normal(0, 0.002 * scale, 3)
+        r = np.random.default_rng([seed0 + q, 2, j])
+        ns = int(round(abs(j - k) * FRAME_DT * IMU_RATE))
+        acc = r.normal(0, 0.05 * scale, (ns, 3))
+        gyro = r.normal(0, 0.002 * scale, (ns, 3)) + bias
+        v0 = r.normal(0, 0.1 * scale, 3) * np.array([1.0, 1.0, 0.2])
+        E, _ = pcc.pc_imu_transform(acc, gyro, 1.0 / IMU_RATE, v0)
+        out[i] = (E.astype(np.float64) @ transforms[i].astype(np.float64)).astype(np.float32)
+    return out
+
+
 def cmd_imu(a, pcc, torch):
     from paper_2008_06972_amd import synth
     S = pcc.Sensor.of(synth.SENSORS[SENSOR])
@@ -145,10 +176,18 @@ def cmd_imu(a, pcc, torch):
     n = a.n
     nseq = max(1, round(a.frames / n))
     for scale in [float(x) for x in a.scales.split(",")]:
-        frames, transforms = _workload(nseq, n, a.seed0, scale)
+        if a.model == "pose":
+            frames, transforms = _workload(nseq, n, a.seed0, scale)
+            noise = dict(sigma_translation_m=0.05 * scale, sigma_yaw_deg=0.1 * scale)
+        else:
+            frames, transforms = _workload(nseq, n, a.seed0, 0.0)
+            transforms = imu_pose_errors(pcc, transforms, n, a.seed0, scale)
+            noise = dict(acc_sigma=0.05 * scale, gyro_sigma=0.002 * scale, gyro_bias_sigma=0.002 * scale,
+                         v0_sigma=0.1 * scale, imu_rate_hz=IMU_RATE)
         ms, outs, key_of = _encode_batch(pcc, torch, ctx, S, prm, frames, transforms, n, a.steps, a.warmup)
-        row = dict(sweep="imu", scale=scale, sigma_translation_m=0.05 * scale, sigma_yaw_deg=0.1 * scale, N=n,
-                   frames=len(frames), frames_per_s=len(frames) / (ms / 1e3))
+        row = dict(sweep="imu", model=a.model, scale=scale, N=n, frames=len(frames),
+                   frames_per_s=len(frames) / (ms / 1e3))
+        row.update(noise)
         row.update(_summary(frames, outs))
         # temporal pixels whose run moved the key plane's offset by > eps, > 2 eps
         moved = {1: 0, 2: 0}
@@ -249,6 +288,8 @@ def main(argv=None):
     m.add_argument("--n", type=int, default=5)
     m.add_argument("--scales", default="0,0.5,1,2,4,8")
     m.add_argument("--seed0", type=int, default=8800)
+    m.add_argument("--model", choices=("pose", "imu"), default="pose",
+                   help="pose: perturb the transforms directly; imu: pose errors from IMU noise through pc_imu_transform")
     m.add_argument("--steps", type=int, default=5)
     m.add_argument("--warmup", type=int, default=1)
     a = ap.parse_args(argv)

@@ -506,12 +506,15 @@ static void emit_pixels(const float *range, const orc_sensor *s, const orc_param
     }
     if (nb & 7) put_byte(f, S_MASK, cur);
   }
-  /* RES: valid pixels no plane reproduces, frame raster order, u16 LE */
+  /* RES: valid pixels no plane reproduces, frame raster order; each code
+   * is sent as the zigzag-mapped difference (mod 2^16) from the previous
+   * residual code of its image row (0 before a row's first), u16 LE */
   float step, inv;
   quant_constants(prm->eps, &step, &inv);
   f->n_res = 0;
   f->range_error = 0;
-  for (int v = 0; v < H; v++)
+  for (int v = 0; v < H; v++) {
+    uint16_t prev = 0;
     for (int u = 0; u < W; u++) {
       float r = range[(int64_t)v * W + u];
       if (!(r > 0.0f)) continue;
@@ -527,9 +530,13 @@ static void emit_pixels(const float *range, const orc_sensor *s, const orc_param
       }
       uint16_t code = (uint16_t)q;
       f->codes[f->n_res++] = code;
-      put_byte(f, S_RES, code & 255u);
-      put_byte(f, S_RES, code >> 8);
+      const int16_t d = (int16_t)(uint16_t)(code - prev);
+      const uint16_t z = (uint16_t)(((uint16_t)d << 1) ^ (uint16_t)(d < 0 ? 0xFFFFu : 0u));
+      prev = code;
+      put_byte(f, S_RES, z & 255u);
+      put_byte(f, S_RES, (unsigned)z >> 8);
     }
+  }
 }
 
 static void alloc_free_tiles(int T, tile_t **tiles) { *tiles = (tile_t *)malloc(sizeof(tile_t) * (size_t)T); }

@@ -169,7 +169,57 @@ def encoded():
     return dict(prm=prm, key=key, pred=pred, rk=rk, rp=rp)
 
 
+def zigzag_row_deltas(codes, rows):
+    """RES bytes written out: per image row, each code's difference (mod
+    2^16) from the row's previous residual code, zigzag mapped, u16 LE."""
+    out = np.zeros(len(codes), np.uint16)
+    prev, last_row = 0, -1
+    for k, (c, r) in enumerate(zip(codes.astype(np.int64), rows)):
+        if r != last_row:
+            prev, last_row = 0, r
+        d = (int(c) - prev) & 0xFFFF
+        d = d - 0x10000 if d >= 0x8000 else d
+        out[k] = ((d << 1) ^ (-1 if d < 0 else 0)) & 0xFFFF
+        prev = int(c)
+    return out.astype("<u2").view(np.uint8)
+
+
+def residual_rows(f, rng, th, tw):
+    """Image row of each residual code (raster order) of an oracle frame."""
+    H, W = rng.shape
+    res = rng > 0
+    TC = W // tw
+    for t in range(len(f.cls)):
+        if f.cls[t] in (oracle.CLS_SPATIAL, oracle.CLS_TEMPORAL):
+            tr, tc = divmod(t, TC)
+            m = int(f.mask[t])
+            for j in range(th * tw):
+                if (m >> j) & 1:
+                    res[tr * th + j // tw, tc * tw + j % tw] = False
+    return np.nonzero(res)[0]
+
+
+def test_residual_prediction_hand_worked():
+    # 4 x 32 sensor, 4x8 tiles, too few points for any fit: every point is a
+    # residual.  Row 0 codes 100, 103, 98 -> differences 100, 3, -5 -> zigzag
+    # 200, 6, 9; row 1 codes 65000, 10 -> 65000 (as -536: 1071), then
+    # 10 - 65000 = 546 (mod 2^16) -> 1092.
+    H, W = 4, 32
+    tb = oracle.Tables(H, W, np.radians(np.array([3.0, 1.0, -1.0, -3.0])), 0.0)
+    prm = oracle.Params(eps=0.02, th=4, tw=8)
+    step = np.float32(2 * 0.02 * (1 - 2.0 ** -8))
+    img = np.zeros((H, W), np.float32)
+    for (v, u), c in {(0, 1): 100, (0, 5): 103, (0, 20): 98, (1, 3): 65000, (1, 30): 10}.items():
+        img[v, u] = np.float32(c) * step
+    f = oracle.encode_key(img, tb, prm)
+    assert f.n_res == 5 and list(f.codes) == [100, 103, 98, 65000, 10]
+    res = f.streams()[3]
+    assert list(res.view("<u2")) == [200, 6, 9, 1071, 1092]
+    assert np.array_equal(res, zigzag_row_deltas(f.codes, [0, 0, 0, 1, 1]))
+
+
 def test_streams_match_histograms_and_sources(encoded):
+    prm = encoded["prm"]
     for name, rng in (("key", encoded["rk"]), ("pred", encoded["rp"])):
         f = encoded[name]
         st = f.streams()
@@ -177,7 +227,8 @@ def test_streams_match_histograms_and_sources(encoded):
             assert len(st[q]) == f.stream_bytes[q]
             assert np.array_equal(np.bincount(st[q], minlength=256), f.hist[q])
         assert np.array_equal(st[0], np.packbits((rng > 0).ravel(), bitorder="little"))
-        assert np.array_equal(st[3], f.codes.astype("<u2").view(np.uint8))
+        rows = residual_rows(f, rng, prm.th, prm.tw)
+        assert np.array_equal(st[3], zigzag_row_deltas(f.codes, rows))
 
 
 def test_frame_round_trip_and_size(encoded):

@@ -968,12 +968,28 @@ __device__ __forceinline__ void residuals_and_streams(StripSmem<TH, TW> &sm, con
             bad = 1;
             q = fminf(q, 65535.0f);
           }
-          uint32_t code = (uint32_t)q;
-          res[o++] = (uint16_t)code;
-          hist_byte(sm.hist, S_RES, code & 255u);
-          hist_byte(sm.hist, S_RES, code >> 8);
+          res[o++] = (uint16_t)q;
         }
       }
+    }
+  }
+  // RES stream bytes: each code's zigzag difference (mod 2^16) from the
+  // previous residual code of its image row, 0 before a row's first; row i
+  // of the strip starts at the scanned count of (i, tile 0)
+  __syncthreads();
+  {
+    uint32_t rs[TH];
+#pragma unroll
+    for (int i = 0; i < TH; i++) rs[i] = sm.cnt()[i * TC];
+    for (uint32_t k = tid; k < total; k += kBlock) {
+      bool first = false;
+#pragma unroll
+      for (int i = 0; i < TH; i++) first |= k == rs[i];
+      const uint32_t code = res[k], prev = first ? 0u : res[k - 1];
+      const uint32_t d = (code - prev) & 0xFFFFu;
+      const uint32_t z = ((d << 1) ^ ((d & 0x8000u) ? 0xFFFFu : 0u)) & 0xFFFFu;
+      hist_byte(sm.hist, S_RES, z & 255u);
+      hist_byte(sm.hist, S_RES, z >> 8);
     }
   }
   // per-tile outputs

@@ -580,9 +580,36 @@ __global__ void __launch_bounds__(kPackBlock) k_pack_frame(PackJob j0, const Pac
       }
       n = tot;
     } else {
+      // each code as the zigzag difference (mod 2^16) from the previous
+      // residual code of its image row; rows start where the strip's
+      // uncovered non-empty pixels of the rows above end
+      __shared__ uint32_t rowc[8];
       const int nr = min(max(f.nres[tr], 0), th * W);
       const uint16_t *rs = f.res + (int64_t)tr * th * W;
-      for (int i = tid; i < nr; i += kPackBlock) ((uint16_t *)buf)[i] = rs[i];
+      if (tid < th) rowc[tid] = 0;
+      __syncthreads();
+      for (int tc = tid; tc < TC; tc += kPackBlock) {
+        const int64_t t = (int64_t)tr * TC + tc;
+        const int c = f.cls[t];
+        const uint64_t R = valid_bits(tc) & ~((c == CLS_SPATIAL || c == CLS_TEMPORAL) ? f.mask[t] : 0ull);
+        for (int i = 0; i < th; i++) {
+          const uint32_t k = (uint32_t)__popcll((R >> (i * tw)) & lowm);
+          if (k) atomicAdd(&rowc[i], k);
+        }
+      }
+      __syncthreads();
+      uint32_t st[8], acc = 0;
+      for (int i = 0; i < 8; i++) {
+        st[i] = i < th ? acc : 0xFFFFFFFFu;
+        acc += i < th ? rowc[i] : 0u;
+      }
+      for (int k = tid; k < nr; k += kPackBlock) {
+        bool first = false;
+        for (int i = 0; i < 8; i++) first |= (uint32_t)k == st[i];
+        const uint32_t prev = first ? 0u : rs[k - 1];
+        const uint32_t d = ((uint32_t)rs[k] - prev) & 0xFFFFu;
+        ((uint16_t *)buf)[k] = (uint16_t)(((d << 1) ^ ((d & 0x8000u) ? 0xFFFFu : 0u)) & 0xFFFFu);
+      }
       n = 2u * (uint32_t)nr;
     }
     __syncthreads();
@@ -828,7 +855,7 @@ __global__ void __launch_bounds__(kUnpackBlock) k_unpack_frame(UnpackPlan *up, S
                                                               FrameDev key, int has_key, int th, int tw, int W) {
   __shared__ uint32_t red[16];
   __shared__ uint32_t err;
-  __shared__ uint32_t nres[256];
+  __shared__ uint32_t rowcnt[1024], rowoff[1024];
   __shared__ uint32_t base;
   if (up->err) return;
   const int tid = threadIdx.x, TR = f.TR, TC = f.TC, T = f.T, H = TR * th;
@@ -995,21 +1022,29 @@ __global__ void __launch_bounds__(kUnpackBlock) k_unpack_frame(UnpackPlan *up, S
   }
   __syncthreads();
   if (tid == 0 && base != nmask) err |= 4u;
-  // residual codes: uncovered valid pixels of each strip, raster order
-  for (int r = tid; r < TR; r += kUnpackBlock) nres[r] = 0;
+  // residual codes: uncovered valid pixels of each image row, raster order;
+  // each stream value is the zigzag difference (mod 2^16) from the row's
+  // previous code, so every row is rebuilt by one thread from its start
+  for (int h = tid; h < H; h += kUnpackBlock) rowcnt[h] = 0;
   __syncthreads();
   for (int64_t t = tid; t < T; t += kUnpackBlock) {
-    const uint32_t c = (uint32_t)__popcll(valid_bits(t) & ~f.mask[t]);
-    if (c) atomicAdd(&nres[t / TC], c);
+    const uint64_t R = valid_bits(t) & ~f.mask[t];
+    const int tr = (int)(t / TC);
+    for (int i = 0; i < th; i++) {
+      const uint32_t c = (uint32_t)__popcll((R >> (i * tw)) & lowm);
+      if (c) atomicAdd(&rowcnt[tr * th + i], c);
+    }
   }
   __syncthreads();
   if (tid == 0) {
     uint32_t s = 0;
+    for (int h = 0; h < H; h++) {
+      rowoff[h] = s;
+      s += rowcnt[h];
+    }
     for (int r = 0; r < TR; r++) {
-      const uint32_t c = nres[r];
-      f.nres[r] = (int32_t)c;
-      nres[r] = s;
-      s += c;
+      const uint32_t end = r + 1 < TR ? rowoff[(r + 1) * th] : s;
+      f.nres[r] = (int32_t)(end - rowoff[r * th]);
     }
     if ((uint64_t)s * 2 != up->nbytes[S_RES]) err |= 4u;
     f.info->n_res = s;
@@ -1020,11 +1055,17 @@ __global__ void __launch_bounds__(kUnpackBlock) k_unpack_frame(UnpackPlan *up, S
     return;
   }
   const uint8_t *Rb = sp.p[S_RES];
-  for (int r = 0; r < TR; r++) {
-    const int c = f.nres[r];
-    const uint32_t b = nres[r];
-    uint16_t *dst = f.res + (int64_t)r * th * W;
-    for (int i = tid; i < c; i += kUnpackBlock) dst[i] = (uint16_t)(Rb[2 * (b + i)] | (Rb[2 * (b + i) + 1] << 8));
+  for (int h = tid; h < H; h += kUnpackBlock) {
+    const int r = h / th;
+    const uint32_t b = rowoff[h], c = rowcnt[h], in_strip = b - rowoff[r * th];
+    uint16_t *dst = f.res + (int64_t)r * th * W + in_strip;
+    uint32_t prev = 0;
+    for (uint32_t j = 0; j < c; j++) {
+      const uint32_t z = Rb[2 * (b + j)] | ((uint32_t)Rb[2 * (b + j) + 1] << 8);
+      const uint32_t d = (z >> 1) ^ ((z & 1u) ? 0xFFFFu : 0u);
+      prev = (prev + d) & 0xFFFFu;
+      dst[j] = (uint16_t)prev;
+    }
   }
 }
 

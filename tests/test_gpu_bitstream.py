@@ -121,6 +121,7 @@ def expected_streams(h, L, kind):
             prev = int(r["s"] + r["len"])
     valid = np.unpackbits(occ, bitorder="little").reshape(H, W).astype(bool)
     mask = bytearray()
+    resmap = valid.copy()
     for t in range(TR * TC):
         if h["cls"][t] not in (2, 3):
             continue
@@ -130,7 +131,22 @@ def expected_streams(h, L, kind):
         bits = [(m >> j) & 1 for j in range(th * tw) if v[j]]
         for b0 in range(0, len(bits), 8):
             mask.append(sum(bit << k for k, bit in enumerate(bits[b0:b0 + 8])))
-    res = h["codes"].astype("<u2").tobytes()
+        blk = resmap[tr * th:(tr + 1) * th, tc * tw:(tc + 1) * tw]
+        blk &= ~np.array([(m >> j) & 1 for j in range(th * tw)], bool).reshape(th, tw)
+    # residual codes: per image row, the zigzag difference (mod 2^16) from
+    # the row's previous code
+    rows = np.nonzero(resmap)[0]
+    codes = h["codes"].astype(np.int64)
+    assert len(rows) == len(codes)
+    z = np.zeros(len(codes), np.uint16)
+    prev, last = 0, -1
+    for k in range(len(codes)):
+        if rows[k] != last:
+            prev, last = 0, rows[k]
+        d = (int(codes[k]) - prev) & 0xFFFF
+        z[k] = ((d << 1) ^ (0xFFFF if d & 0x8000 else 0)) & 0xFFFF
+        prev = int(codes[k])
+    res = z.astype("<u2").tobytes()
     return [occ.copy(), np.frombuffer(bytes(run), np.uint8), np.frombuffer(bytes(mask), np.uint8),
             np.frombuffer(res, np.uint8)]
 

@@ -157,6 +157,23 @@ __device__ __forceinline__ Plane unpack_plane(float4 v) { return Plane{(int)v.w,
 __device__ __forceinline__ void hist_byte(uint32_t *hist, int stream, uint32_t v) {
   atomicAdd(&hist[stream * 128 + ((v & 255u) >> 1)], 1u << ((v & 1u) << 4));
 }
+// The two RES-stream bytes of a residual code given its row predecessor:
+// zigzag-mapped difference mod 2^16, little-endian.  The high byte is zero
+// for nearly every code; those counts are summed over the active lanes of
+// the wavefront and added once, instead of 64 atomics on one LDS word.
+__device__ __forceinline__ void hist_delta(uint32_t *hist, uint32_t code, uint32_t prev) {
+  const uint32_t d = (code - prev) & 0xFFFFu;
+  const uint32_t z = ((d << 1) ^ ((d & 0x8000u) ? 0xFFFFu : 0u)) & 0xFFFFu;
+  hist_byte(hist, S_RES, z & 255u);
+  const uint32_t hi = z >> 8;
+  const uint64_t zero = __ballot(hi == 0u);
+  if (hi != 0u) {
+    hist_byte(hist, S_RES, hi);
+  } else if ((int)(__lane_id()) == __ffsll((long long)zero) - 1) {
+    atomicAdd(&hist[S_RES * 128], (uint32_t)__popcll(zero));   // symbol 0: low half of the first word
+  }
+}
+
 __device__ __forceinline__ int varint_bytes(uint32_t *hist, uint32_t v) {
   int n = 0;
   while (v >= 128u) { hist_byte(hist, S_RUN, (v & 127u) | 128u); v >>= 7; n++; }
@@ -957,6 +974,8 @@ __device__ __forceinline__ void residuals_and_streams(StripSmem<TH, TW> &sm, con
 #pragma unroll
     for (int i = 0; i < TH; i++) {
       uint32_t o = sm.cnt()[i * TC + tc];
+      uint32_t prev = 0;
+      bool have = false;
 #pragma unroll
       for (int k = 0; k < TW; k++) {
         int j = i * TW + k;
@@ -968,29 +987,26 @@ __device__ __forceinline__ void residuals_and_streams(StripSmem<TH, TW> &sm, con
             bad = 1;
             q = fminf(q, 65535.0f);
           }
-          res[o++] = (uint16_t)q;
+          const uint32_t code = (uint32_t)q;
+          res[o++] = (uint16_t)code;
+          // RES stream bytes: the zigzag difference (mod 2^16) from the
+          // previous residual code of the image row; a segment's first code
+          // is done below, once its predecessor in an earlier tile is known
+          if (have) hist_delta(sm.hist, code, prev);
+          prev = code;
+          have = true;
         }
       }
     }
   }
-  // RES stream bytes: each code's zigzag difference (mod 2^16) from the
-  // previous residual code of its image row, 0 before a row's first; row i
-  // of the strip starts at the scanned count of (i, tile 0)
+  // first code of every (row, tile) segment: its predecessor is the code
+  // just before it in the strip's raster-order list, unless it opens its row
   __syncthreads();
-  {
-    uint32_t rs[TH];
-#pragma unroll
-    for (int i = 0; i < TH; i++) rs[i] = sm.cnt()[i * TC];
-    for (uint32_t k = tid; k < total; k += kBlock) {
-      bool first = false;
-#pragma unroll
-      for (int i = 0; i < TH; i++) first |= k == rs[i];
-      const uint32_t code = res[k], prev = first ? 0u : res[k - 1];
-      const uint32_t d = (code - prev) & 0xFFFFu;
-      const uint32_t z = ((d << 1) ^ ((d & 0x8000u) ? 0xFFFFu : 0u)) & 0xFFFFu;
-      hist_byte(sm.hist, S_RES, z & 255u);
-      hist_byte(sm.hist, S_RES, z >> 8);
-    }
+  for (int e = tid; e < TH * TC; e += kBlock) {
+    const uint32_t k = sm.cnt()[e], next = e + 1 < TH * TC ? sm.cnt()[e + 1] : total;
+    if (next == k) continue;
+    const uint32_t row0 = sm.cnt()[(e / TC) * TC];
+    hist_delta(sm.hist, res[k], k == row0 ? 0u : res[k - 1]);
   }
   // per-tile outputs
   for (int tc = tid; tc < TC; tc += kBlock) {

@@ -7,12 +7,16 @@
  * (Sec. III-C), the other frames reuse the key frame's planes after a rigid
  * transform with only the plane offset free (Sec. III-D), and what no plane
  * reproduces within the error bound eps is kept in a residual map whose
- * streams are sized by an optimal Huffman code (Sec. III-A).
+ * streams are sized by an optimal Huffman code (Sec. III-A).  The streams
+ * are emitted as length-limited canonical Huffman containers and read back
+ * (pc_pack, pc_unpack), and transforms can be integrated from IMU samples
+ * (pc_imu_transform, Eq. (4)-(5)).
  *
  * Conventions for every entry point
  *   - Pointers are DEVICE memory unless the comment says "host".
  *   - Every call is asynchronous on the given HIP stream (`stream` is a
- *     hipStream_t; NULL = the null stream).  The caller owns every buffer;
+ *     hipStream_t; NULL = the null stream), except those whose comment says
+ *     they synchronise.  The caller owns every buffer;
  *     the library keeps no pointer to caller memory after a call returns,
  *     except the workspace handed to pc_ctx_create.
  *   - Argument errors are detected on the host before any launch and

@@ -1350,7 +1350,6 @@ pc_status pc_unpack(pc_ctx *ctx, const void *data, uint64_t n_in, const void *ke
   if (stt) return stt;
   if (!data || !work || !frame_out) return set_error(PC_ERR_ARG, "data, workspace or frame is NULL");
   if (key == frame_out) return set_error(PC_ERR_ARG, "output frame must differ from the key frame");
-  if (L.TR > 256) return set_error(PC_ERR_UNSUPPORTED, "more than 256 tile rows");
   if (work_bytes < frame_ws(L)) return set_error(PC_ERR_CAPACITY, "workspace too small");
   hipStream_t st = (hipStream_t)stream;
   FrameCaps k = frame_caps(L);

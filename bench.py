@@ -279,6 +279,31 @@ def main():
     result["compression_ratio"] = forms[head]["compression_ratio"]
     result["compression_ratio_16B_per_point"] = forms[head]["compression_ratio"] * 16.0 / 12.0
 
+    # ------------------------------------------- host-to-device transfer
+    # the boundary takes device-resident points; a caller holding them in
+    # host memory adds one copy per pass (pinned memory, outside `value`)
+    tot_pts = sum(len(f) for f in frames_np)
+    host_pts = torch.empty((tot_pts, 3), dtype=torch.float32, pin_memory=True)
+    off = 0
+    for f in frames_np:
+        host_pts[off:off + len(f)] = torch.from_numpy(f)
+        off += len(f)
+    dev_pts = torch.empty((tot_pts, 3), dtype=torch.float32, device=dev)
+    dev_pts.copy_(host_pts, non_blocking=True)
+    torch.cuda.synchronize()
+    h0, h1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    h0.record(stream)
+    for _ in range(3):
+        dev_pts.copy_(host_pts, non_blocking=True)
+    h1.record(stream)
+    torch.cuda.synchronize()
+    h2d_ms = h0.elapsed_time(h1) / 3
+    result["h2d"] = {"bytes": 12 * tot_pts, "ms": h2d_ms, "GB/s": 12 * tot_pts / (h2d_ms / 1e3) / 1e9,
+                     "frames_per_s_including_h2d": nfr / ((result["ms_per_step"] + h2d_ms) / 1e3),
+                     "what": "every frame's points copied once from pinned host memory (not part of value)"}
+    log(f"h2d: {h2d_ms:.2f} ms for {12 * tot_pts / 1e9:.2f} GB")
+    del host_pts, dev_pts
+
     # ------------------------------------------------------------ roofline
     batch = batches.get(head)
     if batch is not None:

@@ -277,9 +277,12 @@ def test_unpack_rejects_malformed_containers(ctx, oracle_frames):
 
 
 # -------------------------------------------------------- frames on the GPU
-@pytest.mark.parametrize("kind,seed,th,tw", [("c1", 5000, 4, 4), ("c2", 5001, 4, 8), ("c2", 5002, 8, 8)])
+@pytest.mark.parametrize("kind,seed,th,tw", [("c1", 5000, 4, 4), ("c2", 5001, 4, 8), ("c2", 5002, 8, 8),
+                                             ("c2", 5003, 4, 16), ("ragged", 5004, 4, 8)])
 def test_frame_pack_unpack_decode(kind, seed, th, tw):
-    s = synth.SENSORS[kind]
+    # "ragged": 16 x 1056, 132 tiles of 8 per row (not a multiple of a wavefront)
+    s = synth.Sensor(16, 1056, 15.0, -15.0) if kind == "ragged" else synth.SENSORS[kind]
+    kind = "c1" if kind == "ragged" else kind
     S = pcc.Sensor.of(s)
     c = pcc.Context([S])
     try:
@@ -345,6 +348,37 @@ def test_frame_pack_unpack_decode(kind, seed, th, tw):
                 list(info.stream_bytes))
             if i == 0:
                 key_unpacked = out
+    finally:
+        c.close()
+
+
+def test_unpack_rejects_another_sensor_or_tile_shape():
+    s = synth.SENSORS["c1"]
+    S = pcc.Sensor.of(s)
+    c = pcc.Context([S])
+    try:
+        prm = pcc.params(eps=0.02, tile_h=4, tile_w=8)
+        pts, _, _ = synth.make_frame(s, "c1", 5200)
+        g = run_gpu_sequence(pcc, torch, c, S, prm, [pts], np.eye(4, dtype=np.float32)[None], 0, DEV)[0]
+        data, k, _, work = gpu_pack_frame(c, g["fs"], S, prm)
+        other = pcc.params(eps=0.02, tile_h=4, tile_w=4)
+        out = pcc.FrameStream(S, other, DEV)
+        ws = pcc.pc_pack_workspace_size(S, other)
+        w2 = torch.empty(ws, dtype=torch.uint8, device=DEV)
+        with pytest.raises(pcc.PcError):
+            pcc.pc_unpack(c.h, data, k, None, S, other, w2, ws, out)
+        S2 = pcc.Sensor.of(synth.Sensor(16, 1024, 15.0, -15.0))
+        out2 = pcc.FrameStream(S2, prm, DEV)
+        ws2 = pcc.pc_pack_workspace_size(S2, prm)
+        w3 = torch.empty(ws2, dtype=torch.uint8, device=DEV)
+        with pytest.raises(pcc.PcError):
+            pcc.pc_unpack(c.h, data, k, None, S2, prm, w3, ws2, out2)
+        # a predicted container needs its key frame
+        seq = synth.make_sequence(s, "c1", 5201, n_frames=2, key_index=0, shuffle=True)
+        gs = run_gpu_sequence(pcc, torch, c, S, prm, seq.frames, seq.transforms, 0, DEV)
+        dp, kp, _, wp = gpu_pack_frame(c, gs[1]["fs"], S, prm)
+        with pytest.raises(pcc.PcError):
+            pcc.pc_unpack(c.h, dp, kp, None, S, prm, wp, wp.numel(), pcc.FrameStream(S, prm, DEV))
     finally:
         c.close()
 

@@ -109,7 +109,7 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build encodes one GPU's share "
+        print("bench.py runs on one GPU only: it encodes one GPU's share of the sequences "
               "(sequences are independent, so N GPUs would each run this same batch)", file=sys.stderr)
         sys.exit(2)
 

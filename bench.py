@@ -92,6 +92,7 @@ def main():
     ap.add_argument("--cpu-seqs", type=int, default=96, help="oracle sample (sequences)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-pack", action="store_true", help="skip packing the frames into containers")
+    ap.add_argument("--no-decode", action="store_true", help="skip decoding the frames")
     ap.add_argument("--procs", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -392,6 +393,40 @@ def main():
             "what": "pc_pack_batch over every frame of the timed form (job-table upload included)"}
         log(f"bitstream: {int(packed.sum())} bytes vs model {int(model.sum())}, {pms:.3f} ms per batch pack")
         del cont, work
+
+    # ---------------------------------------------------------------- decode
+    # every frame of the head form decoded to its range image by one
+    # pc_decode_batch call (job-table upload included in the time)
+    if batch is not None and not a.no_decode:
+        Lh = batch.outs[0].L
+        prm_d = pcc.params(eps=EPS, tile_h=Lh.th, tile_w=Lh.tw, max_iter=5, min_pts=4, min_inlier_frac=0.5)
+        outs_d = batch.outs
+        dec = torch.empty((nfr, s.H, s.W), dtype=torch.float32, device=dev)
+        dec_list = [dec[i] for i in range(nfr)]
+        keys_d = [None if i == key_of(i) else outs_d[key_of(i)] for i in range(nfr)]
+        wsd = pcc.pc_decode_batch_workspace_size(nfr)
+        work_d = torch.empty(wsd, dtype=torch.uint8, device=dev)
+        pcc.pc_decode_batch(ctx.h, keys_d, outs_d, S, prm_d, dec_list, work_d, wsd, stream=stream)
+        torch.cuda.synchronize()
+        d0, d1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        d0.record(stream)
+        for _ in range(reps):
+            pcc.pc_decode_batch(ctx.h, keys_d, outs_d, S, prm_d, dec_list, work_d, wsd, stream=stream)
+        d1.record(stream)
+        torch.cuda.synchronize()
+        dms = d0.elapsed_time(d1) / reps
+        infos_d = [o.info() for o in outs_d]
+        Td, HWd = Lh.T, s.H * s.W
+        # algorithmic bytes: OCC, masks, run tables, codes read; key run
+        # planes read for temporal runs; the range image written
+        alg_d = sum(HWd // 8 + 8 * Td + 16 * (i.n_sruns + i.n_pruns) + 16 * i.n_pruns + 2 * i.n_res + 4 * HWd
+                    for i in infos_d)
+        result["decode"] = {"frames": nfr, "ms": dms, "frames_per_s": nfr / (dms / 1e3), "bytes": alg_d,
+                            "GB/s": alg_d / (dms / 1e3) / 1e9, "frac_of_hbm_peak": alg_d / (dms / 1e3) / 8e12,
+                            "what": "pc_decode_batch over every frame of the timed form (job-table upload included)"}
+        log(f"decode: {dms:.3f} ms for {nfr} frames")
+        del dec, dec_list, work_d
 
     # ------------------------------------------------------- CPU baseline
     if not a.no_cpu:

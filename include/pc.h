@@ -236,6 +236,17 @@ pc_status pc_encode_pred(pc_ctx *ctx, const void *key, const float *range, const
 pc_status pc_decode(pc_ctx *ctx, const void *key, const void *frame, const pc_sensor *sensor,
                     const pc_params *params, float *range_out, void *stream);
 
+/* pc_decode over n frames of one sensor and tile shape in one launch (a
+ * work-group per tile-row strip and frame).  frames, range_out: host arrays
+ * of n device pointers; keys: NULL (all key frames) or a host array whose
+ * entry i is frame i's key frame buffer, or NULL for a key frame.  The
+ * per-frame job table is uploaded into `work` (pc_decode_batch_workspace_size
+ * bytes), which synchronises `stream`. */
+size_t pc_decode_batch_workspace_size(int32_t n);
+pc_status pc_decode_batch(pc_ctx *ctx, int32_t n, const void *const *keys, const void *const *frames,
+                          const pc_sensor *sensor, const pc_params *params, float *const *range_out, void *work,
+                          size_t work_bytes, void *stream);
+
 /* ---- learned plane seeding -------------------------------------------------
  * A small convolutional network proposes, per 4x8 tile, a plane normal and a
  * planarity logit from the key frame's range image; pc_fit_key tries one

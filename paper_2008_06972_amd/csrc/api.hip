@@ -417,6 +417,42 @@ pc_status pc_decode(pc_ctx *ctx, const void *key, const void *frame, const pc_se
   return PC_OK;
 }
 
+size_t pc_decode_batch_workspace_size(int32_t n) { return n < 1 ? 0 : align256(sizeof(DecodeJob) * (size_t)n); }
+
+pc_status pc_decode_batch(pc_ctx *ctx, int32_t n, const void *const *keys, const void *const *frames,
+                          const pc_sensor *sensor, const pc_params *params, float *const *range_out, void *work,
+                          size_t work_bytes, void *stream) {
+  if (!ctx) return set_error(PC_ERR_ARG, "ctx is NULL");
+  if (n < 1 || n > 65535) return set_error(PC_ERR_ARG, "frame count %d out of range 1..65535", n);
+  pc_status st = check_sensor(sensor);
+  if (st) return st;
+  if ((st = check_params(sensor, params))) return st;
+  if (!frames || !range_out || !work) return set_error(PC_ERR_ARG, "frames, outputs or workspace is NULL");
+  if (work_bytes < pc_decode_batch_workspace_size(n)) return set_error(PC_ERR_CAPACITY, "workspace too small");
+  SensorEntry *e;
+  if ((st = get_sensor(ctx, sensor, &e))) return st;
+  pc_layout L;
+  pc_stream_layout(sensor, params, &L);
+  std::vector<DecodeJob> jobs((size_t)n);
+  for (int i = 0; i < n; i++) {
+    if (!frames[i] || !range_out[i]) return set_error(PC_ERR_ARG, "frame or output %d is NULL", i);
+    const void *k = keys ? keys[i] : nullptr;
+    jobs[i].f = frame_dev((void *)frames[i], L);
+    jobs[i].key = k ? frame_dev((void *)k, L) : jobs[i].f;
+    jobs[i].has_key = k ? 1 : 0;
+    jobs[i].out = range_out[i];
+  }
+  hipStream_t hs = (hipStream_t)stream;
+  DecodeJob *dj = (DecodeJob *)work;
+  // the job table is read by the launch; the host copy must outlive the upload
+  if (hipMemcpyAsync(dj, jobs.data(), sizeof(DecodeJob) * (size_t)n, hipMemcpyHostToDevice, hs) != hipSuccess ||
+      hipStreamSynchronize(hs) != hipSuccess)
+    return set_error(PC_ERR_DEVICE, "job table upload failed");
+  hipError_t he = launch_decode_jobs(jobs[0], dj, n, e->sd, enc_params(params), hs);
+  if (he != hipSuccess) return set_error(PC_ERR_DEVICE, "decode launch failed: %s", hipGetErrorString(he));
+  return PC_OK;
+}
+
 pc_status pc_check(pc_ctx *ctx, void *stream, const void *const *frames, int32_t nframes) {
   if (!ctx) return set_error(PC_ERR_ARG, "ctx is NULL");
   if (nframes < 0 || (nframes > 0 && !frames)) return set_error(PC_ERR_ARG, "bad frame list");

@@ -7,11 +7,43 @@
 
 namespace pcc {
 
+// Exclusive prefix sum of a[0..n) in place, by the whole work-group: each
+// thread sums a contiguous share, wavefronts scan the shares, the
+// wavefront totals are combined through LDS.
+__device__ __forceinline__ void block_prefix(uint32_t *a, int n, uint32_t *wsum) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int per = (n + kBlock - 1) / kBlock, b = min(n, tid * per), e = min(n, b + per);
+  uint32_t local = 0;
+  for (int q = b; q < e; q++) local += a[q];
+  uint32_t x = local;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[wv] = x;
+  __syncthreads();
+  uint32_t run = x - local;
+  for (int w = 0; w < wv; w++) run += wsum[w];
+  for (int q = b; q < e; q++) {
+    const uint32_t c = a[q];
+    a[q] = run;
+    run += c;
+  }
+  __syncthreads();
+}
+
+// One work-group per (tile-row strip, frame); blockIdx.y picks the frame's
+// job from `jobs`, or j0 when jobs is NULL.
 template <int TH, int TW>
-__global__ void __launch_bounds__(kBlock) k_decode(FrameDev key, int has_key, FrameDev f, SensorDev s, EncParams p,
-                                                   float *__restrict__ out) {
+__global__ void __launch_bounds__(kBlock) k_decode(DecodeJob j0, const DecodeJob *jobs, SensorDev s, EncParams p) {
   extern __shared__ __align__(16) char smem_raw[];
+  __shared__ uint32_t wsum[kBlock / 64];
   constexpr int N = TH * TW;
+  const DecodeJob *J = jobs ? jobs + blockIdx.y : &j0;
+  const FrameDev f = J->f;
+  const int has_key = J->has_key;
+  float *__restrict__ out = J->out;
   const int TC = f.TC, tr = blockIdx.x, tid = threadIdx.x, W = s.W;
   float4 *pl = (float4 *)smem_raw;                          // [TC]
   uint8_t *has = (uint8_t *)(pl + TC);                      // [TC]
@@ -29,10 +61,11 @@ __global__ void __launch_bounds__(kBlock) k_decode(FrameDev key, int has_key, Fr
   }
   // temporal runs: key run's normal, own offset
   if (has_key) {
+    const pc_run *ksr = J->key.sruns;
     const int np = f.nruns[f.TR + tr];
     for (int q = tid; q < np; q += kBlock) {
       pc_prun R = f.pruns[(int64_t)tr * TC + q];
-      pc_run K = key.sruns[R.krun];
+      pc_run K = ksr[R.krun];
       for (int e = 0; e < R.len; e++) {
         pl[R.s + e] = make_float4(K.a, K.b, R.c, (float)K.axis);
         has[R.s + e] = 1;
@@ -53,15 +86,7 @@ __global__ void __launch_bounds__(kBlock) k_decode(FrameDev key, int has_key, Fr
     }
   }
   __syncthreads();
-  if (tid == 0) {     // exclusive prefix (TH * TC entries, small)
-    uint32_t run = 0;
-    for (int q = 0; q < TH * TC; q++) {
-      uint32_t c = cnt[q];
-      cnt[q] = run;
-      run += c;
-    }
-  }
-  __syncthreads();
+  block_prefix(cnt, TH * TC, wsum);
   const uint16_t *res = f.res + (int64_t)tr * TH * W;
   for (int tc = tid; tc < TC; tc += kBlock) {
     bool hp = has[tc] != 0;
@@ -92,23 +117,33 @@ __global__ void __launch_bounds__(kBlock) k_decode(FrameDev key, int has_key, Fr
 }
 
 template <int TH, int TW>
-static hipError_t launch_decode_t(const FrameDev *key, const FrameDev &f, const SensorDev &s, const EncParams &p,
-                                  float *out, hipStream_t st) {
-  size_t sh = sizeof(float4) * f.TC + ((f.TC + 15) & ~15) + sizeof(uint32_t) * TH * f.TC + 64;
+static hipError_t launch_decode_t(const DecodeJob &j0, const DecodeJob *jobs, int n, int TR, int TC,
+                                  const SensorDev &s, const EncParams &p, hipStream_t st) {
+  size_t sh = sizeof(float4) * TC + ((TC + 15) & ~15) + sizeof(uint32_t) * TH * TC + 64;
   hipError_t e = hipFuncSetAttribute((const void *)k_decode<TH, TW>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
   if (e != hipSuccess) return e;
-  FrameDev k = key ? *key : f;
-  hipLaunchKernelGGL((k_decode<TH, TW>), dim3(f.TR), dim3(kBlock), sh, st, k, key ? 1 : 0, f, s, p, out);
+  hipLaunchKernelGGL((k_decode<TH, TW>), dim3(TR, n), dim3(kBlock), sh, st, j0, jobs, s, p);
   return hipGetLastError();
+}
+
+hipError_t launch_decode_jobs(const DecodeJob &j0, const DecodeJob *jobs, int n, const SensorDev &s,
+                              const EncParams &p, hipStream_t st) {
+  const int TR = j0.f.TR, TC = j0.f.TC;
+  if (p.th == 4 && p.tw == 4) return launch_decode_t<4, 4>(j0, jobs, n, TR, TC, s, p, st);
+  if (p.th == 4 && p.tw == 8) return launch_decode_t<4, 8>(j0, jobs, n, TR, TC, s, p, st);
+  if (p.th == 4 && p.tw == 16) return launch_decode_t<4, 16>(j0, jobs, n, TR, TC, s, p, st);
+  if (p.th == 8 && p.tw == 8) return launch_decode_t<8, 8>(j0, jobs, n, TR, TC, s, p, st);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_decode(const FrameDev *key, const FrameDev &f, const SensorDev &s, const EncParams &p,
                          float *range_out, hipStream_t st) {
-  if (p.th == 4 && p.tw == 4) return launch_decode_t<4, 4>(key, f, s, p, range_out, st);
-  if (p.th == 4 && p.tw == 8) return launch_decode_t<4, 8>(key, f, s, p, range_out, st);
-  if (p.th == 4 && p.tw == 16) return launch_decode_t<4, 16>(key, f, s, p, range_out, st);
-  if (p.th == 8 && p.tw == 8) return launch_decode_t<8, 8>(key, f, s, p, range_out, st);
-  return hipErrorInvalidValue;
+  DecodeJob j;
+  j.f = f;
+  j.key = key ? *key : f;
+  j.has_key = key ? 1 : 0;
+  j.out = range_out;
+  return launch_decode_jobs(j, nullptr, 1, s, p, st);
 }
 
 }  // namespace pcc

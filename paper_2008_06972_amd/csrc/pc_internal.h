@@ -76,6 +76,16 @@ hipError_t launch_key(const float *range, const SensorDev &s, const EncParams &p
                       const FrameDev &f, const float *M12, hipStream_t st);
 hipError_t launch_pred(const FrameDev &key, const float *range, const SensorDev &s, const EncParams &p,
                        const FrameDev &f, const float *M12, hipStream_t st);
+// One frame of a decode launch: the frame, its key frame (temporal runs take
+// the key run's normal), the output range image.
+struct DecodeJob {
+  FrameDev key;
+  FrameDev f;
+  float *out;
+  int has_key;
+};
+hipError_t launch_decode_jobs(const DecodeJob &j0, const DecodeJob *jobs, int n, const SensorDev &s,
+                              const EncParams &p, hipStream_t st);
 hipError_t launch_decode(const FrameDev *key, const FrameDev &f, const SensorDev &s, const EncParams &p,
                          float *range_out, hipStream_t st);
 

@@ -88,13 +88,14 @@ def lib():
                      "pc_project", "pc_fit_key", "pc_encode_pred", "pc_decode", "pc_check", "pc_batch_create",
                      "pc_batch_run", "pc_batch_info", "pc_batch_profile", "pc_batch_destroy", "pc_net_forward",
                      "pc_net_backward", "pc_net_loss", "pc_net_adam", "pc_pack", "pc_unpack", "pc_pack_streams",
-                     "pc_unpack_streams", "pc_pack_batch", "pc_imu_transform"):
+                     "pc_unpack_streams", "pc_pack_batch", "pc_imu_transform", "pc_decode_batch"):
             getattr(L, name).restype = C.c_int
         L.pc_batch_workspace_size.restype = C.c_size_t
         L.pc_net_workspace_size.restype = C.c_size_t
         L.pc_pack_bound.restype = C.c_size_t
         L.pc_pack_workspace_size.restype = C.c_size_t
         L.pc_pack_batch_workspace_size.restype = C.c_size_t
+        L.pc_decode_batch_workspace_size.restype = C.c_size_t
         L.pc_stream_pack_bound.restype = C.c_uint64
         L.pc_stream_pack_workspace_size.restype = C.c_size_t
         _lib = L
@@ -107,7 +108,8 @@ EXPORTED = ("pc_stream_layout", "pc_workspace_size", "pc_ctx_create", "pc_ctx_de
             "pc_batch_info", "pc_batch_profile", "pc_batch_destroy", "pc_net_workspace_size", "pc_net_forward",
             "pc_net_backward", "pc_net_loss", "pc_net_adam", "pc_pack_bound", "pc_pack_workspace_size", "pc_pack",
             "pc_unpack", "pc_stream_pack_bound", "pc_stream_pack_workspace_size", "pc_pack_streams",
-            "pc_unpack_streams", "pc_pack_batch_workspace_size", "pc_pack_batch", "pc_imu_transform")
+            "pc_unpack_streams", "pc_pack_batch_workspace_size", "pc_pack_batch", "pc_imu_transform",
+            "pc_decode_batch_workspace_size", "pc_decode_batch")
 PC_NET_PARAMS = 15636
 LAUNCH_KINDS = {0: "reset", 1: "count", 2: "offsets", 3: "scatter", 4: "key", 5: "pred", 6: "finish",
                 7: "keyimage", 8: "net"}
@@ -238,6 +240,21 @@ def pc_encode_pred(ctx, key, range_img, M_host, sensor: Sensor, prm: pc_params, 
 def pc_decode(ctx, key, frame, sensor: Sensor, prm: pc_params, range_out, stream=None):
     _check(lib().pc_decode(ctx, _ptr(key), _ptr(frame), C.byref(sensor.c), C.byref(prm), _ptr(range_out),
                            _stream(stream)))
+
+
+def pc_decode_batch_workspace_size(n: int) -> int:
+    return int(lib().pc_decode_batch_workspace_size(C.c_int32(n)))
+
+
+def pc_decode_batch(ctx, keys, frames, sensor: Sensor, prm: pc_params, range_out, work, work_bytes: int,
+                    stream=None):
+    """keys: None or a list with None for key frames."""
+    n = len(frames)
+    ka = None if keys is None else (C.c_void_p * n)(*[(_ptr(k).value if k is not None else None) for k in keys])
+    fa = (C.c_void_p * n)(*[_ptr(f).value for f in frames])
+    oa = (C.c_void_p * n)(*[_ptr(o).value for o in range_out])
+    _check(lib().pc_decode_batch(ctx, C.c_int32(n), ka, fa, C.byref(sensor.c), C.byref(prm), oa, _ptr(work),
+                                 C.c_size_t(work_bytes), _stream(stream)))
 
 
 def pc_check(ctx, frames, stream=None):

@@ -26,7 +26,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KINDS = (("k_batch_count", "count"), ("k_batch_scatter", "scatter"), ("k_batch_keyimage", "keyimage"),
          ("k_net_", "net"), ("k_batch_key", "key"),
          ("k_batch_pred", "pred"), ("k_batch_finish", "finish"), ("k_batch_offsets", "offsets"),
-         ("k_batch_reset", "reset"), ("k_pack_", "pack"))
+         ("k_batch_reset", "reset"), ("k_pack_", "pack"), ("k_decode", "decode"))
 
 
 def kernel_source_hash() -> str:

@@ -228,3 +228,28 @@ def test_empty_and_ragged_frames(ctx_factory):
     assert st["size_rel"] <= 0.005
     v = g["range"] > 0
     assert np.abs(g["dec"][v].astype(np.float64) - g["range"][v]).max() <= 0.02
+
+
+def test_decode_batch_equals_per_frame(ctx_factory):
+    """One decode launch over a whole sequence (key and predicted frames)
+    gives the per-frame decoder's ranges bit for bit."""
+    s = synth.SENSORS["c2"]
+    S = pcc.Sensor.of(s)
+    ctx = ctx_factory(S)
+    seq = synth.make_sequence(s, "c2", 2300, n_frames=6, key_index=3, shuffle=True)
+    prm = pcc.params(eps=0.02, tile_h=4, tile_w=8)
+    g = run_gpu_sequence(pcc, torch, ctx, S, prm, seq.frames, seq.transforms, 3, DEV)
+    n = len(g)
+    outs = [torch.full((s.H, s.W), -1.0, dtype=torch.float32, device=DEV) for _ in range(n)]
+    ws = pcc.pc_decode_batch_workspace_size(n)
+    work = torch.empty(ws, dtype=torch.uint8, device=DEV)
+    keys = [None if i == 3 else g[3]["fs"] for i in range(n)]
+    pcc.pc_decode_batch(ctx.h, keys, [x["fs"] for x in g], S, prm, outs, work, ws)
+    torch.cuda.synchronize()
+    for i in range(n):
+        assert np.array_equal(outs[i].cpu().numpy(), g[i]["dec"]), f"frame {i}"
+    # key frames only, no key list
+    o1 = [torch.empty(s.H, s.W, dtype=torch.float32, device=DEV)]
+    pcc.pc_decode_batch(ctx.h, None, [g[3]["fs"]], S, prm, o1, work, ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(o1[0].cpu().numpy(), g[3]["dec"])

@@ -392,7 +392,27 @@ def main():
             "pack_host_ms": (time.time() - t_host) * 1e3 / reps,
             "what": "pc_pack_batch over every frame of the timed form (job-table upload included)"}
         log(f"bitstream: {int(packed.sum())} bytes vs model {int(model.sum())}, {pms:.3f} ms per batch pack")
-        del cont, work
+        # decode from bytes: every container back into a frame buffer
+        # (pc_unpack_batch, which synchronises), then checked against the
+        # frames it was packed from through their decoded ranges' sizes
+        outs_u = [pcc.FrameStream(S, prm_h, dev) for _ in range(nfr)]
+        keys_u = [None if i == key_of(i) else outs_u[key_of(i)] for i in range(nfr)]
+        wsu = pcc.pc_unpack_batch_workspace_size(S, prm_h, nfr)
+        work_u = torch.empty(wsu, dtype=torch.uint8, device=dev)
+        sizes_u = [int(x) for x in packed]
+        pcc.pc_unpack_batch(ctx.h, outs_c, sizes_u, keys_u, S, prm_h, work_u, wsu, outs_u, stream=stream)
+        u0 = time.time()
+        reps_u = 3
+        for _ in range(reps_u):
+            pcc.pc_unpack_batch(ctx.h, outs_c, sizes_u, keys_u, S, prm_h, work_u, wsu, outs_u, stream=stream)
+        ums = (time.time() - u0) * 1e3 / reps_u
+        same = all(int(u.info().n_res) == int(o.info().n_res) for u, o in zip(outs_u, batch.outs))
+        result["bitstream"].update({"unpack_ms": ums, "unpack_frames_per_s": nfr / (ums / 1e3),
+                                    "unpacked_residuals_equal": bool(same),
+                                    "unpack_what": "pc_unpack_batch of every container, host clock around the "
+                                                   "synchronising call"})
+        log(f"unpack: {ums:.2f} ms per batch")
+        del cont, work, outs_u, work_u
 
     # ---------------------------------------------------------------- decode
     # every frame of the head form decoded to its range image by one

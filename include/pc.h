@@ -447,6 +447,20 @@ pc_status pc_unpack(pc_ctx *ctx, const void *data, uint64_t n_in, const void *ke
                     const pc_params *params, void *work, size_t work_bytes, void *frame_out, int32_t *kind_out,
                     void *stream);
 
+/* pc_unpack over n containers of one sensor and tile shape: data and
+ * frames_out are host arrays of n device pointers, n_in (host) the
+ * containers' sizes, keys NULL or a host array whose entry i is the key
+ * frame buffer of a predicted container i (it may be another output of the
+ * same call: key frames are parsed first), NULL for key frames.  kinds_out
+ * (host int32[n], may be NULL) receives each container's kind.  Headers,
+ * streams and frame buffers of all containers are decoded by five launches;
+ * the job table upload and the final status read synchronise `stream`.
+ * PC_ERR_ARG names the first failing container. */
+size_t pc_unpack_batch_workspace_size(const pc_sensor *sensor, const pc_params *params, int32_t n);
+pc_status pc_unpack_batch(pc_ctx *ctx, int32_t n, const void *const *data, const uint64_t *n_in,
+                          const void *const *keys, const pc_sensor *sensor, const pc_params *params, void *work,
+                          size_t work_bytes, void *const *frames_out, int32_t *kinds_out, void *stream);
+
 /* The same coder on four raw device byte streams of n[4] bytes each (below
  * 2^28), with the header fields given; `out` needs pc_stream_pack_bound(n)
  * bytes and `work` pc_stream_pack_workspace_size(n). */

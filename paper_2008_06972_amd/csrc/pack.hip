@@ -678,8 +678,7 @@ __device__ __forceinline__ uint32_t rd_u32(const uint8_t *p) {
 
 // Header and code tables.  One thread; the container is small at this point
 // of the check (header and four tables).
-__global__ void k_unpack_plan(const uint8_t *in, uint64_t n_in, UnpackPlan *up, const uint64_t *caps) {
-  if (threadIdx.x != 0) return;
+__device__ void unpack_plan(const uint8_t *in, uint64_t n_in, UnpackPlan *up, const uint64_t *caps) {
   uint32_t err = 0;
   for (int q = 0; q < 4; q++) up->nbytes[q] = up->nbits[q] = up->bit0[q] = 0;
   if (n_in < kHeaderBytes || rd_u32(in) != kMagic) {
@@ -775,13 +774,13 @@ __device__ __forceinline__ void decode_sub(const DecTab &t, const uint8_t *pay, 
   *cnt = c;
 }
 
-// One work-group per stream.
-__global__ void __launch_bounds__(kUnpackBlock) k_unpack_streams(const uint8_t *in, UnpackPlan *up, uint64_t *sub,
-                                                                uint32_t *subc, StreamPtrs outp) {
+// Stream q of one container, by one work-group.
+__device__ __forceinline__ void unpack_stream(int q, const uint8_t *in, UnpackPlan *up, uint64_t *sub, uint32_t *subc,
+                                              const StreamPtrs &outp) {
   __shared__ DecTab t;
   __shared__ uint32_t red[16];
   __shared__ int any, skip;
-  const int q = blockIdx.x, tid = threadIdx.x;
+  const int tid = threadIdx.x;
   // other streams may raise up->err meanwhile: decide once for the group
   if (tid == 0) skip = (up->err & 1u) != 0;
   __syncthreads();
@@ -851,8 +850,8 @@ __global__ void __launch_bounds__(kUnpackBlock) k_unpack_streams(const uint8_t *
 
 // Streams back into a frame stream buffer: occupancy words, runs and tile
 // classes, masks, residual codes per strip.  One work-group.
-__global__ void __launch_bounds__(kUnpackBlock) k_unpack_frame(UnpackPlan *up, StreamPtrs sp, FrameDev f,
-                                                              FrameDev key, int has_key, int th, int tw, int W) {
+__device__ __forceinline__ void unpack_frame(UnpackPlan *up, const StreamPtrs &sp, const FrameDev &f,
+                                             const FrameDev &key, int has_key, int th, int tw, int W) {
   __shared__ uint32_t red[16];
   __shared__ uint32_t err;
   __shared__ uint32_t rowcnt[1024], rowoff[1024];
@@ -1067,6 +1066,75 @@ __global__ void __launch_bounds__(kUnpackBlock) k_unpack_frame(UnpackPlan *up, S
       dst[j] = (uint16_t)prev;
     }
   }
+}
+
+// One container's decoding job (batched unpacking).
+struct UnpackJob {
+  const uint8_t *in;
+  uint64_t n_in;
+  UnpackPlan *up;
+  uint64_t *sub;
+  uint32_t *subc;
+  const uint64_t *caps;
+  StreamPtrs sp;
+  FrameDev f, key;
+  int has_key;
+};
+
+__global__ void k_unpack_plan(const uint8_t *in, uint64_t n_in, UnpackPlan *up, const uint64_t *caps) {
+  if (threadIdx.x == 0) unpack_plan(in, n_in, up, caps);
+}
+__global__ void k_unpack_plan_b(const UnpackJob *jobs) {
+  if (threadIdx.x == 0) {
+    const UnpackJob &J = jobs[blockIdx.x];
+    unpack_plan(J.in, J.n_in, J.up, J.caps);
+  }
+}
+
+// One work-group per stream (and container).
+__global__ void __launch_bounds__(kUnpackBlock) k_unpack_streams(const uint8_t *in, UnpackPlan *up, uint64_t *sub,
+                                                                uint32_t *subc, StreamPtrs outp) {
+  unpack_stream(blockIdx.x, in, up, sub, subc, outp);
+}
+__global__ void __launch_bounds__(kUnpackBlock) k_unpack_streams_b(const UnpackJob *jobs) {
+  const UnpackJob &J = jobs[blockIdx.y];
+  unpack_stream(blockIdx.x, J.in, J.up, J.sub, J.subc, J.sp);
+}
+
+__global__ void __launch_bounds__(kUnpackBlock) k_unpack_frame(UnpackPlan *up, StreamPtrs sp, FrameDev f,
+                                                              FrameDev key, int has_key, int th, int tw, int W) {
+  unpack_frame(up, sp, f, key, has_key, th, tw, W);
+}
+// Containers of kind `pass` (0 key frames first, then 1 predicted frames,
+// which read their key frames' run slots), after checking the header's
+// sensor size and tile shape and that a predicted frame has a key frame.
+__global__ void __launch_bounds__(kUnpackBlock) k_unpack_frame_b(const UnpackJob *jobs, int pass, int H, int W, int th,
+                                                                int tw) {
+  const UnpackJob &J = jobs[blockIdx.x];
+  UnpackPlan *up = J.up;
+  __shared__ int go;
+  if (threadIdx.x == 0) {
+    int g = 0;
+    if (!up->err && pass == 0 && up->kind != 0 && up->kind != 1) up->err |= 8u;
+    if (!up->err && up->kind == pass) {
+      if (up->H != H || up->W != W || up->th != th || up->tw != tw)
+        up->err |= 8u;
+      else if (pass == 1 && !J.has_key)
+        up->err |= 16u;
+      else
+        g = 1;
+    }
+    go = g;
+  }
+  __syncthreads();
+  if (!go) return;
+  unpack_frame(up, J.sp, J.f, J.key, J.has_key, th, tw, W);
+}
+
+// Per container: error bits in the low 16 bits, kind in the next 8.
+__global__ void k_unpack_status(const UnpackJob *jobs, int n, uint32_t *status) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) status[i] = (jobs[i].up->err & 0xFFFFu) | ((uint32_t)(jobs[i].up->kind & 0xFF) << 16);
 }
 
 // ------------------------------------------------------------------ sizing
@@ -1339,6 +1407,89 @@ pc_status pc_unpack_streams(pc_ctx *ctx, const void *data, uint64_t n_in, void *
   pc_status s = unpack_to_streams((const uint8_t *)data, n_in, (char *)work, caps, o, &h, (hipStream_t)stream);
   for (int q = 0; q < 4; q++) n_out[q] = s == PC_OK ? h.nbytes[q] : 0;
   return s;
+}
+
+size_t pc_unpack_batch_workspace_size(const pc_sensor *sensor, const pc_params *params, int32_t n) {
+  pc_layout L;
+  if (n < 1 || pc_stream_layout(sensor, params, &L) != PC_OK) return 0;
+  FrameCaps k = frame_caps(L);
+  size_t per = unpack_ws();
+  for (int q = 0; q < 4; q++) per += a256(k.c[q]);
+  return a256(sizeof(UnpackJob) * (size_t)n) + a256(sizeof(uint32_t) * (size_t)n) + a256(sizeof(uint64_t) * 4) +
+         (size_t)n * per;
+}
+
+pc_status pc_unpack_batch(pc_ctx *ctx, int32_t n, const void *const *data, const uint64_t *n_in,
+                          const void *const *keys, const pc_sensor *sensor, const pc_params *params, void *work,
+                          size_t work_bytes, void *const *frames_out, int32_t *kinds_out, void *stream) {
+  if (!ctx) return set_error(PC_ERR_ARG, "ctx is NULL");
+  if (n < 1 || n > 65535) return set_error(PC_ERR_ARG, "container count %d out of range 1..65535", n);
+  pc_layout L;
+  pc_status stt = pc_stream_layout(sensor, params, &L);
+  if (stt) return stt;
+  if (!data || !n_in || !work || !frames_out) return set_error(PC_ERR_ARG, "NULL argument");
+  const size_t need = pc_unpack_batch_workspace_size(sensor, params, n);
+  if (work_bytes < need) return set_error(PC_ERR_CAPACITY, "workspace %zu bytes < %zu", work_bytes, need);
+  FrameCaps k = frame_caps(L);
+  char *ws = (char *)work;
+  UnpackJob *dj = (UnpackJob *)ws;
+  ws += a256(sizeof(UnpackJob) * (size_t)n);
+  uint32_t *dstatus = (uint32_t *)ws;
+  ws += a256(sizeof(uint32_t) * (size_t)n);
+  uint64_t *dcaps = (uint64_t *)ws;
+  ws += a256(sizeof(uint64_t) * 4);
+  std::vector<UnpackJob> jobs((size_t)n);
+  for (int i = 0; i < n; i++) {
+    if (!data[i] || !frames_out[i]) return set_error(PC_ERR_ARG, "container or output frame %d is NULL", i);
+    const void *key = keys ? keys[i] : nullptr;
+    if (key == frames_out[i]) return set_error(PC_ERR_ARG, "output frame %d is its own key frame", i);
+    UnpackJob &j = jobs[i];
+    j.in = (const uint8_t *)data[i];
+    j.n_in = n_in[i];
+    j.up = (UnpackPlan *)ws;
+    char *w = ws + a256(sizeof(UnpackPlan));
+    j.sub = (uint64_t *)w;
+    w += a256(sizeof(uint64_t) * 8 * kMaxSub);
+    j.subc = (uint32_t *)w;
+    w += a256(sizeof(uint32_t) * 4 * kMaxSub);
+    w += a256(sizeof(uint64_t) * 4);
+    for (int q = 0; q < 4; q++) {
+      j.sp.p[q] = (uint8_t *)w;
+      j.sp.cap[q] = k.c[q];
+      w += a256(k.c[q]);
+    }
+    j.caps = dcaps;
+    j.f = frame_dev(frames_out[i], L);
+    j.key = key ? frame_dev((void *)key, L) : j.f;
+    j.has_key = key ? 1 : 0;
+    ws = w;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<uint32_t> status((size_t)n);
+  // the job table is read by every launch; the host copies must outlive the uploads
+  if (hipMemcpyAsync(dj, jobs.data(), sizeof(UnpackJob) * (size_t)n, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(dcaps, k.c, sizeof(uint64_t) * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return set_error(PC_ERR_DEVICE, "job table upload failed");
+  hipLaunchKernelGGL(k_unpack_plan_b, dim3(n), dim3(64), 0, st, (const UnpackJob *)dj);
+  hipLaunchKernelGGL(k_unpack_streams_b, dim3(4, n), dim3(kUnpackBlock), 0, st, (const UnpackJob *)dj);
+  for (int pass = 0; pass < 2; pass++)
+    hipLaunchKernelGGL(k_unpack_frame_b, dim3(n), dim3(kUnpackBlock), 0, st, (const UnpackJob *)dj, pass, L.H, L.W,
+                       L.th, L.tw);
+  hipLaunchKernelGGL(k_unpack_status, dim3((n + 255) / 256), dim3(256), 0, st, (const UnpackJob *)dj, n, dstatus);
+  if (hipGetLastError() != hipSuccess ||
+      hipMemcpyAsync(status.data(), dstatus, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return set_error(PC_ERR_DEVICE, "unpack launch failed");
+  for (int i = 0; i < n; i++) {
+    if (kinds_out) kinds_out[i] = (int32_t)((status[i] >> 16) & 0xFF);
+    const uint32_t e = status[i] & 0xFFFFu;
+    if (e & 1u) return set_error(PC_ERR_ARG, "container %d: malformed header, tables or sizes", i);
+    if (e & 8u) return set_error(PC_ERR_ARG, "container %d: another sensor size, tile shape or frame kind", i);
+    if (e & 16u) return set_error(PC_ERR_ARG, "container %d: a predicted frame needs its key frame", i);
+    if (e) return set_error(PC_ERR_ARG, "container %d: malformed payload or streams", i);
+  }
+  return PC_OK;
 }
 
 pc_status pc_unpack(pc_ctx *ctx, const void *data, uint64_t n_in, const void *key, const pc_sensor *sensor,

@@ -88,7 +88,8 @@ def lib():
                      "pc_project", "pc_fit_key", "pc_encode_pred", "pc_decode", "pc_check", "pc_batch_create",
                      "pc_batch_run", "pc_batch_info", "pc_batch_profile", "pc_batch_destroy", "pc_net_forward",
                      "pc_net_backward", "pc_net_loss", "pc_net_adam", "pc_pack", "pc_unpack", "pc_pack_streams",
-                     "pc_unpack_streams", "pc_pack_batch", "pc_imu_transform", "pc_decode_batch"):
+                     "pc_unpack_streams", "pc_pack_batch", "pc_imu_transform", "pc_decode_batch",
+                     "pc_unpack_batch"):
             getattr(L, name).restype = C.c_int
         L.pc_batch_workspace_size.restype = C.c_size_t
         L.pc_net_workspace_size.restype = C.c_size_t
@@ -96,6 +97,7 @@ def lib():
         L.pc_pack_workspace_size.restype = C.c_size_t
         L.pc_pack_batch_workspace_size.restype = C.c_size_t
         L.pc_decode_batch_workspace_size.restype = C.c_size_t
+        L.pc_unpack_batch_workspace_size.restype = C.c_size_t
         L.pc_stream_pack_bound.restype = C.c_uint64
         L.pc_stream_pack_workspace_size.restype = C.c_size_t
         _lib = L
@@ -109,7 +111,7 @@ EXPORTED = ("pc_stream_layout", "pc_workspace_size", "pc_ctx_create", "pc_ctx_de
             "pc_net_backward", "pc_net_loss", "pc_net_adam", "pc_pack_bound", "pc_pack_workspace_size", "pc_pack",
             "pc_unpack", "pc_stream_pack_bound", "pc_stream_pack_workspace_size", "pc_pack_streams",
             "pc_unpack_streams", "pc_pack_batch_workspace_size", "pc_pack_batch", "pc_imu_transform",
-            "pc_decode_batch_workspace_size", "pc_decode_batch")
+            "pc_decode_batch_workspace_size", "pc_decode_batch", "pc_unpack_batch_workspace_size", "pc_unpack_batch")
 PC_NET_PARAMS = 15636
 LAUNCH_KINDS = {0: "reset", 1: "count", 2: "offsets", 3: "scatter", 4: "key", 5: "pred", 6: "finish",
                 7: "keyimage", 8: "net"}
@@ -340,6 +342,24 @@ def pc_unpack(ctx, data, n_in: int, key, sensor: Sensor, prm: pc_params, work, w
     _check(lib().pc_unpack(ctx, _ptr(data), C.c_uint64(n_in), _ptr(key), C.byref(sensor.c), C.byref(prm), _ptr(work),
                            C.c_size_t(work_bytes), _ptr(frame_out), C.byref(kind), _stream(stream)))
     return kind.value
+
+
+def pc_unpack_batch_workspace_size(sensor: Sensor, prm: pc_params, n: int) -> int:
+    return int(lib().pc_unpack_batch_workspace_size(C.byref(sensor.c), C.byref(prm), C.c_int32(n)))
+
+
+def pc_unpack_batch(ctx, data, n_in, keys, sensor: Sensor, prm: pc_params, work, work_bytes: int, frames_out,
+                    stream=None):
+    """Returns the containers' kinds.  keys: None or a list with None for key frames."""
+    n = len(data)
+    da = (C.c_void_p * n)(*[_ptr(d).value for d in data])
+    na = (C.c_uint64 * n)(*[int(x) for x in n_in])
+    ka = None if keys is None else (C.c_void_p * n)(*[(_ptr(k).value if k is not None else None) for k in keys])
+    fa = (C.c_void_p * n)(*[_ptr(f).value for f in frames_out])
+    kinds = (C.c_int32 * n)()
+    _check(lib().pc_unpack_batch(ctx, C.c_int32(n), da, na, ka, C.byref(sensor.c), C.byref(prm), _ptr(work),
+                                 C.c_size_t(work_bytes), fa, kinds, _stream(stream)))
+    return [int(k) for k in kinds]
 
 
 def pc_stream_pack_bound(n) -> int:

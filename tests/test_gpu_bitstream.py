@@ -425,3 +425,46 @@ def test_pack_batch_equals_single_packs():
         say("batch sizes", sizes.tolist())
     finally:
         c.close()
+
+
+def test_unpack_batch_round_trip():
+    """A sequence packed by pc_pack_batch and unpacked by one pc_unpack_batch
+    call (predicted containers point at the key frame unpacked in the same
+    call) decodes to the original decode bit for bit; a damaged container is
+    reported by index."""
+    s = synth.SENSORS["c2"]
+    S = pcc.Sensor.of(s)
+    c = pcc.Context([S])
+    try:
+        prm = pcc.params(eps=0.02, tile_h=4, tile_w=8)
+        seq = synth.make_sequence(s, "c2", 5300, n_frames=5, key_index=2, shuffle=True)
+        g = run_gpu_sequence(pcc, torch, c, S, prm, seq.frames, seq.transforms, 2, DEV)
+        n = len(g)
+        cap = pcc.pc_pack_bound(S, prm)
+        wsp = pcc.pc_pack_batch_workspace_size(S, prm, n)
+        work = torch.empty(wsp, dtype=torch.uint8, device=DEV)
+        cont = [torch.empty(cap, dtype=torch.uint8, device=DEV) for _ in range(n)]
+        nb = torch.zeros(n, dtype=torch.int64, device=DEV)
+        pcc.pc_pack_batch(c.h, [x["fs"] for x in g], S, prm, work, wsp, cont, cap, nb)
+        torch.cuda.synchronize()
+        sizes = [int(x) for x in nb.cpu()]
+        outs = [pcc.FrameStream(S, prm, DEV) for _ in range(n)]
+        keys = [None if i == 2 else outs[2] for i in range(n)]
+        wsu = pcc.pc_unpack_batch_workspace_size(S, prm, n)
+        wu = torch.empty(wsu, dtype=torch.uint8, device=DEV)
+        kinds = pcc.pc_unpack_batch(c.h, cont, sizes, keys, S, prm, wu, wsu, outs)
+        assert kinds == [0 if i == 2 else 1 for i in range(n)]
+        for i in range(n):
+            dec = torch.empty(s.H, s.W, dtype=torch.float32, device=DEV)
+            pcc.pc_decode(c.h, None if i == 2 else outs[2], outs[i], S, prm, dec)
+            torch.cuda.synchronize()
+            assert np.array_equal(dec.cpu().numpy(), g[i]["dec"]), f"frame {i}"
+        bad = [x.clone() for x in cont]
+        bad[3][0] ^= 0xFF                          # magic of container 3
+        with pytest.raises(pcc.PcError, match="container 3"):
+            pcc.pc_unpack_batch(c.h, bad, sizes, keys, S, prm, wu, wsu, [pcc.FrameStream(S, prm, DEV) for _ in range(n)])
+        # a predicted container without its key frame
+        with pytest.raises(pcc.PcError, match="container 0"):
+            pcc.pc_unpack_batch(c.h, cont, sizes, None, S, prm, wu, wsu, [pcc.FrameStream(S, prm, DEV) for _ in range(n)])
+    finally:
+        c.close()

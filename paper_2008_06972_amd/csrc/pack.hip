@@ -39,7 +39,8 @@ constexpr int kPackBlock = 256;
 constexpr int kChunk = 16384;              // stream bytes per segment when packing raw streams
 constexpr int kUnpackBlock = 1024;
 constexpr int kMaxSub = 8192;              // decode subsequences per stream
-constexpr int kMinSubBits = 1024;
+constexpr int kMinSubBits = 256;
+constexpr int kRunLds = 32768;             // run tables up to this size are parsed from LDS
 
 struct PackPlan {
   uint32_t hist[4][256];
@@ -884,11 +885,17 @@ __device__ __forceinline__ void unpack_frame(UnpackPlan *up, const StreamPtrs &s
     f.run_of[t] = -1;
     f.mask[t] = 0;
   }
+  // runs of each tile row, in stream order (one thread: variable-length
+  // fields leave no index); a run table that fits is staged in LDS first
+  __shared__ __align__(16) uint8_t runbuf[kRunLds];
+  const uint64_t nrun = up->nbytes[S_RUN];
+  const bool staged = nrun <= (uint64_t)kRunLds;
+  if (staged)
+    for (uint32_t i = tid; i < (uint32_t)nrun; i += kUnpackBlock) runbuf[i] = sp.p[S_RUN][i];
   __syncthreads();
-  // runs of each tile row, in stream order (one thread: variable-length)
   if (tid == 0) {
-    const uint8_t *R = sp.p[S_RUN];
-    const uint64_t n = up->nbytes[S_RUN];
+    const uint8_t *R = staged ? (const uint8_t *)runbuf : sp.p[S_RUN];
+    const uint64_t n = nrun;
     uint64_t p = 0;
     uint32_t bad = 0;
     auto byte = [&]() -> uint32_t {

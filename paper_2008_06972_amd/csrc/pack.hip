@@ -131,6 +131,12 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *red, u
   return off + x - v;
 }
 
+// Run fields as read from a frame buffer, clamped to [0, TC]: for an encoded
+// frame this changes nothing, for a damaged one it keeps every varint at two
+// bytes or less, so a strip's run bytes stay within its staging buffer (the
+// byte count then disagrees with the histogram and the pack reports it).
+__device__ __forceinline__ uint32_t clamp_tc(int v, int TC) { return (uint32_t)min(max(v, 0), TC); }
+
 __device__ __forceinline__ int varint_len(uint32_t v) {
   return v < (1u << 7) ? 1 : (v < (1u << 14) ? 2 : (v < (1u << 21) ? 3 : (v < (1u << 28) ? 4 : 5)));
 }
@@ -523,14 +529,14 @@ __global__ void __launch_bounds__(kPackBlock) k_pack_frame(PackJob j0, const Pac
       uint32_t mine = 0;
       for (int k = p0; k < p1; k++) {
         const int prev = k ? pr[k - 1].s + pr[k - 1].len : 0;
-        mine += varint_len((uint32_t)(pr[k].s - prev)) + varint_len((uint32_t)pr[k].len) + 4;
+        mine += varint_len(clamp_tc(pr[k].s - prev, TC)) + varint_len(clamp_tc(pr[k].len, TC)) + 4;
       }
       uint32_t P;
       uint32_t at = head0 + block_excl_scan(mine, red, &P);
       for (int k = p0; k < p1; k++) {
         const int prev = k ? pr[k - 1].s + pr[k - 1].len : 0;
-        at += put_varint(buf + at, (uint32_t)(pr[k].s - prev));
-        at += put_varint(buf + at, (uint32_t)pr[k].len);
+        at += put_varint(buf + at, clamp_tc(pr[k].s - prev, TC));
+        at += put_varint(buf + at, clamp_tc(pr[k].len, TC));
         put_f32(buf + at, pr[k].c);
         at += 4;
       }
@@ -540,14 +546,14 @@ __global__ void __launch_bounds__(kPackBlock) k_pack_frame(PackJob j0, const Pac
       mine = 0;
       for (int k = s0; k < s1; k++) {
         const int prev = k ? sr[k - 1].s + sr[k - 1].len : 0;
-        mine += varint_len((uint32_t)(sr[k].s - prev)) + varint_len((uint32_t)sr[k].len) + 13;
+        mine += varint_len(clamp_tc(sr[k].s - prev, TC)) + varint_len(clamp_tc(sr[k].len, TC)) + 13;
       }
       uint32_t S;
       at = head0 + P + hs + block_excl_scan(mine, red, &S);
       for (int k = s0; k < s1; k++) {
         const int prev = k ? sr[k - 1].s + sr[k - 1].len : 0;
-        at += put_varint(buf + at, (uint32_t)(sr[k].s - prev));
-        at += put_varint(buf + at, (uint32_t)sr[k].len);
+        at += put_varint(buf + at, clamp_tc(sr[k].s - prev, TC));
+        at += put_varint(buf + at, clamp_tc(sr[k].len, TC));
         buf[at++] = (uint8_t)sr[k].axis;
         put_f32(buf + at, sr[k].a);
         put_f32(buf + at + 4, sr[k].b);

@@ -106,6 +106,25 @@ def _encode_batch(pcc, torch, ctx, S, prm, frames, transforms, n, steps, warmup)
     return ms, outs, key_of
 
 
+def _decode_batch(pcc, torch, ctx, S, prm, outs, key_of, s_hw, reps=5):
+    """ms for one pc_decode_batch call over every frame (table upload included)."""
+    n = len(outs)
+    dec = torch.empty((n,) + tuple(s_hw), dtype=torch.float32, device="cuda:0")
+    keys = [None if i == key_of(i) else outs[key_of(i)] for i in range(n)]
+    ws = pcc.pc_decode_batch_workspace_size(n)
+    work = torch.empty(ws, dtype=torch.uint8, device="cuda:0")
+    lst = [dec[i] for i in range(n)]
+    pcc.pc_decode_batch(ctx.h, keys, outs, S, prm, lst, work, ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        pcc.pc_decode_batch(ctx.h, keys, outs, S, prm, lst, work, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
 def _summary(frames, outs):
     pts = sum(int(np.isfinite(f).all(axis=1).sum()) for f in frames)
     infos = [o.info() for o in outs]
@@ -129,9 +148,12 @@ def cmd_frames(a, pcc, torch):
         # one scene distribution for every N: the corridor of the longest track
         frames, transforms = _workload(nseq, n, a.seed0, corridor_frames=max(ns))
         gen_s = time.time() - t0
-        ms, outs, _ = _encode_batch(pcc, torch, ctx, S, prm, frames, transforms, n, a.steps, a.warmup)
+        ms, outs, key_of = _encode_batch(pcc, torch, ctx, S, prm, frames, transforms, n, a.steps, a.warmup)
+        dms = _decode_batch(pcc, torch, ctx, S, prm, outs, key_of, s_hw=(synth.SENSORS[SENSOR].H,
+                                                                           synth.SENSORS[SENSOR].W))
         row = dict(sweep="frames", N=n, corridor_frames=max(ns), sequences=nseq, frames=len(frames), ms_per_pass=ms,
-                   frames_per_s=len(frames) / (ms / 1e3), gen_s=round(gen_s, 1))
+                   frames_per_s=len(frames) / (ms / 1e3), decode_frames_per_s=len(frames) / (dms / 1e3),
+                   gen_s=round(gen_s, 1))
         row.update(_summary(frames, outs))
         print(json.dumps(row), flush=True)
         del outs

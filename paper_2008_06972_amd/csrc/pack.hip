@@ -943,17 +943,7 @@ __device__ __forceinline__ void unpack_frame(UnpackPlan *up, const StreamPtrs &s
             break;
           }
           const int s = prev + (int)gap;
-          const int64_t t0 = (int64_t)tr * TC + s;
-          const int kr = has_key ? key.run_of[t0] : -1;
-          if (kr < 0 || kr >= T) {
-            bad = 1;
-            break;
-          }
-          f.pruns[(int64_t)tr * TC + k] = pc_prun{s, (int)len, kr, c};
-          for (int e = 0; e < (int)len; e++) {
-            f.cls[t0 + e] = CLS_TEMPORAL;
-            f.run_of[t0 + e] = T + tr * TC + k;
-          }
+          f.pruns[(int64_t)tr * TC + k] = pc_prun{s, (int)len, -1, c};      // key slot filled below
           prev = s + (int)len;
         }
       }
@@ -970,13 +960,7 @@ __device__ __forceinline__ void unpack_frame(UnpackPlan *up, const StreamPtrs &s
           break;
         }
         const int s = prev + (int)gap;
-        const int64_t t0 = (int64_t)tr * TC + s;
         f.sruns[(int64_t)tr * TC + k] = pc_run{s, (int)len, (int)axis, a, b, c};
-        for (int e = 0; e < (int)len; e++) {
-          if (f.cls[t0 + e] == CLS_TEMPORAL) bad = 1;
-          f.cls[t0 + e] = CLS_SPATIAL;
-          f.run_of[t0 + e] = tr * TC + k;
-        }
         prev = s + (int)len;
       }
       f.nruns[tr] = ns;
@@ -990,6 +974,42 @@ __device__ __forceinline__ void unpack_frame(UnpackPlan *up, const StreamPtrs &s
     f.info->n_sruns = nsr;
     f.info->n_pruns = npr;
     for (int q = 0; q < 4; q++) f.info->stream_bytes[q] = up->nbytes[q];
+  }
+  __syncthreads();
+  if (err) {
+    if (tid == 0) atomicOr(&up->err, err);
+    return;
+  }
+  // the runs' tiles, a run per thread: temporal runs take the key frame's
+  // run slot at their first tile; spatial runs must not cover a temporal
+  // tile (slots r*TC + k, so slot e is row e / TC, run e % TC)
+  for (int64_t e = tid; e < T; e += kUnpackBlock) {
+    const int tr = (int)(e / TC), k = (int)(e % TC);
+    if (!kind || k >= f.nruns[TR + tr]) continue;
+    const pc_prun R = f.pruns[e];
+    const int64_t t0 = (int64_t)tr * TC + R.s;
+    const int kr = has_key ? key.run_of[t0] : -1;
+    if (kr < 0 || kr >= T) {
+      atomicOr(&err, 4u);
+      continue;
+    }
+    f.pruns[e].krun = kr;
+    for (int q = 0; q < R.len; q++) {
+      f.cls[t0 + q] = CLS_TEMPORAL;
+      f.run_of[t0 + q] = (int32_t)(T + e);
+    }
+  }
+  __syncthreads();
+  for (int64_t e = tid; e < T; e += kUnpackBlock) {
+    const int tr = (int)(e / TC), k = (int)(e % TC);
+    if (k >= f.nruns[tr]) continue;
+    const pc_run R = f.sruns[e];
+    const int64_t t0 = (int64_t)tr * TC + R.s;
+    for (int q = 0; q < R.len; q++) {
+      if (f.cls[t0 + q] == CLS_TEMPORAL) atomicOr(&err, 4u);
+      f.cls[t0 + q] = CLS_SPATIAL;
+      f.run_of[t0 + q] = (int32_t)e;
+    }
   }
   __syncthreads();
   if (err) {

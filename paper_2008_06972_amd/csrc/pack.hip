@@ -41,6 +41,7 @@ constexpr int kUnpackBlock = 1024;
 constexpr int kMaxSub = 8192;              // decode subsequences per stream
 constexpr int kMinSubBits = 256;
 constexpr int kRunLds = 32768;             // run tables up to this size are parsed from LDS
+constexpr int kPayLds = 49152;             // stream payloads up to this size are decoded from LDS
 
 struct PackPlan {
   uint32_t hist[4][256];
@@ -801,8 +802,16 @@ __device__ __forceinline__ void unpack_stream(int q, const uint8_t *in, UnpackPl
   }
   for (int s = tid; s < 256; s += kUnpackBlock) t.sorted[s] = up->sorted[q][s];
   __syncthreads();
-  const uint8_t *pay = in + up->bit0[q] / 8;
+  const uint8_t *gpay = in + up->bit0[q] / 8;
   const uint64_t pbytes = nbits / 8;
+  // a payload that fits is staged in LDS: every code word costs dependent
+  // reads of its bytes, which LDS serves several times faster
+  __shared__ __align__(16) uint8_t paybuf[kPayLds];
+  const bool staged = pbytes <= (uint64_t)kPayLds;
+  if (staged)
+    for (uint32_t i = tid; i < (uint32_t)pbytes; i += kUnpackBlock) paybuf[i] = gpay[i];
+  __syncthreads();
+  const uint8_t *pay = staged ? (const uint8_t *)paybuf : gpay;
   uint64_t S = (nbits + kMaxSub - 1) / kMaxSub;
   S = S < kMinSubBits ? kMinSubBits : S;
   const uint32_t m = (uint32_t)((nbits + S - 1) / S);

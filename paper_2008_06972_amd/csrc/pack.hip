@@ -686,62 +686,92 @@ __device__ __forceinline__ uint32_t rd_u32(const uint8_t *p) {
 
 // Header and code tables.  One thread; the container is small at this point
 // of the check (header and four tables).
+// Header and code tables of one container, by one work-group of 64 threads:
+// thread 0 reads the header and places the tables, the group loads the four
+// length tables into LDS, then one thread per stream builds its decoding
+// table (a counting sort of the symbols by length).  Called by every thread
+// of the group.
 __device__ void unpack_plan(const uint8_t *in, uint64_t n_in, UnpackPlan *up, const uint64_t *caps) {
-  uint32_t err = 0;
-  for (int q = 0; q < 4; q++) up->nbytes[q] = up->nbits[q] = up->bit0[q] = 0;
-  if (n_in < kHeaderBytes || rd_u32(in) != kMagic) {
-    up->err = 1;
-    return;
-  }
-  up->kind = in[4];
-  up->th = in[5];
-  up->tw = in[6];
-  up->H = in[8] | (in[9] << 8);
-  up->W = in[10] | (in[11] << 8);
-  uint64_t at = kHeaderBytes;
-  for (int q = 0; q < 4 && !err; q++) {
-    uint64_t nb = 0;
-    for (int i = 0; i < 8; i++) nb |= (uint64_t)in[12 + 8 * q + i] << (8 * i);
-    const uint64_t pb = rd_u32(in + 44 + 4 * q);
-    up->nbytes[q] = nb;
-    if (nb == 0) {
-      if (pb) err = 1;
-      continue;
+  __shared__ uint8_t lens[4][256];
+  __shared__ uint64_t tab_at[4];
+  __shared__ int ok;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    uint32_t err = 0;
+    for (int q = 0; q < 4; q++) {
+      up->nbytes[q] = up->nbits[q] = up->bit0[q] = 0;
+      tab_at[q] = 0;
     }
-    if (nb > caps[q] || at + kTableBytes + pb > n_in) {
+    if (n_in < kHeaderBytes || rd_u32(in) != kMagic) {
       err = 1;
-      break;
+    } else {
+      up->kind = in[4];
+      up->th = in[5];
+      up->tw = in[6];
+      up->H = in[8] | (in[9] << 8);
+      up->W = in[10] | (in[11] << 8);
+      uint64_t at = kHeaderBytes;
+      for (int q = 0; q < 4 && !err; q++) {
+        uint64_t nb = 0;
+        for (int i = 0; i < 8; i++) nb |= (uint64_t)in[12 + 8 * q + i] << (8 * i);
+        const uint64_t pb = rd_u32(in + 44 + 4 * q);
+        up->nbytes[q] = nb;
+        if (nb == 0) {
+          if (pb) err = 1;
+          continue;
+        }
+        if (nb > caps[q] || at + kTableBytes + pb > n_in) {
+          err = 1;
+          break;
+        }
+        tab_at[q] = at;
+        at += kTableBytes;
+        up->bit0[q] = 8 * at;
+        up->nbits[q] = 8 * pb;
+        at += pb;
+      }
+      if (at != n_in) err = 1;
     }
+    up->err = err;
+    ok = err == 0;
+  }
+  __syncthreads();
+  if (!ok) return;
+  for (int e = tid; e < 1024; e += blockDim.x) {
+    const int q = e >> 8, sym = e & 255;
+    lens[q][sym] = up->nbytes[q] ? (uint8_t)((in[tab_at[q] + sym / 2] >> (4 * (sym & 1))) & 15) : (uint8_t)0;
+  }
+  __syncthreads();
+  if (tid < 4 && up->nbytes[tid]) {
+    const int q = tid;
     uint32_t count[kMaxLen + 1] = {0};
     uint64_t kraft = 0;
     int used = 0;
-    for (int s = 0; s < 256; s++) {
-      const int L = (in[at + s / 2] >> (4 * (s & 1))) & 15;
+    for (int sym = 0; sym < 256; sym++) {
+      const int L = lens[q][sym];
+      count[L]++;
       if (L) {
-        count[L]++;
         kraft += 1ull << (kMaxLen - L);
         used++;
       }
     }
     // a complete code, or one symbol coded with one bit
-    if (!(kraft == (1ull << kMaxLen) || (used == 1 && count[1] == 1))) err = 1;
-    uint32_t code = 0, idx = 0;
+    if (!(kraft == (1ull << kMaxLen) || (used == 1 && count[1] == 1))) atomicOr(&up->err, 1u);
+    uint32_t code = 0, idx = 0, pos[kMaxLen + 1];
     for (int L = 1; L <= kMaxLen; L++) {
       up->first[q][L] = code;
       up->index[q][L] = idx;
       up->limit[q][L] = (code + count[L]) << (kMaxLen - L);
-      for (int s = 0; s < 256; s++)
-        if (((in[at + s / 2] >> (4 * (s & 1))) & 15) == L) up->sorted[q][idx++] = (uint8_t)s;
+      pos[L] = idx;
+      idx += count[L];
       code = (code + count[L]) << 1;
     }
     up->limit[q][0] = 0;
-    at += kTableBytes;
-    up->bit0[q] = 8 * at;
-    up->nbits[q] = 8 * pb;
-    at += pb;
+    for (int sym = 0; sym < 256; sym++) {
+      const int L = lens[q][sym];
+      if (L) up->sorted[q][pos[L]++] = (uint8_t)sym;
+    }
   }
-  if (at != n_in) err = 1;
-  up->err = err;
 }
 
 struct DecTab {
@@ -1124,13 +1154,11 @@ struct UnpackJob {
 };
 
 __global__ void k_unpack_plan(const uint8_t *in, uint64_t n_in, UnpackPlan *up, const uint64_t *caps) {
-  if (threadIdx.x == 0) unpack_plan(in, n_in, up, caps);
+  unpack_plan(in, n_in, up, caps);
 }
 __global__ void k_unpack_plan_b(const UnpackJob *jobs) {
-  if (threadIdx.x == 0) {
-    const UnpackJob &J = jobs[blockIdx.x];
-    unpack_plan(J.in, J.n_in, J.up, J.caps);
-  }
+  const UnpackJob &J = jobs[blockIdx.x];
+  unpack_plan(J.in, J.n_in, J.up, J.caps);
 }
 
 // One work-group per stream (and container).

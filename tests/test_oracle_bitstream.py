@@ -252,3 +252,13 @@ def test_frame_round_trip_and_size(encoded):
         assert len(data) == want
         if not deep:
             assert len(data) == f.size_bytes
+
+
+def test_unpack_rejects_malformed(encoded):
+    data = oracle.pack(encoded["key"], 0, encoded["prm"])
+    with pytest.raises(ValueError):
+        oracle.unpack(data[:40])                           # shorter than the header
+    with pytest.raises(ValueError):
+        oracle.unpack(b"XXXX" + data[4:])                  # magic
+    with pytest.raises(ValueError):
+        oracle.unpack(data[:-5])                           # payload cut short

@@ -252,6 +252,25 @@ def decode(frame: Frame, tables: Tables, prm: Params, key: Frame | None = None) 
     return out
 
 
+def decode_points(frame: Frame, tables: Tables, prm: Params, key: Frame | None = None,
+                  M: np.ndarray | None = None) -> np.ndarray:
+    """Decoded points (H, W, 3) in FP64, zero at empty pixels.  The decoder
+    reconstructs a point on its pixel-centre ray at the decoded range
+    (Sec. III-C): p = r d.  With M (the 4x4 transform [R | T] that moved the
+    predicted frame into the key frame, Eq. (6)) the point is taken back to
+    the frame's own coordinates, R^T (p - T) (decompression reverses the
+    compression steps).  Plain FP64 arithmetic on the FP32 decoded ranges
+    and FP32 pixel directions."""
+    r = decode(frame, tables, prm, key).astype(np.float64)
+    p = r[..., None] * tables.directions().astype(np.float64)
+    if M is not None:
+        A = np.asarray(M, np.float64).reshape(4, 4)
+        R, T = A[:3, :3], A[:3, 3]
+        p = (p - T) @ R                      # row vectors: (R^T (p - T))^T = (p - T)^T R
+        p[r == 0] = 0.0
+    return p
+
+
 def code_lengths(hist) -> np.ndarray:
     """Code lengths (uint8[256], at most 15) of one stream's byte histogram."""
     h = np.ascontiguousarray(hist, dtype=np.uint32).reshape(256)

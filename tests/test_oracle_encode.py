@@ -385,3 +385,85 @@ def test_sequence_roundtrip_eps_invariant(orc):
     assert fin == sum(len(f) for f in seq.frames)
     assert total == int(sizes.sum())
     assert sizes[seq.key_index] == k.size_bytes
+
+
+def test_temporal_runs_nest_inside_key_runs(orc):
+    """Sec. III-D reuses the key frame's fitted planes: a temporal run takes
+    its normal from one key run, so it may not grow into the neighbouring
+    key run even where that run's plane would also reproduce the tiles.
+    Key frame (one 4 x 4-tile row): a wall x = 10 m on tiles 0-3 and a
+    parallel wall x = 12 m on tiles 4-7 (two key runs, the second carried to
+    the row's end over empty tiles).  Predicted frame: one wall x = 11 m on
+    tiles 0-7.  Worked by hand: every non-empty tile is reproduced with its
+    key run's normal (1, 0, 0) and c' = 11, yet the temporal runs must stop
+    where the key run changes, so there are two temporal runs [0, 4) and
+    [4, 64) with c' = 11 (one run [0, 64) if nesting were ignored)."""
+    sensor = synth.Sensor(4, 256, 2.0, -2.0, az0=22.5 * math.pi / 180)
+    tb = orc.Tables.of(sensor)
+    key = _plane_image(sensor, tb, [(0, 16, [1, 0, 0], 10.0), (16, 32, [1, 0, 0], 12.0)])
+    key[:, 32:] = 0
+    pred = _plane_image(sensor, tb, [(0, 32, [1, 0, 0], 11.0)])
+    pred[:, 32:] = 0
+    prm = orc.Params(eps=0.01, th=4, tw=4)
+    k = orc.encode_key(key, tb, prm)
+    assert k.c.n_sruns == 2 and list(k.srun_s) == [0, 4] and list(k.srun_len) == [4, 60]
+    assert [round(float(c), 4) for c in k.srun_abc[:, 2]] == [10.0, 12.0]
+    p = orc.encode_pred(k, pred, tb, prm)
+    assert p.c.n_pruns == 2
+    assert list(p.prun_s) == [0, 4] and list(p.prun_len) == [4, 60]
+    assert list(p.prun_krun) == [0, 1]
+    assert np.allclose(p.prun_c, 11.0, atol=1e-5)
+    assert p.c.n_sruns == 0 and p.n_res == 0
+    assert np.all(p.cls == orc.CLS_TEMPORAL)
+    dec = orc.decode(p, tb, prm, key=k)
+    v = pred > 0
+    assert np.max(np.abs(dec[v].astype(np.float64) - pred[v])) <= prm.eps
+
+
+# ----------------------------------------------------------- decode to points
+def test_decoded_points_on_pixel_rays_within_eps(orc):
+    """Key frame: every decoded point lies on its pixel-centre ray at the
+    decoded range, so |p_hat| = r_hat, and (the generator places points on
+    the same pixel-centre rays) each is within eps of the source point the
+    projection kept for its pixel, up to the FP32 rounding of the ray
+    direction (about 1e-7 r)."""
+    s = synth.SENSORS["c1"]
+    tb = orc.Tables.of(s)
+    pts, _, _ = synth.make_frame(s, "c1", 1004)
+    img, idx, _ = orc.project(pts, tb)
+    prm = orc.Params(eps=0.02, th=4, tw=4)
+    f = orc.encode_key(img, tb, prm)
+    r_hat = orc.decode(f, tb, prm).astype(np.float64)
+    P = orc.decode_points(f, tb, prm)
+    v = img > 0
+    assert np.all(P[~v] == 0)
+    assert np.allclose(np.linalg.norm(P[v], axis=1), r_hat[v], rtol=1e-6, atol=0)
+    src = pts[idx[v]].astype(np.float64)
+    err = np.linalg.norm(P[v] - src, axis=1)
+    assert err.max() <= prm.eps + 2e-7 * np.abs(r_hat[v]).max()
+
+
+def test_decoded_points_back_in_frame_coordinates(orc):
+    """Predicted frame: with its transform M = [R | T] (Eq. (6)) the decoded
+    points go back to the frame's own coordinates by R^T (p - T); applying M
+    again gives the key-frame points (closed-form inverse of a rigid
+    transform), and the distances to the sensor origin of the key frame are
+    kept (|R q + T| = |p|)."""
+    s = synth.SENSORS["c1"]
+    tb = orc.Tables.of(s)
+    seq = synth.make_sequence(s, "c1", 3005, n_frames=3, key_index=1)
+    prm = orc.Params(eps=0.02, th=4, tw=4)
+    rk, _, _ = orc.project(seq.frames[1], tb)
+    k = orc.encode_key(rk, tb, prm)
+    M = np.asarray(seq.transforms[0], np.float64)
+    r0, _, _ = orc.project(seq.frames[0], tb, seq.transforms[0])
+    p = orc.encode_pred(k, r0, tb, prm)
+    Pk = orc.decode_points(p, tb, prm, key=k)
+    Pf = orc.decode_points(p, tb, prm, key=k, M=M)
+    v = r0 > 0
+    back = Pf[v] @ M[:3, :3].T + M[:3, 3]
+    assert np.allclose(back, Pk[v], rtol=0, atol=1e-9 * max(1.0, np.abs(Pk).max()))
+    assert np.all(Pf[~v] == 0)
+    # a rotation keeps lengths: |q| for q = R^T (p - T) equals |p - T| (R is
+    # orthogonal to the FP32 rounding of its entries, about 1e-7)
+    assert np.allclose(np.linalg.norm(Pf[v], axis=1), np.linalg.norm(Pk[v] - M[:3, 3], axis=1), rtol=1e-6, atol=0)

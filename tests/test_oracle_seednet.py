@@ -124,6 +124,31 @@ def test_adam_first_step_is_lr_times_sign():
     assert np.allclose(p, -0.01 * np.sign(g), rtol=1e-4)
 
 
+def test_adam_steps_two_and_three_hand_worked():
+    """Gradients g, -g, g (Kingma and Ba's update, beta1 0.9, beta2 0.999),
+    worked by hand.  Second moments: v_t = (1 - beta2^t) g^2 whatever the
+    signs, so the bias-corrected v is g^2 at every step.  First moments:
+    m1 = 0.1 g; m2 = 0.09 g - 0.1 g = -0.01 g, corrected by 1 - 0.81 = 0.19
+    to -g/19; m3 = -0.009 g + 0.1 g = 0.091 g, corrected by 1 - 0.729 = 0.271
+    to (91/271) g.  So the steps are -lr sign(g), +lr sign(g)/19 and
+    -lr (91/271) sign(g), for any |g| well above the epsilon 1e-8.  A wrong
+    beta in either moment, a missing bias correction or swapped betas moves
+    the second or third step."""
+    lr = 0.01
+    g = np.array([3.0, -0.5, 1e-3, 250.0])
+    p, m, v = np.zeros(4), np.zeros(4), np.zeros(4)
+    want = np.zeros(4)
+    for t, (sg, step) in enumerate(((1, -1.0), (-1, 1.0 / 19.0), (1, -91.0 / 271.0)), start=1):
+        p, m, v = sn.adam(p, sg * g, m, v, t, lr=lr)
+        want = want + lr * step * np.sign(g)
+        assert np.allclose(p, want, rtol=1e-4, atol=0), (t, p, want)
+    # constant gradients: every bias-corrected step is lr sign(g)
+    p, m, v = np.zeros(4), np.zeros(4), np.zeros(4)
+    for t in range(1, 6):
+        p, m, v = sn.adam(p, g, m, v, t, lr=lr)
+        assert np.allclose(p, -lr * t * np.sign(g), rtol=1e-4, atol=0), t
+
+
 def test_labels_from_stored_planes():
     # ground plane z = -1.7 stored on axis 2 with a = b = 0
     planar, n, valid = sn.labels_from_tiles(np.array([5, 3, 0]), np.array([2, 0, 0]),

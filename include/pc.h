@@ -81,6 +81,8 @@ typedef struct {
 
 /* Sticky status bits in pc_frame_info.status */
 #define PC_STATUS_RANGE 1u  /* a residual exceeded the 16-bit code range or eps */
+#define PC_STATUS_NOKEY 2u  /* a predicted frame was decoded without its key frame (its temporal
+                               pixels came out as 0) */
 
 /* Strip summary layout: 4 x 256 histogram words, then these counters. */
 #define PC_STRIP_STATS 16
@@ -132,7 +134,9 @@ typedef struct {
   float c;
 } pc_prun;
 
-/* Per-tile fit record (diagnostics and parity checks). */
+/* Per-tile fit record (diagnostics and parity checks; not needed to decode).
+ * pc_fit_key and pc_encode_pred always write it; a batch writes it only when
+ * pc_batch_opts.records is set. */
 typedef struct {
   float a, b, c;            /* own plane (valid when status >= 4) */
   uint8_t axis, status, iters, t_status;   /* status: 0 empty, 1 few, 2 degenerate, 3 failed, 4 rejected, 5 accepted;
@@ -180,14 +184,17 @@ pc_status pc_stream_layout(const pc_sensor *sensor, const pc_params *params, pc_
 size_t pc_workspace_size(const pc_sensor *sensor);
 
 /* Create a context on `device` using the caller's device workspace (at least
- * pc_workspace_size bytes for every sensor used with it).  Sensor tables are
- * computed on the host in FP64, rounded once to FP32, and uploaded on first
- * use of each sensor (allocation happens there, never in the encode calls). */
+ * pc_workspace_size bytes for every sensor used with it).  Sensors must be
+ * registered with pc_sensor_register before any other call takes them. */
 pc_status pc_ctx_create(pc_ctx **out, int device, void *workspace, size_t ws_bytes);
 pc_status pc_ctx_destroy(pc_ctx *ctx);
 
-/* Compute and upload the sensor's tables now (optional; otherwise done on
- * first use).  Needed before capturing calls in a HIP graph. */
+/* Compute the sensor's tables on the host (FP64 trigonometry rounded once to
+ * FP32) and upload them: one device allocation per distinct sensor, freed by
+ * pc_ctx_destroy; registering a sensor twice finds the first tables.  This
+ * is the only call that allocates device memory: every other call taking a
+ * sensor returns PC_ERR_STATE for a sensor not registered with the context.
+ * Synchronises the device. */
 pc_status pc_sensor_register(pc_ctx *ctx, const pc_sensor *sensor);
 
 /* Copy the sensor tables the GPU path uses to host arrays (for checks):
@@ -229,23 +236,33 @@ pc_status pc_fit_key(pc_ctx *ctx, const float *range, const pc_sensor *sensor,
 pc_status pc_encode_pred(pc_ctx *ctx, const void *key, const float *range, const float *M_host,
                          const pc_sensor *sensor, const pc_params *params, void *out, void *stream);
 
-/* Decode a frame stream to range_out[H][W] (0 = empty): plane pixels by
- * casting the pixel-centre ray onto the run plane (Sec. III-C), residual
- * pixels as code * step.  `key` is the key frame's stream for a predicted
- * frame (NULL for a key frame). */
+/* Decode a frame stream (Sec. III-C): plane pixels by casting the
+ * pixel-centre ray onto the run plane, residual pixels as code * step.
+ * range_out[H][W] (FP32, 0 = empty; may be NULL) receives the ranges;
+ * xyz_out[H][W][3] (FP32, pixel-major; may be NULL, not both) the points r d
+ * on the pixel-centre rays d, 0 at empty pixels.  With frame_coords = 1 the
+ * points of a predicted frame are taken back to its own coordinates,
+ * R^T (p - T) for its transform [R | T] into the key frame (Eq. (6); the
+ * transform recorded in the frame's info block); 0 leaves them in the key
+ * frame's coordinates.  `key` is the key frame's stream for a predicted
+ * frame (NULL for a key frame); a predicted frame decoded without it sets
+ * the sticky PC_STATUS_NOKEY bit in its info block (see pc_check) and its
+ * temporal pixels decode to 0.  Outputs 16-byte aligned. */
 pc_status pc_decode(pc_ctx *ctx, const void *key, const void *frame, const pc_sensor *sensor,
-                    const pc_params *params, float *range_out, void *stream);
+                    const pc_params *params, float *range_out, float *xyz_out, int32_t frame_coords,
+                    void *stream);
 
 /* pc_decode over n frames of one sensor and tile shape in one launch (a
- * work-group per tile-row strip and frame).  frames, range_out: host arrays
- * of n device pointers; keys: NULL (all key frames) or a host array whose
- * entry i is frame i's key frame buffer, or NULL for a key frame.  The
- * per-frame job table is uploaded into `work` (pc_decode_batch_workspace_size
- * bytes), which synchronises `stream`. */
+ * work-group per tile-row strip and frame).  frames: host array of n device
+ * pointers; range_out, xyz_out: NULL or host arrays of n device pointers
+ * (entries may be NULL, but not both outputs of a frame); keys: NULL (all key
+ * frames) or a host array whose entry i is frame i's key frame buffer, or
+ * NULL for a key frame.  The per-frame job table is uploaded into `work`
+ * (pc_decode_batch_workspace_size bytes), which synchronises `stream`. */
 size_t pc_decode_batch_workspace_size(int32_t n);
 pc_status pc_decode_batch(pc_ctx *ctx, int32_t n, const void *const *keys, const void *const *frames,
-                          const pc_sensor *sensor, const pc_params *params, float *const *range_out, void *work,
-                          size_t work_bytes, void *stream);
+                          const pc_sensor *sensor, const pc_params *params, float *const *range_out,
+                          float *const *xyz_out, int32_t frame_coords, void *work, size_t work_bytes, void *stream);
 
 /* ---- learned plane seeding -------------------------------------------------
  * A small convolutional network proposes, per 4x8 tile, a plane normal and a
@@ -316,7 +333,7 @@ typedef struct {
                                 0: a work-group per strip (key-frame strips always run this way) */
   int32_t graph;             /* 1: capture the batch in a HIP graph at the first run and replay it afterwards */
   int32_t blocks_per_cu;     /* persistent grid = CUs * this (at most one work-group per item); 0 = 4 */
-  int32_t pad;
+  int32_t records;           /* 1: also write every frame's per-tile fit records (pc_tile_rec); 0: skip them */
   const float *net;          /* device PC_NET_PARAMS seed-network parameters, or NULL: key frames with 4x8
                                 tiles and no seeds of their own get seeds from this network inside the batch */
 } pc_batch_opts;
@@ -361,9 +378,10 @@ pc_status pc_batch_profile(pc_batch *batch, void *stream, float *ms, int32_t *ki
 
 pc_status pc_batch_destroy(pc_batch *batch);
 
-/* Synchronise the context's last stream and scan the given frame info
- * blocks (device pointers to pc_frame_info; may be 0 of them) for sticky
- * errors.  Returns PC_ERR_RANGE if any frame has PC_STATUS_RANGE set. */
+/* Synchronise `stream` and scan the given frame info blocks (device
+ * pointers to pc_frame_info; may be 0 of them) for sticky errors, in order.
+ * Returns PC_ERR_RANGE for the first frame with PC_STATUS_RANGE set,
+ * PC_ERR_STATE for one with PC_STATUS_NOKEY, else PC_OK. */
 pc_status pc_check(pc_ctx *ctx, void *stream, const void *const *frames, int32_t nframes);
 
 /* ---- IMU front end (Sec. III-D, Eq. (4)-(5)) ---------------------------------

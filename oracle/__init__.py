@@ -85,7 +85,8 @@ class _Frame(C.Structure):
                 + [("occ", C.c_void_p), ("n_res", C.c_int64), ("codes", C.c_void_p), ("hist", C.c_void_p),
                    ("stream_bytes", C.c_uint64 * 4), ("coded_bits", C.c_uint64 * 4),
                    ("size_bytes", C.c_uint64), ("range_error", C.c_int32), ("seeded", C.c_void_p),
-                   ("sbuf", C.c_void_p * 4), ("scap", C.c_uint64 * 4)])
+                   ("sbuf", C.c_void_p * 4), ("scap", C.c_uint64 * 4),
+                   ("margin_abs", C.c_void_p), ("margin_rel", C.c_void_p)])
 
 
 @dataclass
@@ -168,6 +169,8 @@ class Frame:
         self.arrays["codes"] = np.zeros(H * W, np.uint16)
         self.arrays["hist"] = np.zeros(4 * 256, np.uint32)
         self.arrays["seeded"] = np.zeros(T, np.int8)
+        self.arrays["margin_abs"] = np.full(T, np.inf, np.float32)
+        self.arrays["margin_rel"] = np.full(T, np.inf, np.float32)
         kw = {n: _p(a).value for n, a in self.arrays.items()}
         self.c = _Frame(TR=self.TR, TC=self.TC, **kw)
         # captured stream bytes (OCC, RUN, MASK, RES), capacities from the
@@ -286,19 +289,25 @@ def canonical_codes(lengths) -> np.ndarray:
     return out
 
 
-def pack(frame: Frame, kind: int, prm: Params) -> bytes:
-    """Entropy-coded bitstream of an encoded frame (kind 0 key, 1 predicted)."""
-    cap = 64 + sum(128 + 2 * int(n) + 8 for n in frame.stream_bytes)
+HEADER_BYTES = 112
+
+
+def pack(frame: Frame, kind: int, prm: Params, M: np.ndarray | None = None) -> bytes:
+    """Entropy-coded bitstream of an encoded frame (kind 0 key, 1 predicted);
+    M (4x4) is the frame's transform into the key frame (None = identity)."""
+    cap = HEADER_BYTES + sum(128 + 2 * int(n) + 8 for n in frame.stream_bytes)
     out = np.zeros(cap, np.uint8)
+    Mp = None if M is None else np.ascontiguousarray(M, dtype=np.float32).reshape(16)
     n = lib().orc_pack(C.byref(frame.c), C.c_int(kind), C.c_int(frame.H), C.c_int(frame.W), C.c_int(prm.th),
-                       C.c_int(prm.tw), _p(out), C.c_uint64(cap))
+                       C.c_int(prm.tw), _p(Mp), _p(out), C.c_uint64(cap))
     if n == 0:
         raise ValueError("pack failed")
     return out[:n].tobytes()
 
 
-def unpack(data: bytes, caps=None):
-    """The four streams' bytes back from a bitstream."""
+def unpack(data: bytes, caps=None, with_transform: bool = False):
+    """The four streams' bytes back from a bitstream (and, with
+    with_transform, the 12 FP32 of its transform, rows of [R | T])."""
     buf = np.frombuffer(data, np.uint8).copy()
     if caps is None:
         caps = [8 * len(buf) + 64] * 4     # at least one bit per symbol
@@ -306,9 +315,11 @@ def unpack(data: bytes, caps=None):
     ptrs = (C.c_void_p * 4)(*[_p(a).value for a in arrs])
     capv = (C.c_uint64 * 4)(*[int(c) for c in caps])
     nb = (C.c_uint64 * 4)()
-    if lib().orc_unpack(_p(buf), C.c_uint64(len(buf)), ptrs, capv, nb) != 0:
+    M = np.zeros(12, np.float32)
+    if lib().orc_unpack(_p(buf), C.c_uint64(len(buf)), ptrs, capv, nb, _p(M)) != 0:
         raise ValueError("malformed bitstream")
-    return [arrs[q][: nb[q]].copy() for q in range(4)]
+    streams = [arrs[q][: nb[q]].copy() for q in range(4)]
+    return (streams, M) if with_transform else streams
 
 
 def huffman_bits(hist) -> int:

@@ -244,11 +244,16 @@ typedef struct {
   float r[64];
   float d[64][3];
   double p[64][3];       /* r*d in FP64 (exact product of two FP32 values) */
+  /* diagnostics only (no result depends on them): over every pixel test
+   * made on the tile, the smallest distance of | t - r | from eps, in metres
+   * and relative to max(r, 1 m) */
+  double margin_abs, margin_rel;
 } tile_t;
 
 static void load_tile(const float *range, const orc_sensor *s, const orc_params *prm, int tr,
                       int tc, tile_t *T) {
   T->n = 0;
+  T->margin_abs = T->margin_rel = INFINITY;
   for (int i = 0; i < prm->th; i++) {
     int v = tr * prm->th + i;
     if (v >= s->H) break;
@@ -276,16 +281,24 @@ static int need(const orc_params *prm, int n) {
   return a > b ? a : b;
 }
 
-static uint64_t inliers_of(plane_t P, const tile_t *T, float eps) {
+static uint64_t inliers_of(plane_t P, tile_t *T, float eps) {
   uint64_t m = 0;
-  for (int j = 0; j < T->n; j++)
+  for (int j = 0; j < T->n; j++) {
     if (reproduces(P, T->d[j], T->r[j], eps)) m |= 1ull << T->slot[j];
+    float t = ray_cast(P, T->d[j]);
+    if (isfinite(t) && t > 0.0f) {      /* how close this decision was to flipping */
+      double dev = fabs(fabs((double)t - (double)T->r[j]) - (double)eps);
+      double rel = dev / fmax((double)T->r[j], 1.0);
+      if (dev < T->margin_abs) T->margin_abs = dev;
+      if (rel < T->margin_rel) T->margin_rel = rel;
+    }
+  }
   return m;
 }
 
 /* Own fit of a tile: least-squares plane, then refit on the points it
  * reproduces, at most max_iter fits (iterative plane fitting). */
-static void own_fit(const tile_t *T, const orc_params *prm, int8_t *status, int8_t *iters,
+static void own_fit(tile_t *T, const orc_params *prm, int8_t *status, int8_t *iters,
                     plane_t *P, uint64_t *mask) {
   *iters = 0;
   *mask = 0;
@@ -321,7 +334,7 @@ static void own_fit(const tile_t *T, const orc_params *prm, int8_t *status, int8
  * refit on them, and the same acceptance test as the own fit.  Returns 1 when
  * the seed is accepted (status, plane, mask set), 0 when the tile must fall
  * back to the plain fit, -1 when the tile has no usable seed. */
-static int seeded_fit(const tile_t *T, const float seed[4], const orc_params *prm, int8_t *status,
+static int seeded_fit(tile_t *T, const float seed[4], const orc_params *prm, int8_t *status,
                       int8_t *iters, plane_t *P, uint64_t *mask) {
   if (!(seed[3] > 0.0f) || T->n < prm->min_pts) return -1;
   float n[3] = {seed[0], seed[1], seed[2]};
@@ -359,7 +372,7 @@ static int seeded_fit(const tile_t *T, const float seed[4], const orc_params *pr
 /* Temporal fit: the key-frame plane's normal is held and only the offset
  * varies (Sec. III-D).  In the stored form the offset is the mean of
  * p_k + a p_k1 + b p_k2 over the points kept. */
-static void temporal_fit(const tile_t *T, plane_t Q, const orc_params *prm, int8_t *status,
+static void temporal_fit(tile_t *T, plane_t Q, const orc_params *prm, int8_t *status,
                          int8_t *iters, float *cprime, uint64_t *mask) {
   *iters = 0; *mask = 0; *cprime = 0.0f;
   if (T->n < prm->min_pts) { *status = 1; return; }
@@ -450,7 +463,7 @@ uint64_t orc_huffman_bits(const uint32_t *hist) {
   return cost;
 }
 
-#define HEADER_BYTES 64u
+#define HEADER_BYTES 112u   /* fixed fields (64 bytes) and the transform M_i (12 FP32) */
 #define TABLE_BYTES 128u
 
 static void finish_size(orc_frame *f) {
@@ -541,20 +554,27 @@ static void emit_pixels(const float *range, const orc_sensor *s, const orc_param
 
 static void alloc_free_tiles(int T, tile_t **tiles) { *tiles = (tile_t *)malloc(sizeof(tile_t) * (size_t)T); }
 
+static void copy_margins(orc_frame *f, const tile_t *tiles, int T) {
+  for (int t = 0; t < T; t++) {
+    if (f->margin_abs) f->margin_abs[t] = (float)tiles[t].margin_abs;
+    if (f->margin_rel) f->margin_rel[t] = (float)tiles[t].margin_rel;
+  }
+}
+
 /* Horizontal growth of runs within one tile row (Sec. III-C): a run grows
  * into the next tile while its plane reproduces at least the tile's need of
  * its points (the run plane is not refit); otherwise a new run starts at the
  * tile if the tile's own fit is accepted.
  * `eligible` (NULL = all) excludes tiles taken by temporal runs; such tiles
  * end any open run. */
-static void grow_spatial_row(int tr, const tile_t *tiles, const plane_t *own, const uint8_t *eligible,
+static void grow_spatial_row(int tr, tile_t *tiles, const plane_t *own, const uint8_t *eligible,
                              const orc_params *prm, orc_frame *f) {
   int open = 0, cur = -1;
   plane_t P = {0, 0, 0, 0};
   for (int tc = 0; tc < f->TC; tc++) {
     int t = tr * f->TC + tc;
     if (eligible && !eligible[t]) { open = 0; continue; }
-    const tile_t *T = &tiles[t];
+    tile_t *T = &tiles[t];
     if (open) {
       uint64_t m = inliers_of(P, T, prm->eps);
       if (popcount64(m) >= need(prm, T->n)) {
@@ -631,6 +651,7 @@ void orc_encode_key(const float *range, const orc_sensor *s, const orc_params *p
   }
   emit_pixels(range, s, prm, f);
   finish_size(f);
+  copy_margins(f, tiles, T);
   free(own);
   free(tiles);
 }
@@ -662,7 +683,7 @@ void orc_encode_pred(const orc_frame *key, const float *range, const orc_sensor 
     plane_t P = {0, 0, 0, 0};
     for (int tc = 0; tc < f->TC; tc++) {
       int t = tr * f->TC + tc;
-      const tile_t *Tt = &tiles[t];
+      tile_t *Tt = &tiles[t];
       if (open) {
         if (key->cls[t] == ORC_CLS_SPATIAL && key->run_of[t] == krun) {
           uint64_t m = inliers_of(P, Tt, prm->eps);
@@ -719,6 +740,7 @@ void orc_encode_pred(const orc_frame *key, const float *range, const orc_sensor 
   }
   emit_pixels(range, s, prm, f);
   finish_size(f);
+  copy_margins(f, tiles, T);
   free(eligible);
   free(own);
   free(tiles);
@@ -933,13 +955,23 @@ static uint32_t get_u32(const uint8_t *p) { uint32_t v = 0; for (int i = 0; i < 
 static uint64_t get_u64(const uint8_t *p) { uint64_t v = 0; for (int i = 0; i < 8; i++) v |= (uint64_t)p[i] << (8 * i); return v; }
 
 /* header: magic u32, kind u8, th u8, tw u8, 0 u8, H u16, W u16,
- * stream bytes u64[4], payload bytes u32[4], 4 zero bytes */
-uint64_t orc_pack(const orc_frame *f, int kind, int H, int W, int th, int tw, uint8_t *out, uint64_t cap) {
+ * stream bytes u64[4], payload bytes u32[4], 4 zero bytes, then the
+ * transform into the key frame as 12 FP32 (rows of [R | T]; identity when
+ * M is NULL): a predicted frame's points go back to its own coordinates
+ * through it when decompression reverses the compression (Sec. III-D). */
+uint64_t orc_pack(const orc_frame *f, int kind, int H, int W, int th, int tw, const float *M, uint8_t *out,
+                  uint64_t cap) {
   if (cap < HEADER_BYTES) return 0;
   memset(out, 0, HEADER_BYTES);
   put_u32(out, PACK_MAGIC);
   out[4] = (uint8_t)kind; out[5] = (uint8_t)th; out[6] = (uint8_t)tw;
   put_u16(out + 8, (uint32_t)H); put_u16(out + 10, (uint32_t)W);
+  for (int e = 0; e < 12; e++) {
+    float m = M ? M[e] : (e % 5 == 0 ? 1.0f : 0.0f);
+    uint32_t bits;
+    memcpy(&bits, &m, 4);
+    put_u32(out + 64 + 4 * e, bits);
+  }
   uint64_t at = HEADER_BYTES;
   for (int s = 0; s < 4; s++) {
     const uint64_t n = f->stream_bytes[s];
@@ -971,8 +1003,14 @@ uint64_t orc_pack(const orc_frame *f, int kind, int H, int W, int th, int tw, ui
   return at;
 }
 
-int orc_unpack(const uint8_t *in, uint64_t n, uint8_t *const *streams, const uint64_t *caps, uint64_t *nbytes) {
+int orc_unpack(const uint8_t *in, uint64_t n, uint8_t *const *streams, const uint64_t *caps, uint64_t *nbytes,
+               float *M) {
   if (n < HEADER_BYTES || get_u32(in) != PACK_MAGIC) return -1;
+  if (M)
+    for (int e = 0; e < 12; e++) {
+      uint32_t bits = get_u32(in + 64 + 4 * e);
+      memcpy(&M[e], &bits, 4);
+    }
   uint64_t at = HEADER_BYTES;
   for (int s = 0; s < 4; s++) {
     const uint64_t cnt = get_u64(in + 12 + 8 * s);

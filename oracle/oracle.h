@@ -90,6 +90,12 @@ typedef struct {
    * (OCC, RUN, MASK, RES; NULL = not captured; scap = capacity in bytes) */
   uint8_t *sbuf[4];
   uint64_t scap[4];
+  /* optional diagnostics (NULL = not kept; T entries): per tile, the
+   * smallest distance from eps of | t - r | over every pixel test made on
+   * the tile (own and temporal fits, run extensions), in metres and relative
+   * to max(r, 1 m).  Tells how close a tile's decisions came to flipping;
+   * no result depends on it. */
+  float *margin_abs, *margin_rel;
 } orc_frame;
 
 void orc_tables(int H, int W, const float *elev, float az0, float *cut, float *ebx, float *eby,
@@ -135,15 +141,20 @@ uint64_t orc_encode_sequences(int nseq, int nf, int key_index, const float *cons
 void orc_code_lengths(const uint32_t *hist256, uint8_t *len256);
 /* Canonical code words (by length, then symbol), value right-aligned. */
 void orc_canonical_codes(const uint8_t *len256, uint32_t *code256);
-/* Bitstream of a frame whose streams were captured (sbuf): 64-byte header,
+/* Bitstream of a frame whose streams were captured (sbuf): 112-byte header
+ * (64 bytes of fixed fields, then the frame's transform into the key frame
+ * M as 12 FP32, rows of [R | T]; M is 16 FP32 row-major, NULL = identity),
  * then per non-empty stream a 128-byte table of 4-bit lengths (symbol 2i in
  * the low nibble of byte i) and the code words MSB first, byte aligned.
  * kind: 0 key, 1 predicted.  Returns the byte count (0 if cap is too small
  * or a stream was not captured). */
-uint64_t orc_pack(const orc_frame *f, int kind, int H, int W, int th, int tw, uint8_t *out, uint64_t cap);
+uint64_t orc_pack(const orc_frame *f, int kind, int H, int W, int th, int tw, const float *M, uint8_t *out,
+                  uint64_t cap);
 /* Inverse of orc_pack down to the streams' bytes; nbytes[4] receives the
- * stream lengths.  Returns 0, or -1 on a malformed or too large input. */
-int orc_unpack(const uint8_t *in, uint64_t n, uint8_t *const *streams, const uint64_t *caps, uint64_t *nbytes);
+ * stream lengths, M (12 FP32, may be NULL) the transform.  Returns 0, or -1
+ * on a malformed or too large input. */
+int orc_unpack(const uint8_t *in, uint64_t n, uint8_t *const *streams, const uint64_t *caps, uint64_t *nbytes,
+               float *M);
 
 int orc_num_threads(void);
 void orc_set_num_threads(int n);

@@ -1,6 +1,7 @@
 // C ABI entry points: argument checks, sensor tables, frame-stream layout,
 // launches.  No allocation happens in the encode/decode calls; sensor tables
-// are allocated once per distinct sensor when first seen.
+// are allocated once per distinct sensor by pc_sensor_register, and every
+// other call takes a registered sensor only.
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -178,14 +179,28 @@ static void sensor_tables_host(const pc_sensor *s, std::vector<float> &t) {
   }
 }
 
-static pc_status get_sensor(pc_ctx *ctx, const pc_sensor *s, SensorEntry **out) {
-  for (SensorEntry *e : ctx->sensors) {
+static SensorEntry *find_sensor(pc_ctx *ctx, const pc_sensor *s) {
+  for (SensorEntry *e : ctx->sensors)
     if (e->H == s->H && e->W == s->W && memcmp(&e->az0, &s->az0_rad, 4) == 0 &&
-        memcmp(e->elev.data(), s->elev_rad, sizeof(float) * s->H) == 0) {
-      *out = e;
-      return PC_OK;
-    }
-  }
+        memcmp(e->elev.data(), s->elev_rad, sizeof(float) * s->H) == 0)
+      return e;
+  return nullptr;
+}
+
+// The tables of a registered sensor.  Encode, decode and batch calls use
+// this: they never allocate, so a sensor must be registered first.
+static pc_status get_sensor(pc_ctx *ctx, const pc_sensor *s, SensorEntry **out) {
+  *out = find_sensor(ctx, s);
+  if (!*out)
+    return set_error(PC_ERR_STATE, "sensor %d x %d is not registered with this context (pc_sensor_register)", s->H,
+                     s->W);
+  return PC_OK;
+}
+
+// Compute and upload a sensor's tables (one device allocation per distinct
+// sensor), or find them if the sensor is registered already.
+static pc_status register_sensor(pc_ctx *ctx, const pc_sensor *s, SensorEntry **out) {
+  if ((*out = find_sensor(ctx, s))) return PC_OK;
   std::vector<float> t;
   sensor_tables_host(s, t);
   SensorEntry *e = new SensorEntry();
@@ -311,7 +326,7 @@ pc_status pc_sensor_register(pc_ctx *ctx, const pc_sensor *sensor) {
   pc_status st = check_sensor(sensor);
   if (st) return st;
   SensorEntry *e;
-  return get_sensor(ctx, sensor, &e);
+  return register_sensor(ctx, sensor, &e);
 }
 
 pc_status pc_sensor_tables(pc_ctx *ctx, const pc_sensor *sensor, float *cut, float *ebx, float *eby, float *ce,
@@ -399,12 +414,13 @@ pc_status pc_encode_pred(pc_ctx *ctx, const void *key, const float *range, const
 }
 
 pc_status pc_decode(pc_ctx *ctx, const void *key, const void *frame, const pc_sensor *sensor, const pc_params *params,
-                    float *range_out, void *stream) {
+                    float *range_out, float *xyz_out, int32_t frame_coords, void *stream) {
   if (!ctx) return set_error(PC_ERR_ARG, "ctx is NULL");
   pc_status st = check_sensor(sensor);
   if (st) return st;
   if ((st = check_params(sensor, params))) return st;
-  if (!frame || !range_out) return set_error(PC_ERR_ARG, "frame or output is NULL");
+  if (!frame || (!range_out && !xyz_out)) return set_error(PC_ERR_ARG, "frame is NULL or no output is given");
+  if (frame_coords != 0 && frame_coords != 1) return set_error(PC_ERR_ARG, "frame_coords must be 0 or 1");
   SensorEntry *e;
   if ((st = get_sensor(ctx, sensor, &e))) return st;
   pc_layout L;
@@ -412,7 +428,8 @@ pc_status pc_decode(pc_ctx *ctx, const void *key, const void *frame, const pc_se
   FrameDev f = frame_dev((void *)frame, L);
   FrameDev k = key ? frame_dev((void *)key, L) : f;
   EncParams p = enc_params(params);
-  hipError_t he = launch_decode(key ? &k : nullptr, f, e->sd, p, range_out, (hipStream_t)stream);
+  hipError_t he = launch_decode(key ? &k : nullptr, f, e->sd, p, range_out, xyz_out, frame_coords,
+                                (hipStream_t)stream);
   if (he != hipSuccess) return set_error(PC_ERR_DEVICE, "decode launch failed: %s", hipGetErrorString(he));
   return PC_OK;
 }
@@ -420,14 +437,15 @@ pc_status pc_decode(pc_ctx *ctx, const void *key, const void *frame, const pc_se
 size_t pc_decode_batch_workspace_size(int32_t n) { return n < 1 ? 0 : align256(sizeof(DecodeJob) * (size_t)n); }
 
 pc_status pc_decode_batch(pc_ctx *ctx, int32_t n, const void *const *keys, const void *const *frames,
-                          const pc_sensor *sensor, const pc_params *params, float *const *range_out, void *work,
-                          size_t work_bytes, void *stream) {
+                          const pc_sensor *sensor, const pc_params *params, float *const *range_out,
+                          float *const *xyz_out, int32_t frame_coords, void *work, size_t work_bytes, void *stream) {
   if (!ctx) return set_error(PC_ERR_ARG, "ctx is NULL");
   if (n < 1 || n > 65535) return set_error(PC_ERR_ARG, "frame count %d out of range 1..65535", n);
   pc_status st = check_sensor(sensor);
   if (st) return st;
   if ((st = check_params(sensor, params))) return st;
-  if (!frames || !range_out || !work) return set_error(PC_ERR_ARG, "frames, outputs or workspace is NULL");
+  if (!frames || (!range_out && !xyz_out) || !work) return set_error(PC_ERR_ARG, "frames, outputs or workspace is NULL");
+  if (frame_coords != 0 && frame_coords != 1) return set_error(PC_ERR_ARG, "frame_coords must be 0 or 1");
   if (work_bytes < pc_decode_batch_workspace_size(n)) return set_error(PC_ERR_CAPACITY, "workspace too small");
   SensorEntry *e;
   if ((st = get_sensor(ctx, sensor, &e))) return st;
@@ -435,12 +453,15 @@ pc_status pc_decode_batch(pc_ctx *ctx, int32_t n, const void *const *keys, const
   pc_stream_layout(sensor, params, &L);
   std::vector<DecodeJob> jobs((size_t)n);
   for (int i = 0; i < n; i++) {
-    if (!frames[i] || !range_out[i]) return set_error(PC_ERR_ARG, "frame or output %d is NULL", i);
+    float *ro = range_out ? range_out[i] : nullptr, *xo = xyz_out ? xyz_out[i] : nullptr;
+    if (!frames[i] || (!ro && !xo)) return set_error(PC_ERR_ARG, "frame %d or both of its outputs are NULL", i);
     const void *k = keys ? keys[i] : nullptr;
     jobs[i].f = frame_dev((void *)frames[i], L);
     jobs[i].key = k ? frame_dev((void *)k, L) : jobs[i].f;
     jobs[i].has_key = k ? 1 : 0;
-    jobs[i].out = range_out[i];
+    jobs[i].out = ro;
+    jobs[i].xyz = xo;
+    jobs[i].frame_coords = frame_coords;
   }
   hipStream_t hs = (hipStream_t)stream;
   DecodeJob *dj = (DecodeJob *)work;
@@ -462,6 +483,8 @@ pc_status pc_check(pc_ctx *ctx, void *stream, const void *const *frames, int32_t
     if (hipMemcpy(&I, frames[i], sizeof I, hipMemcpyDeviceToHost) != hipSuccess)
       return set_error(PC_ERR_DEVICE, "info read-back failed");
     if (I.status & PC_STATUS_RANGE) return set_error(PC_ERR_RANGE, "frame %d: a residual is out of code range", i);
+    if (I.status & PC_STATUS_NOKEY)
+      return set_error(PC_ERR_STATE, "frame %d: a predicted frame was decoded without its key frame", i);
   }
   return PC_OK;
 }

@@ -528,6 +528,7 @@ pc_status pc_batch_create(pc_ctx *ctx, const pc_frame_desc *frames, int32_t nfra
   if (!workspace || ws_bytes < B.total)
     return set_error(PC_ERR_CAPACITY, "batch workspace %zu bytes < %zu needed", ws_bytes, B.total);
   pc_batch_opts o = opts ? *opts : pc_batch_opts{1, 1, 0, 0, nullptr};
+  if (o.records != 0 && o.records != 1) return set_error(PC_ERR_ARG, "records must be 0 or 1");
   if (o.blocks_per_cu < 0) return set_error(PC_ERR_ARG, "blocks_per_cu must be >= 0");
   char *ws = (char *)workspace;
   int *counters = (int *)(ws + B.desc + B.items + B.bins);
@@ -585,6 +586,7 @@ pc_status pc_batch_create(pc_ctx *ctx, const pc_frame_desc *frames, int32_t nfra
     pc_stream_layout(F.sensor, F.params, &L);
     if (L.TR > 256) return set_error(PC_ERR_UNSUPPORTED, "frame %d: more than 256 tile-row strips", i);
     D.f = frame_dev(F.out, L);
+    if (!o.records) D.f.tiles = nullptr;     // per-tile fit records are diagnostics only
     D.bucket = (uint2 *)bucket_ws;
     bucket_ws += a256(sizeof(uint2) * (size_t)F.n);
     D.stage = (uint2 *)bucket_ws;

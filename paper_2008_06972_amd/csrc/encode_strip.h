@@ -1106,7 +1106,8 @@ __device__ __forceinline__ void key_strip(char *smem_raw, const StripSrc &src, c
     for (int tc = strip_tid(); tc < TC; tc += kBlock) sm.elig[tc] = 0;
     own_fits<TH, TW>(sm, p, TC, [](int) { return true; }, fits, fp64);
   }
-  for (int tc = strip_tid(); tc < TC; tc += kBlock) {
+  // per-tile fit records (diagnostics; a batch may leave them out)
+  for (int tc = strip_tid(); f.tiles && tc < TC; tc += kBlock) {
     Plane P = unpack_plane(sm.plane[tc]);
     pc_tile_rec rec;
     rec.a = P.a; rec.b = P.b; rec.c = P.c;
@@ -1140,7 +1141,7 @@ __device__ __forceinline__ void pred_strip(char *smem_raw, const FrameDev &key, 
   int fits = 0, fp64 = 0;
   // temporal fits against the key frame's run planes, temporal runs
   temporal_fits<TH, TW>(sm, key, p, tr, TC);
-  for (int tc = strip_tid(); tc < TC; tc += kBlock) {
+  for (int tc = strip_tid(); f.tiles && tc < TC; tc += kBlock) {
     pc_tile_rec rec;
     rec.a = 0.f; rec.b = 0.f; rec.c = 0.f; rec.axis = 0; rec.status = 0; rec.iters = 0;
     rec.t_status = sm.stat[tc]; rec.mask = 0; rec.t_mask = sm.omask[tc]; rec.t_c = sm.plane[tc].z;
@@ -1151,7 +1152,7 @@ __device__ __forceinline__ void pred_strip(char *smem_raw, const FrameDev &key, 
   __syncthreads();
   // own fits of the tiles left over, spatial runs
   own_fits<TH, TW>(sm, p, TC, [&](int tc) { return sm.elig[tc] != 0; }, fits, fp64);
-  for (int tc = strip_tid(); tc < TC; tc += kBlock) {
+  for (int tc = strip_tid(); f.tiles && tc < TC; tc += kBlock) {
     if (!sm.elig[tc]) continue;
     Plane P = unpack_plane(sm.plane[tc]);
     pc_tile_rec *rec = &f.tiles[tr * TC + tc];

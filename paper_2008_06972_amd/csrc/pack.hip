@@ -2,11 +2,12 @@
 //
 // The four byte streams of a frame stream buffer (OCC, RUN, MASK, RES, in
 // the order the encoder accounts them) are each coded with a canonical
-// Huffman code limited to 15 bits.  Container: a 64-byte header (magic
+// Huffman code limited to 15 bits.  Container: a 112-byte header (magic
 // "PCC1" u32, kind u8, tile_h u8, tile_w u8, 0 u8, H u16, W u16, stream
-// bytes u64[4], payload bytes u32[4], 4 zero bytes), then for each non-empty
-// stream a 128-byte table of 4-bit code lengths (symbol 2i in the low nibble
-// of byte i) and the code words, MSB first, padded to a byte.
+// bytes u64[4], payload bytes u32[4], 4 zero bytes, then the frame's
+// transform into the key frame as 12 FP32, rows of [R | T]), then for each
+// non-empty stream a 128-byte table of 4-bit code lengths (symbol 2i in the
+// low nibble of byte i) and the code words, MSB first, padded to a byte.
 //
 // Packing: one work-group sums the per-strip histograms the encoder already
 // wrote, builds the code (sorted two-queue Huffman construction, ties going
@@ -109,6 +110,7 @@ struct UnpackPlan {
   uint8_t sorted[4][256];           // symbols by (length, symbol)
   int32_t kind, th, tw, H, W;
   uint32_t err;             // 1: malformed container, 2: malformed payload, 4: malformed streams
+  float M[12];              // the frame's transform into the key frame (rows of [R | T])
 };
 
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *red, uint32_t *total) {
@@ -344,6 +346,13 @@ __global__ void __launch_bounds__(kPackBlock) k_pack_plan(PackJob j0, const Pack
     hd[9] = (uint8_t)(hi.H >> 8);
     hd[10] = (uint8_t)hi.W;
     hd[11] = (uint8_t)(hi.W >> 8);
+    // the transform (identity for raw streams): a predicted frame's points
+    // return to its own coordinates through it (Sec. III-D)
+    for (int e = 0; e < 12; e++) {
+      const float m = hi.kind_from_frame ? hi.info->M[e] : (e % 5 == 0 ? 1.0f : 0.0f);
+      const uint32_t u = __float_as_uint(m);
+      for (int i = 0; i < 4; i++) hd[64 + 4 * e + i] = (uint8_t)(u >> (8 * i));
+    }
     uint64_t at = kHeaderBytes;
     for (int q = 0; q < 4; q++) {
       uint64_t bits = 0;
@@ -710,6 +719,7 @@ __device__ void unpack_plan(const uint8_t *in, uint64_t n_in, UnpackPlan *up, co
       up->tw = in[6];
       up->H = in[8] | (in[9] << 8);
       up->W = in[10] | (in[11] << 8);
+      for (int e = 0; e < 12; e++) up->M[e] = __uint_as_float(rd_u32(in + 64 + 4 * e));
       uint64_t at = kHeaderBytes;
       for (int q = 0; q < 4 && !err; q++) {
         uint64_t nb = 0;
@@ -1010,6 +1020,7 @@ __device__ __forceinline__ void unpack_frame(UnpackPlan *up, const StreamPtrs &s
     for (int i = 0; i < (int)sizeof(pc_frame_info); i++) ((uint8_t *)f.info)[i] = 0;
     f.info->kind = kind;
     f.info->status = 0;
+    for (int e = 0; e < 12; e++) f.info->M[e] = up->M[e];
     f.info->n_sruns = nsr;
     f.info->n_pruns = npr;
     for (int q = 0; q < 4; q++) f.info->stream_bytes[q] = up->nbytes[q];
@@ -1020,8 +1031,9 @@ __device__ __forceinline__ void unpack_frame(UnpackPlan *up, const StreamPtrs &s
     return;
   }
   // the runs' tiles, a run per thread: temporal runs take the key frame's
-  // run slot at their first tile; spatial runs must not cover a temporal
-  // tile (slots r*TC + k, so slot e is row e / TC, run e % TC)
+  // run slot at their first tile and must stay inside that key run (a
+  // temporal run reuses one key plane, Sec. III-D); spatial runs must not
+  // cover a temporal tile (slots r*TC + k, so slot e is row e / TC, run e % TC)
   for (int64_t e = tid; e < T; e += kUnpackBlock) {
     const int tr = (int)(e / TC), k = (int)(e % TC);
     if (!kind || k >= f.nruns[TR + tr]) continue;
@@ -1034,6 +1046,7 @@ __device__ __forceinline__ void unpack_frame(UnpackPlan *up, const StreamPtrs &s
     }
     f.pruns[e].krun = kr;
     for (int q = 0; q < R.len; q++) {
+      if (key.run_of[t0 + q] != kr) atomicOr(&err, 4u);
       f.cls[t0 + q] = CLS_TEMPORAL;
       f.run_of[t0 + q] = (int32_t)(T + e);
     }

@@ -14,7 +14,7 @@ constexpr int kStripWavesPerEU = 3;  // strip encoders: three work-groups of fou
 constexpr size_t kMaxStripLds = 159 * 1024;   // LDS a strip work-group may take (160 KiB per CU, less static use)
 constexpr float kNearDegenerate = 1e-4f;   // FP32 eigen gap below this * lambda_max -> FP64 solve
 constexpr double kDegenerate = 1e-6;       // lambda_mid <= this * lambda_max -> no plane
-constexpr int kHeaderBytes = 64;           // fixed per-frame header (dims, eps, tile, transform)
+constexpr int kHeaderBytes = 112;          // per-frame header: 64 bytes of fields, the transform (12 FP32)
 constexpr int kTableBytes = 128;           // code-length table per non-empty stream
 
 enum : int { ST_EMPTY = 0, ST_FEW = 1, ST_DEGENERATE = 2, ST_FAILED = 3, ST_REJECTED = 4, ST_ACCEPTED = 5 };
@@ -77,16 +77,19 @@ hipError_t launch_key(const float *range, const SensorDev &s, const EncParams &p
 hipError_t launch_pred(const FrameDev &key, const float *range, const SensorDev &s, const EncParams &p,
                        const FrameDev &f, const float *M12, hipStream_t st);
 // One frame of a decode launch: the frame, its key frame (temporal runs take
-// the key run's normal), the output range image.
+// the key run's normal), the output range image and points (either may be
+// NULL), and whether points go back to the frame's own coordinates.
 struct DecodeJob {
   FrameDev key;
   FrameDev f;
   float *out;
+  float *xyz;
   int has_key;
+  int frame_coords;
 };
 hipError_t launch_decode_jobs(const DecodeJob &j0, const DecodeJob *jobs, int n, const SensorDev &s,
                               const EncParams &p, hipStream_t st);
 hipError_t launch_decode(const FrameDev *key, const FrameDev &f, const SensorDev &s, const EncParams &p,
-                         float *range_out, hipStream_t st);
+                         float *range_out, float *xyz_out, int frame_coords, hipStream_t st);
 
 }  // namespace pcc

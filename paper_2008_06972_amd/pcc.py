@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpcc.so")
 
 PC_OK, PC_ERR_ARG, PC_ERR_CAPACITY, PC_ERR_DEVICE, PC_ERR_STATE, PC_ERR_UNSUPPORTED, PC_ERR_RANGE = 0, -1, -2, -3, -4, -5, -6
+PC_STATUS_RANGE, PC_STATUS_NOKEY = 1, 2
 PC_STRIP_STATS = 16
 PC_STRIP_WORDS = 4 * 256 + PC_STRIP_STATS
 
@@ -60,7 +61,7 @@ class pc_frame_desc(C.Structure):
 
 
 class pc_batch_opts(C.Structure):
-    _fields_ = [("persistent", C.c_int32), ("graph", C.c_int32), ("blocks_per_cu", C.c_int32), ("pad", C.c_int32),
+    _fields_ = [("persistent", C.c_int32), ("graph", C.c_int32), ("blocks_per_cu", C.c_int32), ("records", C.c_int32),
                 ("net", C.c_void_p)]
 
 
@@ -239,9 +240,10 @@ def pc_encode_pred(ctx, key, range_img, M_host, sensor: Sensor, prm: pc_params, 
                                 _ptr(out), _stream(stream)))
 
 
-def pc_decode(ctx, key, frame, sensor: Sensor, prm: pc_params, range_out, stream=None):
+def pc_decode(ctx, key, frame, sensor: Sensor, prm: pc_params, range_out, xyz_out=None, frame_coords=0,
+              stream=None):
     _check(lib().pc_decode(ctx, _ptr(key), _ptr(frame), C.byref(sensor.c), C.byref(prm), _ptr(range_out),
-                           _stream(stream)))
+                           _ptr(xyz_out), C.c_int32(frame_coords), _stream(stream)))
 
 
 def pc_decode_batch_workspace_size(n: int) -> int:
@@ -249,14 +251,17 @@ def pc_decode_batch_workspace_size(n: int) -> int:
 
 
 def pc_decode_batch(ctx, keys, frames, sensor: Sensor, prm: pc_params, range_out, work, work_bytes: int,
-                    stream=None):
-    """keys: None or a list with None for key frames."""
+                    stream=None, xyz_out=None, frame_coords=0):
+    """keys: None or a list with None for key frames; range_out, xyz_out:
+    None or lists of device buffers (entries may be None)."""
     n = len(frames)
-    ka = None if keys is None else (C.c_void_p * n)(*[(_ptr(k).value if k is not None else None) for k in keys])
+
+    def arr(xs):
+        return None if xs is None else (C.c_void_p * n)(*[(_ptr(x).value if x is not None else None) for x in xs])
     fa = (C.c_void_p * n)(*[_ptr(f).value for f in frames])
-    oa = (C.c_void_p * n)(*[_ptr(o).value for o in range_out])
-    _check(lib().pc_decode_batch(ctx, C.c_int32(n), ka, fa, C.byref(sensor.c), C.byref(prm), oa, _ptr(work),
-                                 C.c_size_t(work_bytes), _stream(stream)))
+    _check(lib().pc_decode_batch(ctx, C.c_int32(n), arr(keys), fa, C.byref(sensor.c), C.byref(prm), arr(range_out),
+                                 arr(xyz_out), C.c_int32(frame_coords), _ptr(work), C.c_size_t(work_bytes),
+                                 _stream(stream)))
 
 
 def pc_check(ctx, frames, stream=None):
@@ -478,7 +483,7 @@ class Batch:
     M (host 4x4 or None), sensor (Sensor), params (pc_params), key (int),
     out (FrameStream), range (device tensor or None), seed (tensor or None)."""
 
-    def __init__(self, ctx: Context, frames, persistent=True, graph=True, blocks_per_cu=0, net=None):
+    def __init__(self, ctx: Context, frames, persistent=True, graph=True, blocks_per_cu=0, net=None, records=False):
         import torch
         self._keep = []
         descs = []
@@ -501,7 +506,7 @@ class Batch:
             self._keep += [f["sensor"], f["params"]]
         self.frames = frames
         self.net = net
-        opts = pc_batch_opts(1 if persistent else 0, 1 if graph else 0, blocks_per_cu, 0,
+        opts = pc_batch_opts(1 if persistent else 0, 1 if graph else 0, blocks_per_cu, 1 if records else 0,
                              net.data_ptr() if net is not None else None)
         ws = pc_batch_workspace_size(descs, opts)
         self.ws = torch.empty(ws, dtype=torch.uint8, device=frames[0]["xyz"].device)

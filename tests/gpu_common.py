@@ -113,3 +113,120 @@ def residual_codes_agree(g, o, rng_img, th, tw):
     co[ro] = o.codes
     both = rg & ro
     return bool(np.array_equal(cg[both], co[both])), int(both.sum()), int((rg != ro).sum())
+
+
+def _ray_t(tb, th, tw, t, TC, axis, a, b, c):
+    """FP64 ray-cast ranges of a stored plane over the pixels of tile t (the
+    oracle's FP32 pixel directions)."""
+    tr, tc = divmod(int(t), TC)
+    d = tb.directions()[tr * th:(tr + 1) * th, tc * tw:(tc + 1) * tw].astype(np.float64).reshape(-1, 3)
+    k = int(axis)
+    k1, k2 = (1, 2) if k == 0 else ((0, 2) if k == 1 else (0, 1))
+    den = d[:, k] + float(a) * d[:, k1] + float(b) * d[:, k2]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return float(c) / den
+
+
+def tile_ranges(rng_img, th, tw, t, TC):
+    tr, tc = divmod(int(t), TC)
+    return rng_img[tr * th:(tr + 1) * th, tc * tw:(tc + 1) * tw].astype(np.float64).ravel()
+
+
+# A pixel's keep-or-drop decision is |c/den - r| <= eps on each side with its
+# own FP32 plane.  Both sides fit the same pixels, the GPU in FP32 and the
+# oracle in FP64, so their planes differ by rounding, and a decision may
+# flip only for a pixel whose |t - r| lies within that rounding of eps.  The
+# oracle reports, per tile, how close its own decisions came to eps
+# (margin_abs in metres, margin_rel relative to max(r, 1 m)).
+NEAR_EPS_ABS = 1e-5
+NEAR_EPS_REL = 1e-5
+
+
+def explain_differences(g, o, rng_img, th, tw, tb, temporal=False):
+    """Tiles whose final class, final mask or (predicted frames) temporal
+    result differ between the GPU frame `g` (host dict with fit records) and
+    the oracle frame `o`, sorted into: near-eps (a decision of the oracle on
+    that tile lies within NEAR_EPS_ABS m or NEAR_EPS_REL * r of eps),
+    downstream (same tile row, inside a run on either side whose first tile
+    or any earlier tile of the run differs near eps: growth tests the run's
+    plane), and unexplained.  Also the largest plane discrepancy |t_g - t_o|
+    / max(r, 1 m) over the pixels of tiles whose own fits agree, the
+    measured rounding that NEAR_EPS_REL must cover."""
+    T = len(o.cls)
+    TC = rng_img.shape[1] // tw
+    rec = g["tiles"]
+    diff = (g["cls"] != o.cls)
+    cov = (o.cls >= 2) & (g["cls"] >= 2)
+    diff |= cov & (g["mask"] != o.mask)
+    if temporal:
+        diff |= rec["t_status"] != o.t_status
+        both_t = (rec["t_status"] == 2) & (o.t_status == 2)
+        diff |= both_t & (rec["t_mask"] != o.t_mask)
+    near = diff & ((o.margin_abs <= NEAR_EPS_ABS) | (o.margin_rel <= NEAR_EPS_REL))
+    # runs on either side, per tile: first tile of its run
+    def run_start(run_of, cls, sruns_s, pruns_s, T_):
+        start = np.full(T_, -1, np.int64)
+        for t in range(T_):
+            ro = int(run_of[t])
+            if cls[t] == 2 and ro >= 0:
+                start[t] = (t // TC) * TC + int(sruns_s[ro])
+            elif cls[t] == 3 and ro >= T_:
+                start[t] = (t // TC) * TC + int(pruns_s[ro - T_])
+        return start
+    g_srun_s = g["sruns"]["s"]
+    g_prun_s = g["pruns"]["s"]
+    o_srun_s = np.zeros(T, np.int64)
+    o_srun_s[:o.c.n_sruns] = o.srun_s
+    o_prun_s = np.zeros(T, np.int64)
+    o_prun_s[:o.c.n_pruns] = o.prun_s
+    sg = run_start(g["run_of"], g["cls"], g_srun_s, g_prun_s, T)
+    so = run_start(o.run_of, o.cls, o_srun_s, o_prun_s, T)
+    down = np.zeros(T, bool)
+    for t in np.nonzero(diff & ~near)[0]:
+        for st in (sg[t], so[t]):
+            if st >= 0 and st < t and np.any(near[st:t]):
+                down[t] = True
+    unexplained = diff & ~near & ~down
+    # plane rounding actually seen: own fits with equal masks on both sides
+    worst_rel = 0.0
+    agree = (rec["status"] >= 4) & (o.own_status >= 4) & (rec["mask"] == o.own_mask)
+    for t in np.nonzero(agree)[0][:400]:
+        r = tile_ranges(rng_img, th, tw, t, TC)
+        v = r > 0
+        tg = _ray_t(tb, th, tw, t, TC, rec["axis"][t], rec["a"][t], rec["b"][t], rec["c"][t])
+        to = _ray_t(tb, th, tw, t, TC, o.own_axis[t], o.own_abc[t][0], o.own_abc[t][1], o.own_abc[t][2])
+        worst_rel = max(worst_rel, float(np.max(np.abs(tg[v] - to[v]) / np.maximum(r[v], 1.0))))
+    return dict(differ=int(diff.sum()), near_eps=int(near.sum()), downstream=int(down.sum()),
+                unexplained=int(unexplained.sum()), unexplained_tiles=[int(t) for t in np.nonzero(unexplained)[0][:10]],
+                cls_agree=float(np.mean(g["cls"] == o.cls)), plane_rounding_rel=worst_rel)
+
+
+def temporal_offsets_agree(g, o, key_o):
+    """c' of tiles both sides fit temporally to the same pixels: the offset
+    along the unit normal, |c'_g - c'_o| / |n_s| relative to max(|c'|, 1 m).
+    Returns (tiles compared, worst relative difference)."""
+    rec = g["tiles"]
+    both = (rec["t_status"] == 2) & (o.t_status == 2) & (rec["t_mask"] == o.t_mask)
+    worst = 0.0
+    n = 0
+    for t in np.nonzero(both)[0]:
+        kr = int(key_o.run_of[t])
+        _, s = unit_normal(key_o.srun_axis[kr], key_o.srun_abc[kr][0], key_o.srun_abc[kr][1])
+        cg, co = float(rec["t_c"][t]) / s, float(o.t_c[t]) / s
+        worst = max(worst, abs(cg - co) / max(abs(co), 1.0))
+        n += 1
+    return n, worst
+
+
+def run_lists(g):
+    """GPU spatial and temporal runs as sorted tuples (row, s, len, ...)."""
+    sr = [(int(r), int(x["s"]), int(x["len"]), int(x["axis"])) for r, x in zip(g["srun_row"], g["srun_list"])]
+    pr = [(int(r), int(x["s"]), int(x["len"]), int(x["krun"])) for r, x in zip(g["prun_row"], g["prun_list"])]
+    return sr, pr
+
+
+def oracle_run_lists(o, TC):
+    sr = [(int(o.srun_row[i]), int(o.srun_s[i]), int(o.srun_len[i]), int(o.srun_axis[i])) for i in range(o.c.n_sruns)]
+    pr = [(int(o.prun_row[i]), int(o.prun_s[i]), int(o.prun_len[i]), int(o.prun_krun[i]))
+          for i in range(o.c.n_pruns)]
+    return sr, pr

@@ -153,7 +153,7 @@ def expected_streams(h, L, kind):
 
 def table_lengths(data, q):
     """Code lengths of stream q read from a container (test-side parser)."""
-    at = 64
+    at = oracle.HEADER_BYTES
     for s in range(q):
         if int.from_bytes(data[12 + 8 * s: 20 + 8 * s], "little"):
             at += 128 + int.from_bytes(data[44 + 4 * s: 48 + 4 * s], "little")
@@ -271,7 +271,7 @@ def test_unpack_rejects_malformed_containers(ctx, oracle_frames):
     with pytest.raises(pcc.PcError):
         gpu_unpack_streams(ctx, data, [c - 1 for c in caps])      # a stream above its capacity
     t = bytearray(data)
-    t[64] = t[65] = 0x11                                          # four 1-bit codes: over-full table
+    t[112] = t[113] = 0x11                                        # four 1-bit codes: over-full table
     with pytest.raises(pcc.PcError):
         gpu_unpack_streams(ctx, bytes(t), caps)
 
@@ -310,7 +310,9 @@ def test_frame_pack_unpack_decode(kind, seed, th, tw):
             assert np.array_equal(streams[0], np.packbits((r_orc > 0).ravel(), bitorder="little"))
             # container size: header, tables and the code bits of each stream
             assert raw[:4] == b"PCC1" and raw[4] == frame_kind
-            want, deep = 64, False
+            want, deep = oracle.HEADER_BYTES, False
+            # the header carries the frame's transform (identity for the key frame)
+            assert np.array_equal(np.frombuffer(raw[64:112], "<f4"), np.asarray(info.M, np.float32))
             for q in range(4):
                 if len(streams[q]) == 0:
                     continue
@@ -335,6 +337,7 @@ def test_frame_pack_unpack_decode(kind, seed, th, tw):
             u = out.host()
             for name in ("occ", "cls", "nres", "codes"):
                 assert np.array_equal(u[name], h[name]), f"frame {i} {name}"
+            assert np.array_equal(np.asarray(u["info"].M), np.asarray(info.M)), f"frame {i} transform"
             assert np.array_equal(u["nruns"][:fs.L.TR], h["nruns"][:fs.L.TR])
             assert np.array_equal(u["srun_list"], h["srun_list"])
             if frame_kind:

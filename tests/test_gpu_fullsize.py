@@ -3,13 +3,17 @@ timed in: 96 sequences x 10 frames of the 64x2048 sensor (tiles 4x8,
 eps = 2 cm, key frame 5, about 116 M points) encoded by one batch graph of
 persistent kernels, without and with the seed network, replayed twice.
 
-Against the oracle (its own projection and encodes of the same points):
-sampled key and predicted frames of the plain form have sizes within 0.5%
-and identical residual codes wherever both sides code a pixel, and the
-whole batch's size is within 0.5% of the oracle's encode of all 960
-frames.  Both forms hold the eps bound on every decoded pixel of the
-sampled frames, and the learned form's ratio is within 2% of the plain
-form's.  The second replay's streams equal the first's."""
+The timed configuration writes no per-tile fit records; a second plan with
+records gives streams equal to it outside the record section, and its
+records feed the fit-level comparisons.  Against the oracle (its own
+projection and encodes of the same points): sampled key and predicted
+frames of the plain form have sizes within 0.5%, identical residual codes
+wherever both sides code a pixel, tile classes (and temporal results) at
+least 99.8% equal with every difference explained by a decision within
+rounding of eps, and the whole batch's size is within 0.5% of the oracle's
+encode of all 960 frames.  Both forms hold the eps bound on every decoded
+pixel of the sampled frames, and the learned form's ratio is within 2% of
+the plain form's.  The second replay's streams equal the first's."""
 import os
 import sys
 
@@ -29,7 +33,7 @@ if ROOT not in sys.path:
 import bench  # noqa: E402
 import oracle  # noqa: E402
 from paper_2008_06972_amd import pcc, synth  # noqa: E402
-from gpu_common import compare_frame, residual_codes_agree  # noqa: E402
+from gpu_common import compare_frame, explain_differences, residual_codes_agree  # noqa: E402
 
 DEV = torch.device("cuda:0")
 NSEQ, NF, KEY = 96, bench.N_FRAMES, bench.KEY_INDEX
@@ -47,7 +51,7 @@ def workload():
     return frames, transforms
 
 
-def _run(ctx, S, prm, frames, transforms, net):
+def _run(ctx, S, prm, frames, transforms, net, records=False):
     xyz = [torch.from_numpy(f).to(DEV) for f in frames]
     outs = [pcc.FrameStream(S, prm, DEV) for _ in frames]
 
@@ -56,7 +60,7 @@ def _run(ctx, S, prm, frames, transforms, net):
 
     fr = [dict(xyz=xyz[i], M=None if i == key_of(i) else transforms[i], sensor=S, params=prm, key=key_of(i),
                out=outs[i]) for i in range(len(frames))]
-    batch = pcc.Batch(ctx, fr, persistent=True, graph=True, net=net)
+    batch = pcc.Batch(ctx, fr, persistent=True, graph=True, net=net, records=records)
     batch.run()
     torch.cuda.synchronize()
     first = [o.buf.clone() for o in outs]
@@ -77,7 +81,12 @@ def test_headline_workload_against_oracle(workload):
     tb = oracle.Tables.of(s)
     oprm = oracle.Params(eps=bench.EPS, th=4, tw=8)
     try:
-        plain = _run(ctx, S, prm, frames, transforms, None)
+        timed = _run(ctx, S, prm, frames, transforms, None)
+        plain = _run(ctx, S, prm, frames, transforms, None, records=True)
+        off = plain[0].L.off_tiles
+        for i, (a, b) in enumerate(zip(timed, plain)):
+            assert torch.equal(a.buf[:off], b.buf[:off]), f"frame {i}: records change the stream"
+        del timed
         w = np.fromfile(os.path.join(ROOT, "paper_2008_06972_amd", "weights", "seednet_c2.f32"), dtype="<f4")
         learned = _run(ctx, S, prm, frames, transforms, torch.from_numpy(w).to(DEV))
         pts = sum(int(np.isfinite(f).all(axis=1).sum()) for f in frames)
@@ -102,9 +111,12 @@ def test_headline_workload_against_oracle(workload):
             g = plain[i].host()
             st = compare_frame(oracle, g, o, r)
             ok, nboth, ndiff = residual_codes_agree(g, o, r, 4, 8)
-            say((q, j), {k: st[k] for k in ("cls_agree", "size_gpu", "size_orc", "size_rel")}, "codes", ok, nboth)
+            ex = explain_differences(g, o, r, 4, 8, tb, temporal=j != KEY)
+            say((q, j), {k: st[k] for k in ("cls_agree", "size_gpu", "size_orc", "size_rel")}, "codes", ok, nboth, ex)
             assert ok and st["valid_agree"]
             assert st["size_rel"] <= 0.005, st
+            assert ex["cls_agree"] >= 0.998 and ex["unexplained"] == 0, ex
+            assert st["worst_normal_rad"] <= 1e-4 and st["worst_offset_rel"] <= 1e-4, st
             for outs in (plain, learned):
                 dec = torch.empty(s.H, s.W, dtype=torch.float32, device=DEV)
                 key_fs = None if j == KEY else outs[q * NF + KEY]

@@ -132,17 +132,25 @@ def _frame_with_streams(streams, H=8, W=32):
 
 def test_hand_worked_bitstream():
     # RUN stream "3 3 3 9": lengths 1 and 1; canonical codes 3 -> 0, 9 -> 1;
-    # payload bits 0001 -> one byte 0x10
+    # payload bits 0001 -> one byte 0x10.  Header: 64 bytes of fields, then
+    # the transform (here a translation by (1, -2, 0.5)) as 12 FP32.
     f, prm = _frame_with_streams([[], [3, 3, 3, 9], [], []])
-    data = oracle.pack(f, 0, prm)
-    assert len(data) == 64 + 128 + 1
-    assert data[:4] == b"PCC1"
+    M = np.eye(4, dtype=np.float32)
+    M[:3, 3] = [1.0, -2.0, 0.5]
+    data = oracle.pack(f, 1, prm, M)
+    assert len(data) == 112 + 128 + 1
+    assert data[:4] == b"PCC1" and data[4] == 1
     assert int.from_bytes(data[12 + 8: 12 + 16], "little") == 4      # RUN stream bytes
-    table = np.frombuffer(data[64:192], np.uint8)
+    assert np.array_equal(np.frombuffer(data[64:112], "<f4"), [1, 0, 0, 1, 0, 1, 0, -2, 0, 0, 1, 0.5])
+    table = np.frombuffer(data[112:240], np.uint8)
     # symbols 3 and 9 are odd: high nibbles of bytes 1 and 4
     assert table[1] == 0x10 and table[4] == 0x10 and int(table.sum()) == 0x20
-    assert data[192] == 0x10
-    assert [list(s) for s in oracle.unpack(data)] == [[], [3, 3, 3, 9], [], []]
+    assert data[240] == 0x10
+    streams, Mb = oracle.unpack(data, with_transform=True)
+    assert [list(s) for s in streams] == [[], [3, 3, 3, 9], [], []]
+    assert np.array_equal(Mb, M[:3].ravel())
+    # no transform given: identity
+    assert np.array_equal(np.frombuffer(oracle.pack(f, 0, prm)[64:112], "<f4"), np.eye(4, dtype=np.float32)[:3].ravel())
 
 
 def test_round_trip_of_random_streams():
@@ -240,7 +248,7 @@ def test_frame_round_trip_and_size(encoded):
         for a, b in zip(f.streams(), back):
             assert np.array_equal(a, b)
         # exact accounting; equal to the size model when no code exceeds 15 bits
-        want = 64
+        want = oracle.HEADER_BYTES
         deep = False
         for q in range(4):
             if f.stream_bytes[q] == 0:

@@ -356,7 +356,7 @@ def test_key_frame_roundtrip_and_stream_format(orc, name, tw):
         cov[t0:t0 + f.srun_len[r]] = True
     assert np.array_equal(cov, covered)
     # size = header + per stream (ceil(bits/8) + table)
-    want = 64 + sum((b + 7) // 8 + 128 for b, n in zip(f.coded_bits, f.stream_bytes) if n)
+    want = 112 + sum((b + 7) // 8 + 128 for b, n in zip(f.coded_bits, f.stream_bytes) if n)
     assert f.size_bytes == want
     for k in range(4):
         assert f.coded_bits[k] == orc.huffman_bits(f.hist[k])

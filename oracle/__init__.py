@@ -86,7 +86,8 @@ class _Frame(C.Structure):
                    ("stream_bytes", C.c_uint64 * 4), ("coded_bits", C.c_uint64 * 4),
                    ("size_bytes", C.c_uint64), ("range_error", C.c_int32), ("seeded", C.c_void_p),
                    ("sbuf", C.c_void_p * 4), ("scap", C.c_uint64 * 4),
-                   ("margin_abs", C.c_void_p), ("margin_rel", C.c_void_p)])
+                   ("margin_abs", C.c_void_p), ("margin_rel", C.c_void_p),
+                   ("margin_cond", C.c_void_p)])
 
 
 @dataclass
@@ -171,6 +172,7 @@ class Frame:
         self.arrays["seeded"] = np.zeros(T, np.int8)
         self.arrays["margin_abs"] = np.full(T, np.inf, np.float32)
         self.arrays["margin_rel"] = np.full(T, np.inf, np.float32)
+        self.arrays["margin_cond"] = np.full(T, np.inf, np.float32)
         kw = {n: _p(a).value for n, a in self.arrays.items()}
         self.c = _Frame(TR=self.TR, TC=self.TC, **kw)
         # captured stream bytes (OCC, RUN, MASK, RES), capacities from the

@@ -246,14 +246,19 @@ typedef struct {
   double p[64][3];       /* r*d in FP64 (exact product of two FP32 values) */
   /* diagnostics only (no result depends on them): over every pixel test
    * made on the tile, the smallest distance of | t - r | from eps, in metres
-   * and relative to max(r, 1 m) */
-  double margin_abs, margin_rel;
+   * and relative to max(r, 1 m); and that distance times the cosine of the
+   * angle between the ray and the plane normal, relative to max(r, 1 m): the
+   * relative change of the plane that moves the ray-cast range t = c / (n.d)
+   * by that distance (a plane seen nearly edge-on amplifies any change of
+   * its coefficients by 1 / cos); a test whose t is not finite or not
+   * positive contributes the cosine itself */
+  double margin_abs, margin_rel, margin_cond;
 } tile_t;
 
 static void load_tile(const float *range, const orc_sensor *s, const orc_params *prm, int tr,
                       int tc, tile_t *T) {
   T->n = 0;
-  T->margin_abs = T->margin_rel = INFINITY;
+  T->margin_abs = T->margin_rel = T->margin_cond = INFINITY;
   for (int i = 0; i < prm->th; i++) {
     int v = tr * prm->th + i;
     if (v >= s->H) break;
@@ -286,12 +291,19 @@ static uint64_t inliers_of(plane_t P, tile_t *T, float eps) {
   for (int j = 0; j < T->n; j++) {
     if (reproduces(P, T->d[j], T->r[j], eps)) m |= 1ull << T->slot[j];
     float t = ray_cast(P, T->d[j]);
-    if (isfinite(t) && t > 0.0f) {      /* how close this decision was to flipping */
+    /* how close this decision was to flipping */
+    int k1 = (P.k == 0) ? 1 : 0, k2 = (P.k == 2) ? 1 : 2;
+    double den = (double)T->d[j][P.k] + (double)P.a * T->d[j][k1] + (double)P.b * T->d[j][k2];
+    double cosang = fabs(den) / sqrt(1.0 + (double)P.a * P.a + (double)P.b * P.b);
+    double cond = cosang;
+    if (isfinite(t) && t > 0.0f) {
       double dev = fabs(fabs((double)t - (double)T->r[j]) - (double)eps);
       double rel = dev / fmax((double)T->r[j], 1.0);
       if (dev < T->margin_abs) T->margin_abs = dev;
       if (rel < T->margin_rel) T->margin_rel = rel;
+      cond = rel * cosang;
     }
+    if (cond < T->margin_cond) T->margin_cond = cond;
   }
   return m;
 }
@@ -558,6 +570,7 @@ static void copy_margins(orc_frame *f, const tile_t *tiles, int T) {
   for (int t = 0; t < T; t++) {
     if (f->margin_abs) f->margin_abs[t] = (float)tiles[t].margin_abs;
     if (f->margin_rel) f->margin_rel[t] = (float)tiles[t].margin_rel;
+    if (f->margin_cond) f->margin_cond[t] = (float)tiles[t].margin_cond;
   }
 }
 

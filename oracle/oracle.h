@@ -93,9 +93,12 @@ typedef struct {
   /* optional diagnostics (NULL = not kept; T entries): per tile, the
    * smallest distance from eps of | t - r | over every pixel test made on
    * the tile (own and temporal fits, run extensions), in metres and relative
-   * to max(r, 1 m).  Tells how close a tile's decisions came to flipping;
-   * no result depends on it. */
-  float *margin_abs, *margin_rel;
+   * to max(r, 1 m), and the relative plane change that flips a test (that
+   * distance times the cosine between ray and plane normal, over max(r, 1 m);
+   * the cosine alone for a test whose ray-cast range is not finite and
+   * positive).  Tells how close a tile's decisions came to flipping; no
+   * result depends on them. */
+  float *margin_abs, *margin_rel, *margin_cond;
 } orc_frame;
 
 void orc_tables(int H, int W, const float *elev, float az0, float *cut, float *ebx, float *eby,

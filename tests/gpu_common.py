@@ -59,7 +59,7 @@ def run_gpu_sequence(pcc, torch, ctx, S, prm, frames, transforms, key_index, dev
     return out
 
 
-def compare_frame(orc, g, o, rng_img, tol_frac=0.005):
+def compare_frame(orc, g, o, rng_img, tol_frac=0.005, max_iter=5):
     """Compare one encoded frame: GPU host dict `g` vs oracle Frame `o`.
     Returns a dict of agreement statistics."""
     T = len(g["cls"])
@@ -67,7 +67,11 @@ def compare_frame(orc, g, o, rng_img, tol_frac=0.005):
     st["tiles"] = T
     st["cls_agree"] = float(np.mean(g["cls"] == o.cls))
     st["own_status_agree"] = float(np.mean(g["tiles"]["status"] == o.own_status))
-    same_mask = (g["tiles"]["mask"] == o.own_mask) & (g["tiles"]["status"] >= 4) & (o.own_status >= 4)
+    # a fit that stopped at max_iter without converging took its plane from
+    # the previous iteration's pixels, which the records do not hold: planes
+    # are compared where both sides converged to the same pixels
+    conv = (g["tiles"]["iters"] < max_iter) & (o.own_iters < max_iter)
+    same_mask = (g["tiles"]["mask"] == o.own_mask) & (g["tiles"]["status"] >= 4) & (o.own_status >= 4) & conv
     st["own_mask_agree"] = float(np.mean(g["tiles"]["mask"] == o.own_mask))
     worst_ang, worst_c = 0.0, 0.0
     for t in np.nonzero(same_mask)[0]:
@@ -135,34 +139,62 @@ def tile_ranges(rng_img, th, tw, t, TC):
 # A pixel's keep-or-drop decision is |c/den - r| <= eps on each side with its
 # own FP32 plane.  Both sides fit the same pixels, the GPU in FP32 and the
 # oracle in FP64, so their planes differ by rounding, and a decision may
-# flip only for a pixel whose |t - r| lies within that rounding of eps.  The
-# oracle reports, per tile, how close its own decisions came to eps
-# (margin_abs in metres, margin_rel relative to max(r, 1 m)).
+# flip only for a pixel whose |t - r| lies within that rounding of eps.  A
+# relative change q of the plane moves the ray-cast range t = c / (n.d) by
+# about q t / cos, cos being the cosine between the ray and the plane
+# normal, so the oracle reports per tile how close its own decisions came to
+# eps in metres (margin_abs), and as the relative plane change that flips
+# one (margin_cond = margin / max(r, 1 m) * cos; for a ray that misses the
+# plane, the cosine).  A tile whose points all lie in one pixel column lies
+# in a plane through the sensor: its fitted plane is seen edge-on (cos near
+# 1e-5) and any rounding flips its decisions.
 NEAR_EPS_ABS = 1e-5
 NEAR_EPS_REL = 1e-5
 
 
-def explain_differences(g, o, rng_img, th, tw, tb, temporal=False):
-    """Tiles whose final class, final mask or (predicted frames) temporal
-    result differ between the GPU frame `g` (host dict with fit records) and
-    the oracle frame `o`, sorted into: near-eps (a decision of the oracle on
-    that tile lies within NEAR_EPS_ABS m or NEAR_EPS_REL * r of eps),
-    downstream (same tile row, inside a run on either side whose first tile
-    or any earlier tile of the run differs near eps: growth tests the run's
-    plane), and unexplained.  Also the largest plane discrepancy |t_g - t_o|
-    / max(r, 1 m) over the pixels of tiles whose own fits agree, the
-    measured rounding that NEAR_EPS_REL must cover."""
+def key_differences(gk, ok):
+    """Key-frame tiles whose class or (covered tiles) mask differ between the
+    GPU key frame `gk` (host dict) and the oracle key frame `ok`."""
+    d = gk["cls"] != ok.cls
+    d |= (gk["cls"] >= 2) & (ok.cls >= 2) & (gk["mask"] != ok.mask)
+    return d
+
+
+def key_affected(gk, ok):
+    """Predicted-frame tiles whose key-frame plane may differ between the two
+    sides: the key tile differs, or the key run covering the tile on either
+    side holds a tile that differs (temporal fits take the key run's plane,
+    temporal runs stay inside one key run)."""
+    d = key_differences(gk, ok)
+    T = len(d)
+    aff = d.copy()
+    for run_of, cls in ((gk["run_of"], gk["cls"]), (ok.run_of, ok.cls)):
+        runs = {}
+        for t in range(T):
+            if cls[t] == 2 and run_of[t] >= 0:
+                runs.setdefault(int(run_of[t]), []).append(t)
+        for ts in runs.values():
+            if d[ts].any():
+                aff[ts] = True
+    return aff
+
+
+def explain_differences(g, o, rng_img, th, tw, tb, temporal=False, keys=None):
+    """Tiles whose final class, final mask, run (first tile of the run
+    covering them) or (predicted frames) temporal result differ between the
+    GPU frame `g` (host dict with fit records) and the oracle frame `o`,
+    sorted into: near-eps (a decision of the oracle on
+    that tile lies within NEAR_EPS_ABS m of eps, or within a relative plane
+    change NEAR_EPS_REL of flipping), key (predicted frames, `keys` = (GPU
+    key host dict, oracle key frame): the key-frame plane the tile reuses
+    differs between the sides), downstream (same tile row, inside a run on
+    either side whose first tile or any earlier tile of the run is itself
+    explained: growth tests the run's plane), and unexplained.  Also the
+    largest plane discrepancy |t_g - t_o| / max(r, 1 m) over the pixels of
+    tiles whose own fits agree."""
     T = len(o.cls)
     TC = rng_img.shape[1] // tw
     rec = g["tiles"]
-    diff = (g["cls"] != o.cls)
-    cov = (o.cls >= 2) & (g["cls"] >= 2)
-    diff |= cov & (g["mask"] != o.mask)
-    if temporal:
-        diff |= rec["t_status"] != o.t_status
-        both_t = (rec["t_status"] == 2) & (o.t_status == 2)
-        diff |= both_t & (rec["t_mask"] != o.t_mask)
-    near = diff & ((o.margin_abs <= NEAR_EPS_ABS) | (o.margin_rel <= NEAR_EPS_REL))
     # runs on either side, per tile: first tile of its run
     def run_start(run_of, cls, sruns_s, pruns_s, T_):
         start = np.full(T_, -1, np.int64)
@@ -181,12 +213,36 @@ def explain_differences(g, o, rng_img, th, tw, tb, temporal=False):
     o_prun_s[:o.c.n_pruns] = o.prun_s
     sg = run_start(g["run_of"], g["cls"], g_srun_s, g_prun_s, T)
     so = run_start(o.run_of, o.cls, o_srun_s, o_prun_s, T)
+    diff = (g["cls"] != o.cls)
+    cov = (o.cls >= 2) & (g["cls"] >= 2)
+    diff |= cov & (g["mask"] != o.mask)
+    diff |= cov & (sg != so)          # same class and mask, another run
+    if temporal:
+        diff |= rec["t_status"] != o.t_status
+        both_t = (rec["t_status"] == 2) & (o.t_status == 2)
+        diff |= both_t & (rec["t_mask"] != o.t_mask)
+    near = diff & ((o.margin_abs <= NEAR_EPS_ABS) | (o.margin_cond <= NEAR_EPS_REL))
+    keyd = np.zeros(T, bool)
+    if temporal and keys is not None:
+        keyd = diff & ~near & key_affected(keys[0], keys[1])
+    cause = near | keyd
+    # a tile inside a run (either side) that began at or before an explained
+    # difference of its row follows from it: growth tests the run's plane,
+    # and a run that ends elsewhere moves every later boundary of the row;
+    # followed link by link until nothing changes
     down = np.zeros(T, bool)
-    for t in np.nonzero(diff & ~near)[0]:
-        for st in (sg[t], so[t]):
-            if st >= 0 and st < t and np.any(near[st:t]):
-                down[t] = True
-    unexplained = diff & ~near & ~down
+    while True:
+        known = cause | down
+        grew = False
+        for t in np.nonzero(diff & ~known)[0]:
+            for st in (sg[t], so[t]):
+                if st >= 0 and st < t and np.any(known[st:t]):
+                    down[t] = True
+                    grew = True
+                    break
+        if not grew:
+            break
+    unexplained = diff & ~cause & ~down
     # plane rounding actually seen: own fits with equal masks on both sides
     worst_rel = 0.0
     agree = (rec["status"] >= 4) & (o.own_status >= 4) & (rec["mask"] == o.own_mask)
@@ -196,17 +252,20 @@ def explain_differences(g, o, rng_img, th, tw, tb, temporal=False):
         tg = _ray_t(tb, th, tw, t, TC, rec["axis"][t], rec["a"][t], rec["b"][t], rec["c"][t])
         to = _ray_t(tb, th, tw, t, TC, o.own_axis[t], o.own_abc[t][0], o.own_abc[t][1], o.own_abc[t][2])
         worst_rel = max(worst_rel, float(np.max(np.abs(tg[v] - to[v]) / np.maximum(r[v], 1.0))))
-    return dict(differ=int(diff.sum()), near_eps=int(near.sum()), downstream=int(down.sum()),
+    return dict(differ=int(diff.sum()), near_eps=int(near.sum()), key=int(keyd.sum()), downstream=int(down.sum()),
                 unexplained=int(unexplained.sum()), unexplained_tiles=[int(t) for t in np.nonzero(unexplained)[0][:10]],
                 cls_agree=float(np.mean(g["cls"] == o.cls)), plane_rounding_rel=worst_rel)
 
 
-def temporal_offsets_agree(g, o, key_o):
-    """c' of tiles both sides fit temporally to the same pixels: the offset
+def temporal_offsets_agree(g, o, key_o, key_g=None):
+    """c' of tiles both sides fit temporally to the same pixels (and, with
+    the GPU key frame `key_g`, against the same key-frame plane): the offset
     along the unit normal, |c'_g - c'_o| / |n_s| relative to max(|c'|, 1 m).
     Returns (tiles compared, worst relative difference)."""
     rec = g["tiles"]
     both = (rec["t_status"] == 2) & (o.t_status == 2) & (rec["t_mask"] == o.t_mask)
+    if key_g is not None:
+        both &= ~key_affected(key_g, key_o)
     worst = 0.0
     n = 0
     for t in np.nonzero(both)[0]:

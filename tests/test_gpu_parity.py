@@ -1,10 +1,13 @@
 """GPU parity: the HIP path through the C ABI against the oracle, on the same
 seeded inputs.  Projection indices, ranges and residual codes must agree bit
 for bit; planes within 1e-4 (normal angle in rad, offset relative to
-max(|c|, 1 m)) where both sides keep the same pixels; tile classes at least
-99.8 % equal per frame, and every tile whose class, mask or temporal result
-differs explained by a decision of the oracle within rounding of eps (or
-downstream of one in the same run); the compressed size within 0.5 %; every
+max(|c|, 1 m)) where both sides converge to the same pixels; every tile
+whose class, mask, run or temporal result differs explained by a decision
+of the oracle within rounding of eps (at most 0.2 % of the tiles), for a
+predicted frame by a key-frame difference in the key run it reuses, or
+downstream of either in the same run; tile classes 99.8 % equal on key
+frames and 99 % on predicted frames (a decision at a run's growth moves the
+rest of the run); the compressed size within 0.5 %; every
 decoded pixel within eps of its source (100 %); the GPU decoder bit-exact
 against the oracle's decoder on oracle-encoded frames."""
 import sys
@@ -228,24 +231,88 @@ def test_sequence_parity_and_invariant(ctx_factory):
         h = gi["host"]
         st = compare_frame(oracle, h, o, gi["range"])
         ok, _, _ = residual_codes_agree(h, o, gi["range"], 4, 4)
-        ex = explain_differences(h, o, gi["range"], 4, 4, tb, temporal=pred)
+        ex = explain_differences(h, o, gi["range"], 4, 4, tb, temporal=pred, keys=(g[ki]["host"], ok_key))
         st.update(ex)
         tot_g += st["size_gpu"]
         tot_o += st["size_orc"]
         t_agree = float(np.mean(h["tiles"]["t_status"] == o.t_status))
-        n_c, worst_c = temporal_offsets_agree(h, o, ok_key) if pred else (0, 0.0)
+        n_c, worst_c = temporal_offsets_agree(h, o, ok_key, g[ki]["host"]) if pred else (0, 0.0)
         compared += n_c
-        say(i, {k: st[k] for k in ("cls_agree", "size_rel", "differ", "near_eps", "downstream", "unexplained",
+        say(i, {k: st[k] for k in ("cls_agree", "size_rel", "differ", "near_eps", "key", "downstream", "unexplained",
                                    "plane_rounding_rel")},
             "temporal tiles", int(np.sum(h["cls"] == 3)), int(np.sum(o.cls == 3)), "t_status agree", t_agree,
             "c' compared", n_c, "worst", worst_c)
         assert ok, f"frame {i} residual codes"
         assert st["size_rel"] <= 0.005, (i, st)
-        assert st["cls_agree"] >= 0.998 and t_agree >= 0.998, (i, st, t_agree)
-        assert st["unexplained"] == 0, (i, st)
+        assert st["cls_agree"] >= (0.998 if not pred else 0.99) and t_agree >= 0.998, (i, st, t_agree)
+        assert st["unexplained"] == 0 and st["near_eps"] <= 0.002 * len(o.cls), (i, st)
         assert worst_c <= 1e-4, (i, worst_c)
     assert compared > 0
     assert abs(tot_g - tot_o) <= 0.005 * tot_o
+
+
+@pytest.mark.parametrize("kind,seed,th,tw", [("c1", 3010, 4, 4), ("c2", 2500, 4, 8)])
+def test_predicted_frames_on_the_oracle_key(ctx_factory, kind, seed, th, tw):
+    """Predicted frames encoded on the GPU against the oracle's key frame
+    (packed by the oracle, unpacked on the GPU), so both encoders reuse the
+    same key planes and runs: every difference of class, mask, run or
+    temporal result explained by a decision within rounding of eps (at most
+    0.2 % of the tiles) or downstream of one in the same run, none by a
+    key-frame difference; temporal results 99.8 % equal per frame, tile
+    classes 99 % per frame and 99.7 % over the sequence; c' within 1e-4 of max(|c'|, 1 m) wherever both sides keep
+    the same pixels; identical residual codes; sizes within 0.5 %; every
+    decoded pixel within eps."""
+    s = synth.SENSORS[kind]
+    S = pcc.Sensor.of(s)
+    ctx = ctx_factory(S)
+    prm = pcc.params(eps=0.02, tile_h=th, tile_w=tw)
+    n_frames, ki = 6, 3
+    tb, oprm, okey, frames = _oracle_sequence(s, kind, seed, n_frames, ki, th, tw)
+    seq = synth.make_sequence(s, kind, seed, n_frames=n_frames, key_index=ki, shuffle=True)
+    ws = pcc.pc_pack_workspace_size(S, prm)
+    work = torch.empty(ws, dtype=torch.uint8, device=DEV)
+    data = oracle.pack(okey, 0, oprm, None)
+    key_fs = pcc.FrameStream(S, prm, DEV)
+    assert pcc.pc_unpack(ctx.h, torch.from_numpy(np.frombuffer(data, np.uint8).copy()).to(DEV), len(data), None, S,
+                         prm, work, ws, key_fs) == 0
+    compared = 0
+    agree = []
+    for i in range(n_frames):
+        if i == ki:
+            continue
+        o, _, M, r = frames[i]
+        xyz = torch.from_numpy(np.ascontiguousarray(seq.frames[i])).to(DEV)
+        rng = torch.empty(s.H, s.W, dtype=torch.float32, device=DEV)
+        pcc.pc_project(ctx.h, xyz, len(seq.frames[i]), M, S, rng)
+        fs = pcc.FrameStream(S, prm, DEV)
+        pcc.pc_encode_pred(ctx.h, key_fs, rng, M, S, prm, fs)
+        dec = torch.empty_like(rng)
+        pcc.pc_decode(ctx.h, key_fs, fs, S, prm, dec)
+        torch.cuda.synchronize()
+        assert np.array_equal(rng.cpu().numpy(), r)
+        h = fs.host()
+        st = compare_frame(oracle, h, o, r)
+        ok, _, _ = residual_codes_agree(h, o, r, th, tw)
+        ex = explain_differences(h, o, r, th, tw, tb, temporal=True)
+        t_agree = float(np.mean(h["tiles"]["t_status"] == o.t_status))
+        n_c, worst_c = temporal_offsets_agree(h, o, okey)
+        compared += n_c
+        say(kind, i, {k: st[k] for k in ("cls_agree", "size_rel")}, ex, "t_status agree", t_agree, "c'", n_c, worst_c)
+        d = dec.cpu().numpy().astype(np.float64)
+        v = r > 0
+        assert np.all(d[~v] == 0) and np.abs(d[v] - r[v]).max() <= 0.02
+        assert ok and st["size_rel"] <= 0.005, st
+        # one decision within rounding of eps where a run grows moves the
+        # rest of that run (each such tile is counted as downstream): the
+        # root decisions are bounded, the class agreement they leave is not
+        # a per-frame invariant
+        assert ex["cls_agree"] >= 0.99 and t_agree >= 0.998, (ex, t_agree)
+        assert ex["unexplained"] == 0 and ex["key"] == 0, ex
+        assert ex["near_eps"] <= 0.002 * len(o.cls), ex
+        assert worst_c <= 1e-4
+        agree.append(ex["cls_agree"])
+    assert compared > 0
+    assert np.mean(agree) >= 0.997, agree
 
 
 def test_run_twice_bitwise(ctx_factory):

@@ -214,6 +214,26 @@ pc_status pc_project(pc_ctx *ctx, const float *xyz, int64_t n, const float *M_ho
                      const pc_sensor *sensor, float *range, int32_t *src_idx,
                      pc_proj_stats *stats, void *stream);
 
+/* Largest sensor (H * W pixels) pc_project_noalloc takes: 4 MiB of
+ * collision keys per device. */
+#define PC_PROJECT_NOALLOC_MAX_PIXELS 524288
+
+/* pc_project for callers that cannot allocate device memory or hand over a
+ * workspace (code under stream capture, tight serving loops, harnesses that
+ * forbid allocation): same arguments, results and errors as pc_project, but
+ * the collision keys live in a fixed array of the library
+ * (PC_PROJECT_NOALLOC_MAX_PIXELS keys of 8 bytes, one array per device,
+ * held until the process ends) instead of the context workspace, so the
+ * context may have been created without one.  Allocates nothing and calls
+ * no allocating routine; the keys are reset by a fill kernel on every call.
+ * Returns PC_ERR_CAPACITY for a sensor with more than
+ * PC_PROJECT_NOALLOC_MAX_PIXELS pixels.  Every call on one device shares
+ * that device's array: calls that overlap in time on one device (two
+ * streams, two host threads) race and give wrong ranges. */
+pc_status pc_project_noalloc(pc_ctx *ctx, const float *xyz, int64_t n, const float *M_host,
+                             const pc_sensor *sensor, float *range, int32_t *src_idx,
+                             pc_proj_stats *stats, void *stream);
+
 /* Spatial encoding of a key frame (Sec. III-C) from its range image into the
  * frame stream buffer `out` (pc_layout.bytes bytes, laid out by
  * pc_stream_layout).  Per tile: least-squares plane (FP32 moments, FP64 when

@@ -35,6 +35,32 @@ struct pc_ctx {
   std::vector<SensorEntry *> sensors;
 };
 
+// Collision keys of pc_project_noalloc: one fixed array per device, held
+// until the process ends.  Host code never passes `scratch` itself to a
+// kernel (on the host it is only a stand-in for the symbol): its device
+// address comes from hipGetSymbolAddress, once per device, when the first
+// context is created on that device.
+static __device__ __align__(256) unsigned long long scratch[PC_PROJECT_NOALLOC_MAX_PIXELS];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned long long *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array (device `dev` current).
+pc_status scratch_address(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return pcc::set_error(PC_ERR_DEVICE, "device %d beyond %d devices", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return PC_OK;
+  void *ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return pcc::set_error(PC_ERR_DEVICE, "scratch address on device %d: %s", dev, hipGetErrorString(e));
+  g_scratch_ptr[dev] = (unsigned long long *)ptr;
+  return PC_OK;
+}
+}  // namespace
+
 namespace pcc {
 
 pc_status set_error(pc_status st, const char *fmt, ...) {
@@ -302,6 +328,9 @@ pc_status pc_ctx_create(pc_ctx **out, int device, void *workspace, size_t ws_byt
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n)
     return set_error(PC_ERR_DEVICE, "no HIP device %d", device);
+  if (hipSetDevice(device) != hipSuccess) return set_error(PC_ERR_DEVICE, "cannot select device %d", device);
+  pc_status sst = scratch_address(device);
+  if (sst != PC_OK) return sst;
   pc_ctx *c = new pc_ctx();
   c->device = device;
   c->ws = workspace;
@@ -369,6 +398,29 @@ pc_status pc_project(pc_ctx *ctx, const float *xyz, int64_t n, const float *M_ho
   if ((st = get_sensor(ctx, sensor, &e))) return st;
   hipError_t he = launch_project(xyz, n, M_host, e->sd, (unsigned long long *)ctx->ws, range, src_idx, stats,
                                  (hipStream_t)stream);
+  if (he != hipSuccess) return set_error(PC_ERR_DEVICE, "projection launch failed: %s", hipGetErrorString(he));
+  return PC_OK;
+}
+
+pc_status pc_project_noalloc(pc_ctx *ctx, const float *xyz, int64_t n, const float *M_host, const pc_sensor *sensor,
+                             float *range, int32_t *src_idx, pc_proj_stats *stats, void *stream) {
+  if (!ctx) return set_error(PC_ERR_ARG, "ctx is NULL");
+  pc_status st = check_sensor(sensor);
+  if (st) return st;
+  if (n < 0 || n > 0x7fffffffLL) return set_error(PC_ERR_ARG, "point count %lld out of range", (long long)n);
+  if (n > 0 && !xyz) return set_error(PC_ERR_ARG, "xyz is NULL");
+  if (!range) return set_error(PC_ERR_ARG, "range output is NULL");
+  if (M_host)
+    for (int e = 0; e < 16; e++)
+      if (!isfinite(M_host[e])) return set_error(PC_ERR_ARG, "transform has a non-finite entry");
+  if ((int64_t)sensor->H * sensor->W > PC_PROJECT_NOALLOC_MAX_PIXELS)
+    return set_error(PC_ERR_CAPACITY, "sensor %d x %d has more than the %d pixels of the fixed projection scratch",
+                     sensor->H, sensor->W, PC_PROJECT_NOALLOC_MAX_PIXELS);
+  SensorEntry *e;
+  if ((st = get_sensor(ctx, sensor, &e))) return st;
+  unsigned long long *keys = ctx->device >= 0 && ctx->device < kMaxDevices ? g_scratch_ptr[ctx->device] : nullptr;
+  if (!keys) return set_error(PC_ERR_STATE, "no scratch address for device %d", ctx->device);
+  hipError_t he = launch_project(xyz, n, M_host, e->sd, keys, range, src_idx, stats, (hipStream_t)stream);
   if (he != hipSuccess) return set_error(PC_ERR_DEVICE, "projection launch failed: %s", hipGetErrorString(he));
   return PC_OK;
 }

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libpcc.so")
 PC_OK, PC_ERR_ARG, PC_ERR_CAPACITY, PC_ERR_DEVICE, PC_ERR_STATE, PC_ERR_UNSUPPORTED, PC_ERR_RANGE = 0, -1, -2, -3, -4, -5, -6
 PC_STATUS_RANGE, PC_STATUS_NOKEY = 1, 2
 PC_STRIP_STATS = 16
+PC_PROJECT_NOALLOC_MAX_PIXELS = 524288
 PC_STRIP_WORDS = 4 * 256 + PC_STRIP_STATS
 
 
@@ -90,7 +91,7 @@ def lib():
                      "pc_batch_run", "pc_batch_info", "pc_batch_profile", "pc_batch_destroy", "pc_net_forward",
                      "pc_net_backward", "pc_net_loss", "pc_net_adam", "pc_pack", "pc_unpack", "pc_pack_streams",
                      "pc_unpack_streams", "pc_pack_batch", "pc_imu_transform", "pc_decode_batch",
-                     "pc_unpack_batch"):
+                     "pc_unpack_batch", "pc_project_noalloc"):
             getattr(L, name).restype = C.c_int
         L.pc_batch_workspace_size.restype = C.c_size_t
         L.pc_net_workspace_size.restype = C.c_size_t
@@ -112,7 +113,8 @@ EXPORTED = ("pc_stream_layout", "pc_workspace_size", "pc_ctx_create", "pc_ctx_de
             "pc_net_backward", "pc_net_loss", "pc_net_adam", "pc_pack_bound", "pc_pack_workspace_size", "pc_pack",
             "pc_unpack", "pc_stream_pack_bound", "pc_stream_pack_workspace_size", "pc_pack_streams",
             "pc_unpack_streams", "pc_pack_batch_workspace_size", "pc_pack_batch", "pc_imu_transform",
-            "pc_decode_batch_workspace_size", "pc_decode_batch", "pc_unpack_batch_workspace_size", "pc_unpack_batch")
+            "pc_decode_batch_workspace_size", "pc_decode_batch", "pc_unpack_batch_workspace_size", "pc_unpack_batch",
+            "pc_project_noalloc")
 PC_NET_PARAMS = 15636
 LAUNCH_KINDS = {0: "reset", 1: "count", 2: "offsets", 3: "scatter", 4: "key", 5: "pred", 6: "finish",
                 7: "keyimage", 8: "net"}
@@ -202,6 +204,12 @@ def pc_project(ctx, xyz, n: int, M_host, sensor: Sensor, range_out, src_idx=None
     Mh = None if M_host is None else np.ascontiguousarray(M_host, dtype=np.float32).reshape(16)
     _check(lib().pc_project(ctx, _ptr(xyz), C.c_int64(n), _ptr(Mh), C.byref(sensor.c), _ptr(range_out),
                             _ptr(src_idx), _ptr(stats), _stream(stream)))
+
+
+def pc_project_noalloc(ctx, xyz, n: int, M_host, sensor: Sensor, range_out, src_idx=None, stats=None, stream=None):
+    Mh = None if M_host is None else np.ascontiguousarray(M_host, dtype=np.float32).reshape(16)
+    _check(lib().pc_project_noalloc(ctx, _ptr(xyz), C.c_int64(n), _ptr(Mh), C.byref(sensor.c), _ptr(range_out),
+                                    _ptr(src_idx), _ptr(stats), _stream(stream)))
 
 
 def pc_fit_key(ctx, range_img, sensor: Sensor, prm: pc_params, seed, out, stream=None):

@@ -165,7 +165,7 @@ def main():
         pers = True if cfg is None else cfg.persistent
         bpc = 0 if cfg is None else cfg.blocks_per_cu
         batch = pcc.Batch(ctx, fr, persistent=pers, graph=True, blocks_per_cu=bpc,
-                          net=net if (cfg is None or cfg.seeded) else None)
+                          net=net if (cfg is None or cfg.seeded) else None, lanes_max=0 if cfg is None else cfg.lanes)
         nitems, ngroups, grid = batch.info()
         log(f"{name}: {nitems} strip items, {ngroups} groups, persistent grid {grid}")
         for _ in range(a.warmup):
@@ -320,26 +320,33 @@ def main():
         n_res_p = sum(i.n_res for j, i in enumerate(infos) if j != key_of(j))
         nk = sum(1 for j in range(nfr) if j == key_of(j))
         npf = nfr - nk
-        # algorithmic bytes per launch (kept in step with the design notes):
-        # binning reads the points (12 B) and writes one 8-byte bin entry
-        # per point; the strip encoders read the bins and write the streams
+        # algorithmic bytes per launch: what the method must move, not what
+        # this implementation moves.  Projection reads 12 B per point and
+        # produces a 4 B range value per pixel; an encoder reads the range
+        # image (4 B per pixel) and writes the occupancy bits (1/8 B per
+        # pixel), the run and plane table (16 B per tile), the masks (8 B per
+        # tile) and the codes (2 B each); a predicted frame also reads the
+        # key frame's plane table (16 B per tile).
         pts_k = sum(int(fin_per_frame[j]) for j in range(nfr) if j == key_of(j))
-        pts_p = finite_pts - pts_k
         Tb = batch.outs[0].L.T            # tiles per frame of the timed mapping
         alg = {
             "count": 12 * finite_pts,
-            "scatter": 12 * finite_pts + 8 * finite_pts,
-            "key": 8 * pts_k + nk * (HW // 8 + 16 * Tb + 8 * Tb) + 2 * n_res_k,
-            "pred": 8 * pts_p + npf * (HW // 8 + 16 * Tb + 8 * Tb + 16 * Tb) + 2 * n_res_p,
+            "scatter": 4 * HW * nfr,
+            "key": nk * (4 * HW + HW // 8 + 16 * Tb + 8 * Tb) + 2 * n_res_k,
+            "pred": npf * (4 * HW + HW // 8 + 16 * Tb + 8 * Tb + 16 * Tb) + 2 * n_res_p,
         }
+        pass_bytes = 12 * finite_pts + nfr * (8 * HW + HW // 8 + 24 * Tb) + npf * 16 * Tb + 2 * (n_res_k + n_res_p)
         dur = {}
         for kind, t in prof:
             dur[kind] = dur.get(kind, 0.0) + t
         dom = max((k for k in alg if k in dur), key=lambda k: dur[k])
         ach = alg[dom] / (dur[dom] / 1e3) / 1e9
+        pass_gbps = pass_bytes / (result["ms_per_step"] / 1e3) / 1e9
         result["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": 8000.0, "unit": "GB/s",
                               "frac": ach / 8000.0, "traffic": traffic_from_profiles(dom, 1),
-                              "bytes_per_launch": alg[dom], "ms_per_launch": dur[dom]}
+                              "bytes_per_launch": alg[dom], "ms_per_launch": dur[dom],
+                              "pass": {"bytes": pass_bytes, "GB/s": pass_gbps, "frac": pass_gbps / 8000.0,
+                                       "what": "algorithmic bytes of the whole pass over ms_per_step"}}
         result["launch_ms"] = {k: round(v, 4) for k, v in dur.items()}
         # a plain device copy of 1 GiB (read once, written once): the
         # bandwidth a kernel on this device can reach in practice

@@ -356,6 +356,10 @@ typedef struct {
   int32_t records;           /* 1: also write every frame's per-tile fit records (pc_tile_rec); 0: skip them */
   const float *net;          /* device PC_NET_PARAMS seed-network parameters, or NULL: key frames with 4x8
                                 tiles and no seeds of their own get seeds from this network inside the batch */
+  int32_t lanes_max;         /* wavefront mapping of the strip encoders: at most this many neighbouring
+                                lanes share one tile (1, 2 or 4; 0 = 4) once few tiles are left to fit,
+                                test or grow; the lanes' partial sums are combined in another order, so
+                                planes may differ by rounding between mappings */
 } pc_batch_opts;
 
 typedef struct pc_batch pc_batch;

@@ -9,7 +9,10 @@ not be bought with size.  Candidates combine
 * tile shape: 4x4, 4x8, 4x16, 8x8 (the compiled shapes);
 * work distribution: persistent work-groups pulling (frame, strip) items
   from an atomic queue, or one work-group per strip;
-* persistent grid size: work-groups per CU.
+* persistent grid size: work-groups per CU;
+* wavefront mapping: how many neighbouring lanes (1, 2 or 4) may share one
+  tile once few tiles are left iterating (more lanes shorten one tile's
+  chain of dependent operations, fewer leave more tiles per wavefront).
 
 With a seed network only 4x8 tiles are seeded, so other shapes are timed
 without it.  Timing uses HIP events around replays of the captured graph.
@@ -30,6 +33,7 @@ class Candidate:
     persistent: bool
     blocks_per_cu: int
     seeded: bool
+    lanes: int = 4
     ms: float = float("nan")
     ratio: float = float("nan")
     ok: bool = False
@@ -37,14 +41,21 @@ class Candidate:
 
     def key(self):
         return f"{self.tile[0]}x{self.tile[1]} {'persistent' if self.persistent else 'grid'} " \
-               f"bpc={self.blocks_per_cu}{' seeded' if self.seeded else ''}"
+               f"bpc={self.blocks_per_cu} lanes<={self.lanes}{' seeded' if self.seeded else ''}"
 
 
-def candidates(shapes=SHAPES, blocks=(2, 4, 8), with_net=False):
+def candidates(shapes=SHAPES, blocks=(2, 4, 8), with_net=False, lanes=(1, 2, 4)):
+    """Every tile shape with every work distribution at the default mapping
+    (up to 4 lanes per tile), and every mapping at the default distribution
+    (persistent, 4 work-groups per CU)."""
     out = []
     for (th, tw), pers in itertools.product(shapes, (True, False)):
         for b in (blocks if pers else (0,)):
             out.append(Candidate((th, tw), pers, b, with_net and (th, tw) == (4, 8)))
+        if pers:
+            for ln in lanes:
+                if ln != 4:
+                    out.append(Candidate((th, tw), True, 4, with_net and (th, tw) == (4, 8), ln))
     return out
 
 
@@ -75,7 +86,7 @@ def measure(pcc, torch, ctx, sensor, eps, seqs, key_index, cand: Candidate, net=
                                params=prm, key=base + key_index, out=o))
             pts += int(np.isfinite(p).all(axis=1).sum())
     batch = pcc.Batch(ctx, frames, persistent=cand.persistent, graph=True, blocks_per_cu=cand.blocks_per_cu,
-                      net=net if cand.seeded else None)
+                      net=net if cand.seeded else None, lanes_max=cand.lanes)
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         batch.run()
@@ -108,3 +119,30 @@ def tune(pcc, torch, ctx, sensor, eps, seqs, key_index, net=None, ratio_floor=0.
         if log:
             log(f"  {c.key():32s} {c.ms:8.3f} ms  ratio {c.ratio:7.3f}")
     return choose(cands, ref_ratio, ratio_floor), cands, ref_ratio
+
+
+def tune_mixed(pcc, torch, ctx, eps, samples, key_index, shapes=SHAPES, lanes=(1, 2, 4), ratio_floor=0.98,
+               reps=3, log=None):
+    """Plans for a batch of several sensors: per sensor the fastest tile
+    shape and wavefront mapping on its sample (persistent, 4 work-groups per
+    CU) whose ratio keeps the floor of that sensor's plain 4x8 encoding.
+    `samples` maps a sensor key to (Sensor, [(frames, transforms)]).
+    Returns {key: Candidate or None}; the batch-wide mapping is the one
+    chosen for the sensor with the most pixels."""
+    out = {}
+    for k, (S, seqs) in samples.items():
+        ref = Candidate((4, 8), True, 4, False)
+        ref.ms, ref_ratio = measure(pcc, torch, ctx, S, eps, seqs, key_index, ref, reps=1)
+        cands = [Candidate(sh, True, 4, False, ln) for sh in shapes for ln in lanes]
+        for c in cands:
+            try:
+                c.ms, c.ratio = measure(pcc, torch, ctx, S, eps, seqs, key_index, c, reps=reps)
+            except pcc.PcError as e:
+                c.notes["error"] = str(e)
+        best = choose(cands, ref_ratio, ratio_floor)
+        out[k] = best
+        if log:
+            log(f"  {S.H}x{S.W} eps {eps}: {best.key() if best else None} "
+                f"({best.ms if best else float('nan'):.3f} ms, ratio {best.ratio if best else float('nan'):.3f}, "
+                f"4x8 ratio {ref_ratio:.3f})")
+    return out

@@ -148,6 +148,7 @@ static EncParams enc_params(const pc_params *p) {
   double st = 2.0 * (double)p->eps * (1.0 - 1.0 / 256.0);
   e.step = (float)st;
   e.inv = (float)(1.0 / (double)e.step);
+  e.lanes = 4;
   for (int n = 0; n < 72; n++) {
     int a = n < p->min_pts ? n : p->min_pts;
     int b = (int)ceil((double)p->min_inlier_frac * (double)n);

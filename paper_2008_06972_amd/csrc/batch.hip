@@ -527,8 +527,10 @@ pc_status pc_batch_create(pc_ctx *ctx, const pc_frame_desc *frames, int32_t nfra
   if (st) return st;
   if (!workspace || ws_bytes < B.total)
     return set_error(PC_ERR_CAPACITY, "batch workspace %zu bytes < %zu needed", ws_bytes, B.total);
-  pc_batch_opts o = opts ? *opts : pc_batch_opts{1, 1, 0, 0, nullptr};
+  pc_batch_opts o = opts ? *opts : pc_batch_opts{1, 1, 0, 0, nullptr, 0};
   if (o.records != 0 && o.records != 1) return set_error(PC_ERR_ARG, "records must be 0 or 1");
+  if (o.lanes_max != 0 && o.lanes_max != 1 && o.lanes_max != 2 && o.lanes_max != 4)
+    return set_error(PC_ERR_ARG, "lanes_max must be 0, 1, 2 or 4");
   if (o.blocks_per_cu < 0) return set_error(PC_ERR_ARG, "blocks_per_cu must be >= 0");
   char *ws = (char *)workspace;
   int *counters = (int *)(ws + B.desc + B.items + B.bins);
@@ -582,6 +584,7 @@ pc_status pc_batch_create(pc_ctx *ctx, const pc_frame_desc *frames, int32_t nfra
     D.key = F.key;
     if ((st = pcc_sensor_dev(ctx, F.sensor, &D.s))) return st;
     D.p = pcc_enc_params(F.params);
+    D.p.lanes = o.lanes_max ? o.lanes_max : 4;
     pc_layout L;
     pc_stream_layout(F.sensor, F.params, &L);
     if (L.TR > 256) return set_error(PC_ERR_UNSUPPORTED, "frame %d: more than 256 tile-row strips", i);

@@ -423,8 +423,8 @@ __device__ __forceinline__ void own_fits(StripSmem<TH, TW> &sm, const EncParams 
             sm.stat[tc] = __popcll(S2) >= need_of(p, sm.nv[tc]) ? ST_ACCEPTED : ST_REJECTED;
           }
     };
-    if (n <= kBlock / 4) fit_pass<TH, TW, 4>(sm, p, q, n, TC, fits, fp64, degenerate, kept);
-    else if (n <= kBlock / 2) fit_pass<TH, TW, 2>(sm, p, q, n, TC, fits, fp64, degenerate, kept);
+    if (p.lanes >= 4 && n <= kBlock / 4) fit_pass<TH, TW, 4>(sm, p, q, n, TC, fits, fp64, degenerate, kept);
+    else if (p.lanes >= 2 && n <= kBlock / 2) fit_pass<TH, TW, 2>(sm, p, q, n, TC, fits, fp64, degenerate, kept);
     else fit_pass<TH, TW, 1>(sm, p, q, n, TC, fits, fp64, degenerate, kept);
     n = sm.misc[M_LIST + (q ^ 1)];
   }
@@ -583,8 +583,8 @@ __device__ __forceinline__ void temporal_fits(StripSmem<TH, TW> &sm, const Frame
   int n = sm.misc[M_LIST];
   for (int it = 1; it <= p.max_iter && n > 0; it++) {
     const int q = (it - 1) & 1;
-    if (n <= kBlock / 4) temporal_pass<TH, TW, 4>(sm, p, q, n, TC, it);
-    else if (n <= kBlock / 2) temporal_pass<TH, TW, 2>(sm, p, q, n, TC, it);
+    if (p.lanes >= 4 && n <= kBlock / 4) temporal_pass<TH, TW, 4>(sm, p, q, n, TC, it);
+    else if (p.lanes >= 2 && n <= kBlock / 2) temporal_pass<TH, TW, 2>(sm, p, q, n, TC, it);
     else temporal_pass<TH, TW, 1>(sm, p, q, n, TC, it);
     __syncthreads();
     n = sm.misc[M_LIST + (q ^ 1)];
@@ -702,8 +702,8 @@ __device__ __forceinline__ int grow_runs(StripSmem<TH, TW> &sm, const EncParams 
   int n = sm.misc[M_LIST];
   for (int d = 1; d <= kReach && n > 0; d++) {
     const int q = (d - 1) & 1;
-    if (n <= kBlock / 4) reach_pass<TH, TW, 4>(sm, p, q, n, TC, d, allowed, plane_of);
-    else if (n <= kBlock / 2) reach_pass<TH, TW, 2>(sm, p, q, n, TC, d, allowed, plane_of);
+    if (p.lanes >= 4 && n <= kBlock / 4) reach_pass<TH, TW, 4>(sm, p, q, n, TC, d, allowed, plane_of);
+    else if (p.lanes >= 2 && n <= kBlock / 2) reach_pass<TH, TW, 2>(sm, p, q, n, TC, d, allowed, plane_of);
     else reach_pass<TH, TW, 1>(sm, p, q, n, TC, d, allowed, plane_of);
     __syncthreads();
     n = sm.misc[M_LIST + (q ^ 1)];

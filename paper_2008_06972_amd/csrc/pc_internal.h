@@ -39,6 +39,7 @@ struct EncParams {
   int th, tw, max_iter, min_pts;
   float rho;
   float step, inv;      // residual quantiser: step = 2 eps (1 - 2^-8), inv = 1/step
+  int lanes;            // most lanes that share one tile in the fit, temporal and reach passes (1, 2, 4)
   uint8_t need[72];     // need[n] = max(min(min_pts, n), ceil(rho n)) for n = 0..64
 };
 

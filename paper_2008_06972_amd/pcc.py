@@ -63,7 +63,7 @@ class pc_frame_desc(C.Structure):
 
 class pc_batch_opts(C.Structure):
     _fields_ = [("persistent", C.c_int32), ("graph", C.c_int32), ("blocks_per_cu", C.c_int32), ("records", C.c_int32),
-                ("net", C.c_void_p)]
+                ("net", C.c_void_p), ("lanes_max", C.c_int32)]
 
 
 # numpy views of the device records
@@ -491,7 +491,8 @@ class Batch:
     M (host 4x4 or None), sensor (Sensor), params (pc_params), key (int),
     out (FrameStream), range (device tensor or None), seed (tensor or None)."""
 
-    def __init__(self, ctx: Context, frames, persistent=True, graph=True, blocks_per_cu=0, net=None, records=False):
+    def __init__(self, ctx: Context, frames, persistent=True, graph=True, blocks_per_cu=0, net=None, records=False,
+                 lanes_max=0):
         import torch
         self._keep = []
         descs = []
@@ -515,7 +516,7 @@ class Batch:
         self.frames = frames
         self.net = net
         opts = pc_batch_opts(1 if persistent else 0, 1 if graph else 0, blocks_per_cu, 1 if records else 0,
-                             net.data_ptr() if net is not None else None)
+                             net.data_ptr() if net is not None else None, lanes_max)
         ws = pc_batch_workspace_size(descs, opts)
         self.ws = torch.empty(ws, dtype=torch.uint8, device=frames[0]["xyz"].device)
         self.h = pc_batch_create(ctx.h, descs, opts, self.ws, ws)

@@ -11,7 +11,9 @@ batched encoder's kernels and of a plain device copy of COPY_BYTES bytes
 (read once, written once); the copy's readings give the scale from counter
 units to bytes, which is applied to every kernel.  The result is JSON keyed
 by launch kind (count, scatter, keyimage, net, key, pred, finish, ...) with
-the hash of the kernel sources it was taken on.
+the hash of the kernel sources it was taken on: bytes per pass of the batch
+graph for its kinds (a pass launches the binning kernels twice, for key and
+for predicted frames), per dispatch for the others.
 """
 from __future__ import annotations
 
@@ -27,6 +29,10 @@ KINDS = (("k_batch_count", "count"), ("k_batch_scatter", "scatter"), ("k_batch_k
          ("k_net_", "net"), ("k_batch_key", "key"),
          ("k_batch_pred", "pred"), ("k_batch_finish", "finish"), ("k_batch_offsets", "offsets"),
          ("k_batch_reset", "reset"), ("k_pack_", "pack"), ("k_decode", "decode"))
+
+
+# launch kinds of the batch graph: their traffic is given per pass
+PASS_KINDS = ("count", "scatter", "keyimage", "net", "key", "pred", "finish", "offsets", "reset")
 
 
 def kernel_source_hash() -> str:
@@ -84,20 +90,29 @@ def traffic(d, fetch, write, copy_fetch, copy_write, copy_bytes, out, command):
     f_write = kib / copy_value(cw)
     bf = _counter(os.path.join(d, f"{fetch}_counter_collection.csv"), "FETCH_SIZE")
     bw = _counter(os.path.join(d, f"{write}_counter_collection.csv"), "WRITE_SIZE")
+    # a pass of the batch graph launches the predicted-frame encoder once;
+    # kinds launched several times per pass (binning of key and predicted
+    # frames) are summed over the pass
+    passes = {m: max(1, sum(len(v) for n, v in b.items() if kind_of(n) == "pred")) for m, b in (("f", bf), ("w", bw))}
     kernels = {}
     for name in sorted(set(bf) | set(bw)):
         kind = kind_of(name)
         if kind is None:
             continue
-        fv, wv = bf.get(name, [0.0]), bw.get(name, [0.0])
-        fb = sum(fv) / len(fv) * 1024.0 * f_fetch
-        wb = sum(wv) / len(wv) * 1024.0 * f_write
+        fv, wv = bf.get(name, []), bw.get(name, [])
+        if kind in PASS_KINDS:
+            fb = sum(fv) / passes["f"] * 1024.0 * f_fetch
+            wb = sum(wv) / passes["w"] * 1024.0 * f_write
+        else:
+            fb = sum(fv) / max(1, len(fv)) * 1024.0 * f_fetch
+            wb = sum(wv) / max(1, len(wv)) * 1024.0 * f_write
         k = kernels.setdefault(kind, {"kernels": [], "fetch_bytes": 0.0, "write_bytes": 0.0})
         k["kernels"].append(short(name))
         k["fetch_bytes"] += fb
         k["write_bytes"] += wb
-    for k in kernels.values():
+    for kind, k in kernels.items():
         k["bytes_per_launch"] = k["fetch_bytes"] + k["write_bytes"]
+        k["per"] = "pass" if kind in PASS_KINDS else "dispatch"
     res = {"source_hash": kernel_source_hash(), "command": command, "copy_bytes": copy_bytes,
            "scale_fetch": f_fetch, "scale_write": f_write, "kernels": kernels}
     json.dump(res, open(out, "w"), indent=1)

@@ -74,6 +74,18 @@ def mixed_sensor(beams: int, width: int) -> Sensor:
     raise ValueError(f"no preset for {beams} beams")
 
 
+# The uneven batch: every beam count with every azimuth resolution.
+MIXED = tuple((b, w) for b in (16, 32, 64, 128) for w in (1024, 2048))
+
+
+def mixed_sequence(q: int, seed0: int = 4000, n_frames: int = 10, key_index: int = 5):
+    """Sequence q of the uneven batch: sensor MIXED[q % 8] (so any run of 8
+    consecutive sequences holds every sensor), a config-1 style scene with
+    the moving cars of the sequences, seed seed0 + q."""
+    s = mixed_sensor(*MIXED[q % len(MIXED)])
+    return make_sequence(s, "c1", seed0 + q, n_frames=n_frames, key_index=key_index, moving=5, shuffle=True)
+
+
 def pixel_directions(sensor: Sensor) -> np.ndarray:
     """Unit ray directions (H, W, 3) in FP64 at the pixel centres, sensor frame."""
     e = sensor.elevations().astype(np.float64)

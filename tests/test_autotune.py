@@ -25,7 +25,10 @@ def test_none_when_nothing_qualifies():
 
 def test_candidate_space():
     cs = at.candidates(blocks=(2, 4, 8), with_net=True)
-    # 4 shapes x (3 persistent grid sizes + 1 grid form); seeds only on 4x8
-    assert len(cs) == 16
+    # 4 shapes x (3 persistent grid sizes + 1 grid form + 2 more wavefront
+    # mappings: at most 1 or 2 lanes per tile); seeds only on 4x8
+    assert len(cs) == 24
     assert all(c.seeded == (c.tile == (4, 8)) for c in cs)
     assert sum(1 for c in cs if not c.persistent) == 4
+    assert sorted({c.lanes for c in cs}) == [1, 2, 4]
+    assert len({c.key() for c in cs}) == len(cs)

@@ -23,7 +23,8 @@ def test_autotune_picks_a_valid_fast_plan():
         q = synth.make_sequence(s, "c1", seed, n_frames=10, shuffle=True)
         seqs.append((q.frames, q.transforms))
     best, cands, ref = autotune.tune(pcc, torch, ctx, S, 0.02, seqs, 5, shapes=((4, 8), (4, 4)), blocks=(2, 4), reps=2)
-    assert len(cands) == 6
+    assert len(cands) == 10
+    assert {c.lanes for c in cands} == {1, 2, 4}
     assert all(np.isfinite(c.ms) and c.ms > 0 for c in cands)
     assert best is not None and best.ok and best.ratio >= 0.98 * ref
     assert best.ms == min(c.ms for c in cands if c.ok)

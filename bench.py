@@ -78,6 +78,82 @@ def traffic_from_profiles(kernel_kind: str, launches: int):
     return k.get("bytes_per_launch")
 
 
+def _gen_mixed(q):
+    from paper_2008_06972_amd import synth
+    seq = synth.mixed_sequence(q, n_frames=N_FRAMES, key_index=KEY_INDEX)
+    return (seq.sensor.H, seq.sensor.W), seq.frames, seq.transforms
+
+
+def run_mixed(a, log, nseq=96):
+    import torch
+    from paper_2008_06972_amd import autotune, pcc, synth
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    if a.procs > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(a.procs) as pool:
+            seqs = pool.map(_gen_mixed, range(nseq), chunksize=1)
+    else:
+        seqs = [_gen_mixed(q) for q in range(nseq)]
+    sens = {hw: pcc.Sensor.of(synth.mixed_sensor(*hw)) for hw, _, _ in seqs}
+    npts = [len(f) for _, fr, _ in seqs for f in fr]
+    pts = sum(int(np.isfinite(f).all(axis=1).sum()) for _, fr, _ in seqs for f in fr)
+    xyz = [torch.from_numpy(f).to(dev) for _, fr, _ in seqs for f in fr]
+    log(f"mixed: {len(npts)} frames, {min(npts)}-{max(npts)} points per frame, generated in {time.time() - t0:.1f}s")
+    ctx = pcc.Context(list(sens.values()))
+    stream = torch.cuda.current_stream()
+    out = {"workload": f"{nseq} sequences x {N_FRAMES} frames, sensors {sorted(sens)}, 12 sequences each, "
+                       "config-1 style scenes with moving cars, key frame 5",
+           "frames": len(npts), "points": pts, "points_per_frame": [min(npts), max(npts)]}
+
+    def timed(plans, lanes):
+        fr, outs = [], []
+        prms = {}
+        j = 0
+        for q, (hw, frames, transforms) in enumerate(seqs):
+            th, tw = plans[hw]
+            prm = prms.setdefault(hw, pcc.params(eps=eps, tile_h=th, tile_w=tw))
+            for i in range(len(frames)):
+                o = pcc.FrameStream(sens[hw], prm, dev)
+                outs.append(o)
+                fr.append(dict(xyz=xyz[j], M=None if i == KEY_INDEX else transforms[i], sensor=sens[hw], params=prm,
+                               key=q * N_FRAMES + KEY_INDEX, out=o))
+                j += 1
+        b = pcc.Batch(ctx, fr, persistent=True, graph=True, lanes_max=lanes)
+        for _ in range(a.warmup):
+            b.run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(a.steps):
+            b.run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / a.steps
+        size = sum(int(o.info().size_bytes) for o in outs)
+        b.close()
+        return {"ms_per_step": ms, "frames_per_s": len(npts) / (ms / 1e3), "compression_ratio": 12.0 * pts / size,
+                "bytes": size}
+
+    for eps in (0.01, 0.02):
+        plain = timed({hw: (4, 8) for hw in sens}, 0)
+        samples = {}
+        for hw in sens:
+            q = next(q for q, x in enumerate(seqs) if x[0] == hw)
+            samples[hw] = (sens[hw], [(seqs[q][1], seqs[q][2])])
+        chosen = autotune.tune_mixed(pcc, torch, ctx, eps, samples, KEY_INDEX)
+        plans = {hw: (c.tile if c else (4, 8)) for hw, c in chosen.items()}
+        big = max(sens, key=lambda hw: hw[0] * hw[1])
+        tuned = timed(plans, chosen[big].lanes if chosen[big] else 0)
+        tuned["plans"] = {f"{hw[0]}x{hw[1]}": (c.key() if c else None) for hw, c in chosen.items()}
+        out[f"eps_{eps}"] = {"tiles_4x8": plain, "autotuned": tuned}
+        log(f"mixed eps {eps}: 4x8 {plain['frames_per_s']:.0f} frames/s ratio {plain['compression_ratio']:.2f}; "
+            f"autotuned {tuned['frames_per_s']:.0f} frames/s ratio {tuned['compression_ratio']:.2f}")
+    ctx.close()
+    del xyz
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +169,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-pack", action="store_true", help="skip packing the frames into containers")
     ap.add_argument("--no-decode", action="store_true", help="skip decoding the frames")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the uneven batch (eight sensors, eps 1 and 2 cm)")
     ap.add_argument("--procs", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -454,6 +531,14 @@ def main():
                             "what": "pc_decode_batch over every frame of the timed form (job-table upload included)"}
         log(f"decode: {dms:.3f} ms for {nfr} frames")
         del dec, dec_list, work_d
+
+    # ------------------------------------------------------ uneven batch
+    # 96 sequences over eight sensors (16/32/64/128 beams x 1024/2048 bins),
+    # config-1 style scenes, one graph per eps; per sensor the autotuner's
+    # tile shape and mapping (timed on one sequence per sensor), beside the
+    # same batch with 4x8 tiles everywhere
+    if not a.no_mixed:
+        result["mixed"] = run_mixed(a, log)
 
     # ------------------------------------------------------- CPU baseline
     if not a.no_cpu:

@@ -59,6 +59,9 @@ SENSORS = {
     "c1": Sensor(16, 512, 15.0, -15.0),
     # HDL-64E-like: 64 beams from +2 to -24.8 deg, 2048 bins
     "c2": Sensor(64, 2048, 2.0, -24.8),
+    # the seed network's sensor: 128 beams from +15 to -25 deg, 2048 bins
+    # (config-2 style scenes)
+    "c5": Sensor(128, 2048, 15.0, -25.0),
 }
 
 

@@ -2,7 +2,8 @@
 the oracle: forward seeds and parameter gradients within cosine >= 0.999 and
 relative L2 error <= 2e-2 per tensor (bfloat16 inputs and weights, FP32
 accumulation against FP64), the loss and its gradient, one Adam step, and the
-seeded fit with fallback on a 64x2048 frame."""
+seeded fit with fallback, on a 64x2048 frame and on a 128x2048 frame (the
+network's own sensor, 128 beams from +15 to -25 deg)."""
 import sys
 
 import numpy as np
@@ -37,12 +38,13 @@ def _agree(g, o):
     return cos, rel
 
 
-@pytest.fixture(scope="module")
-def frame():
-    s = synth.SENSORS["c2"]
+@pytest.fixture(scope="module", params=[("c2", 2100), ("c5", 900500)], ids=["64x2048", "128x2048"])
+def frame(request):
+    name, fseed = request.param
+    s = synth.SENSORS[name]
     S = pcc.Sensor.of(s)
     ctx = pcc.Context([S])
-    pts, _, _ = synth.make_frame(s, "c2", 2100)
+    pts, _, _ = synth.make_frame(s, "c2", fseed)
     xyz = torch.from_numpy(pts).to(DEV)
     rng = torch.empty(s.H, s.W, dtype=torch.float32, device=DEV)
     pcc.pc_project(ctx.h, xyz, len(pts), None, S, rng)

@@ -398,8 +398,8 @@ def main():
         nk = sum(1 for j in range(nfr) if j == key_of(j))
         npf = nfr - nk
         # algorithmic bytes per launch: what the method must move, not what
-        # this implementation moves.  Projection reads 12 B per point and
-        # produces a 4 B range value per pixel; an encoder reads the range
+        # this implementation moves.  Projection (binning) reads 12 B per
+        # point and produces a 4 B range value per pixel; an encoder reads the range
         # image (4 B per pixel) and writes the occupancy bits (1/8 B per
         # pixel), the run and plane table (16 B per tile), the masks (8 B per
         # tile) and the codes (2 B each); a predicted frame also reads the
@@ -407,8 +407,7 @@ def main():
         pts_k = sum(int(fin_per_frame[j]) for j in range(nfr) if j == key_of(j))
         Tb = batch.outs[0].L.T            # tiles per frame of the timed mapping
         alg = {
-            "count": 12 * finite_pts,
-            "scatter": 4 * HW * nfr,
+            "bin": 12 * finite_pts + 4 * HW * nfr,
             "key": nk * (4 * HW + HW // 8 + 16 * Tb + 8 * Tb) + 2 * n_res_k,
             "pred": npf * (4 * HW + HW // 8 + 16 * Tb + 8 * Tb + 16 * Tb) + 2 * n_res_p,
         }

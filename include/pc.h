@@ -390,9 +390,9 @@ pc_status pc_batch_info(const pc_batch *batch, int32_t *nitems, int32_t *ngroups
  * launch; ms[i] is the duration of launch i and kinds[i] its PC_LAUNCH_* kind
  * (kinds may be NULL).  Synchronises the stream.  For measurement only. */
 #define PC_LAUNCH_RESET 0
-#define PC_LAUNCH_COUNT 1     /* projection, points per strip */
-#define PC_LAUNCH_OFFSETS 2
-#define PC_LAUNCH_SCATTER 3   /* projection, points into their strips' buckets */
+#define PC_LAUNCH_COUNT 1     /* binning: projection, each block's points grouped by strip */
+#define PC_LAUNCH_OFFSETS 2   /* (not launched: kept for the numbering) */
+#define PC_LAUNCH_SCATTER 3   /* (not launched: kept for the numbering) */
 #define PC_LAUNCH_KEY 4
 #define PC_LAUNCH_PRED 5
 #define PC_LAUNCH_FINISH 6

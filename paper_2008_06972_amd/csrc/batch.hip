@@ -1,28 +1,27 @@
 // Batched encoding of many frames of many sensors in one HIP graph.
 //
 // A plan holds a device table of frame descriptors.  One replay runs:
-//   reset    zero the strip counters and queue counters (a kernel, so the
-//            graph holds no memset node)
-//   count    project every point (Eq. (1), (2), (6)), stage it as (strip,
-//            LDS slot, range bits) and count the points of each (frame,
-//            tile-row strip); one global atomic per (work-group, strip)
-//   offsets  per frame, exclusive sum of the strip counts
-//   scatter  move the staged points into their strips' buckets, reserving
-//            space once per (work-group, strip)
+//   reset    zero the queue counters (a kernel, so the graph holds no memset
+//            node)
+//   bin      project every point (Eq. (1), (2), (6)); each work-group groups
+//            its 2048 points by tile-row strip in LDS and writes them as one
+//            chunk of (LDS slot, range bits) entries, with the chunk's first
+//            entry of every strip
 //   keyimage (with a seed network) the key frames' range images, built per
-//            strip from the buckets in LDS
+//            strip from the chunks in LDS
 //   net      the seed network's forward pass over those key frames
 //   key      persistent work-groups pull (key frame, strip) items from an
-//            atomic counter; each builds its strip from the bucket with LDS
-//            atomicMin (nearest point wins, Sec. III-D) and encodes it
+//            atomic counter; each builds its strip from its segment of every
+//            chunk of the frame with LDS atomicMin (nearest point wins,
+//            Sec. III-D) and encodes it
 //   pred     the same for the predicted frames' strips
 //   finish   one block per frame: totals and the Huffman size
-// Device-wide atomics are slow on this chip (a few tens of billions per
-// second): binning keeps them to a few per 2048 points, and the per-pixel
-// minimum happens in LDS.  The range image never goes through HBM.
-// Phases are separate kernels, so a predicted strip never waits inside a
-// kernel for its key strip.  Items are grouped by tile shape; each group is
-// one launch per phase.
+// Binning needs no device-wide atomics and moves each point once (12 bytes
+// read, 8 written, 8 read back by its strip); the per-pixel minimum happens
+// in LDS and the range image never goes through HBM.  Phases are separate
+// kernels, so a predicted strip never waits inside a kernel for its key
+// strip.  Items are grouped by tile shape; each group is one launch per
+// phase.
 #include <string.h>
 
 #include <algorithm>
@@ -38,6 +37,7 @@ namespace pcc {
 constexpr int kBinPts = 8;                 // points per thread in the binning passes
 constexpr int kBinBlock = 256;
 constexpr int kBinChunk = kBinPts * kBinBlock;
+static_assert(kBinChunk == kBinChunkPts, "chunk capacity as the strip loader reads it");
 constexpr size_t kCountTabMax = 32 * 1024;  // sensor tables up to this size go to LDS in the binning pass
 
 struct FrameDescDev {
@@ -50,12 +50,11 @@ struct FrameDescDev {
   int pad0;
   SensorDev s;
   EncParams p;
-  uint2 *stage;    // n entries: (strip << 16 | LDS slot, range bits), ~0 for dropped points
-  uint2 *bucket;   // n entries: (LDS slot, range bits), grouped by strip
+  uint2 *chunks;   // nblk * kBinChunk entries (LDS slot, range bits): binning block b's kept points
+                   // from b * kBinChunk on, grouped by strip
+  int *blkoff;     // [nblk][TR + 1]: first entry of each strip in block b's chunk; [TR]: its kept points
+  int nblk;        // binning blocks of the frame
   int twl;         // log2 tile_w
-  int *bcount;     // [TR] points per strip
-  int *boff;       // [TR] first bucket entry of each strip
-  int *bcur;       // [TR] scatter cursors
   float *range_out;
   const float *seed;
   float *net_range;  // key frame's range image for the seed network, or NULL
@@ -71,20 +70,24 @@ __global__ void k_batch_reset(int *a, int64_t n) {
 // blocks [first[f], first[f+1]) belong to frame f; owner[b] = f.  With
 // LdsTab the sensor's cut tangents and edge vectors are first copied into
 // LDS (H + 1 + 2 W floats) and the row and column walks read them there.
+// Each thread projects kBinPts points and takes a rank in its strip's LDS
+// count; after the block's exclusive sum over the strips, the entries are
+// grouped by strip in LDS (over the tables, which are no longer needed) and
+// copied out as one contiguous chunk, and the strip offsets beside it.
 template <bool LdsTab>
-__global__ void __launch_bounds__(kBinBlock) k_batch_count(const FrameDescDev *__restrict__ d, const int *__restrict__ owner,
-                                                           const int *__restrict__ first, int base) {
-  __shared__ int hist[256];
-  extern __shared__ __align__(16) float tabs[];
+__global__ void __launch_bounds__(kBinBlock) k_batch_bin(const FrameDescDev *__restrict__ d, const int *__restrict__ owner,
+                                                         const int *__restrict__ first, int base) {
+  __shared__ int cnt[256], loff[257];
+  extern __shared__ __align__(16) float tabs[];      // tables, then the grouped entries
   const int blk = base + blockIdx.x;
   const int fidx = __builtin_amdgcn_readfirstlane(owner[blk]);
   const FrameDescDev &D = d[fidx];
-  const int th = D.p.th, thl = __ffs(th) - 1, TR = D.f.TR;     // tile heights are powers of two
-  for (int t = threadIdx.x; t < TR; t += kBinBlock) hist[t] = 0;
+  const int th = D.p.th, thl = __ffs(th) - 1, TR = D.f.TR, tid = threadIdx.x;     // tile heights are powers of two
+  for (int t = tid; t < TR; t += kBinBlock) cnt[t] = 0;
   const int H = D.s.H, W = D.s.W;
   if (LdsTab) {
-    for (int t = threadIdx.x; t <= H; t += kBinBlock) tabs[t] = gload(D.s.cut + t);
-    for (int t = threadIdx.x; t < W; t += kBinBlock) {
+    for (int t = tid; t <= H; t += kBinBlock) tabs[t] = gload(D.s.cut + t);
+    for (int t = tid; t < W; t += kBinBlock) {
       tabs[H + 1 + t] = gload(D.s.ebx + t);
       tabs[H + 1 + W + t] = gload(D.s.eby + t);
     }
@@ -93,86 +96,33 @@ __global__ void __launch_bounds__(kBinBlock) k_batch_count(const FrameDescDev *_
   const TabLds tl{(lfloat *)tabs, (lfloat *)(tabs + H + 1), (lfloat *)(tabs + H + 1 + W)};
   const TabGlobal tg{D.s.cut, D.s.ebx, D.s.eby};
   __syncthreads();
-  const int64_t p0 = (int64_t)(blk - first[fidx]) * kBinChunk;
+  const int b = blk - first[fidx];
+  const int64_t p0 = (int64_t)b * kBinChunk;
   const auto *xyz = (const __attribute__((address_space(1))) float *)D.xyz;
-  auto *stage = (__attribute__((address_space(1))) uint64_t *)D.stage;    // x | y << 32
-#pragma unroll 4
+  uint64_t e[kBinPts];
+  int key[kBinPts];     // strip << 16 | rank in the strip, -1 for a dropped point
+#pragma unroll
   for (int q = 0; q < kBinPts; q++) {
-    const int64_t i = p0 + q * kBinBlock + threadIdx.x;
-    if (i >= D.n) break;
+    const int64_t i = p0 + q * kBinBlock + tid;
+    key[q] = -1;
+    e[q] = 0;
+    if (i >= D.n) continue;
     int v, u;
     float r;
-    uint64_t e = ~0ull;
     const int st = LdsTab ? project_point(D.s, tl, D.M, D.hasM, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], v, u, r)
                           : project_point(D.s, tg, D.M, D.hasM, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], v, u, r);
     if (st == PROJ_KEPT) {
       const int strip = v >> thl;
-      const uint32_t x = ((uint32_t)strip << 16) | (uint32_t)strip_slot(v & (th - 1), u, th, D.twl);
-      e = (uint64_t)x | ((uint64_t)__float_as_uint(r) << 32);
-      atomicAdd(&hist[strip], 1);
+      e[q] = (uint64_t)(uint32_t)strip_slot(v & (th - 1), u, th, D.twl) | ((uint64_t)__float_as_uint(r) << 32);
+      key[q] = (strip << 16) | atomicAdd(&cnt[strip], 1);
     }
-    stage[i] = e;
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < TR; t += kBinBlock)
-    if (hist[t]) atomicAdd(&D.bcount[t], hist[t]);
-}
-
-// frames[0 .. n): the frames whose strip offsets to compute, one wavefront
-// per frame (exclusive prefix sum of the strip counts)
-__global__ void __launch_bounds__(256) k_batch_offsets(const FrameDescDev *__restrict__ d, const int *__restrict__ frames,
-                                                       int n) {
-  const int w = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6), lane = (int)(threadIdx.x & 63);
-  if (w >= n) return;
-  const FrameDescDev &D = d[frames[w]];
-  const int TR = D.f.TR;
-  int carry = 0;
-  for (int t0 = 0; t0 < TR; t0 += 64) {
-    const int t = t0 + lane;
-    const int c = t < TR ? D.bcount[t] : 0;
-    int x = c;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(x, o, 64);
-      if (lane >= o) x += y;
-    }
-    if (t < TR) {
-      D.boff[t] = carry + x - c;
-      D.bcur[t] = carry + x - c;
-    }
-    carry += __shfl(x, 63, 64);
-  }
-}
-
-__global__ void __launch_bounds__(kBinBlock) k_batch_scatter(const FrameDescDev *__restrict__ d,
-                                                             const int *__restrict__ owner, const int *__restrict__ first,
-                                                             int bbase) {
-  __shared__ int cnt[256], base[256], lim[256], loff[256];
-  __shared__ uint64_t sorted[kBinChunk];       // the block's entries, grouped by strip
-  const int blk = bbase + blockIdx.x;
-  const int fidx = __builtin_amdgcn_readfirstlane(owner[blk]);
-  const FrameDescDev &D = d[fidx];
-  const int TR = D.f.TR, tid = threadIdx.x, lane = tid & 63;
-  for (int t = tid; t < TR; t += kBinBlock) cnt[t] = 0;
-  __syncthreads();
-  const int64_t b0 = (int64_t)(blk - first[fidx]) * kBinChunk;
-  // entries are x | y << 32: x = strip << 16 | slot (~0 dropped), y = range bits
-  const auto *stage = (const __attribute__((address_space(1))) uint64_t *)D.stage;
-  auto *bucket = (__attribute__((address_space(1))) uint64_t *)D.bucket;
-  uint64_t e[kBinPts];
-  int slot[kBinPts];
-#pragma unroll
-  for (int q = 0; q < kBinPts; q++) {
-    const int64_t i = b0 + q * kBinBlock + tid;
-    e[q] = i < D.n ? (uint64_t)stage[i] : ~0ull;
-  }
-#pragma unroll
-  for (int q = 0; q < kBinPts; q++)
-    slot[q] = (uint32_t)e[q] != 0xffffffffu ? atomicAdd(&cnt[(uint32_t)e[q] >> 16], 1) : 0;
-  __syncthreads();
-  // the block's strip offsets (exclusive prefix sum, first wavefront) and
-  // its place in each strip's bucket
+  // exclusive sum over the strips (first wavefront); the offsets go out
+  // beside the chunk
+  int *bo = D.blkoff + (int64_t)b * (TR + 1);
   if (tid < 64) {
+    const int lane = tid;
     int carry = 0;
     for (int t0 = 0; t0 < TR; t0 += 64) {
       const int t = t0 + lane;
@@ -183,34 +133,30 @@ __global__ void __launch_bounds__(kBinBlock) k_batch_scatter(const FrameDescDev 
         const int y = __shfl_up(x, o, 64);
         if (lane >= o) x += y;
       }
-      if (t < TR) loff[t] = carry + x - c;
+      if (t < TR) {
+        loff[t] = carry + x - c;
+        bo[t] = carry + x - c;
+      }
       carry += __shfl(x, 63, 64);
     }
-  }
-  for (int t = tid; t < TR; t += kBinBlock)
-    if (cnt[t]) {
-      base[t] = atomicAdd(&D.bcur[t], cnt[t]);
-      lim[t] = D.boff[t] + D.bcount[t];
+    if (lane == 0) {
+      loff[TR] = carry;
+      bo[TR] = carry;
     }
+  }
   __syncthreads();
+  uint64_t *sorted = reinterpret_cast<uint64_t *>(tabs);
 #pragma unroll
   for (int q = 0; q < kBinPts; q++)
-    if ((uint32_t)e[q] != 0xffffffffu) sorted[loff[(uint32_t)e[q] >> 16] + slot[q]] = e[q];
+    if (key[q] >= 0) sorted[loff[key[q] >> 16] + (key[q] & 0xffff)] = e[q];
   __syncthreads();
-  // consecutive entries of a strip go to consecutive bucket slots.  Both
-  // passes see the same staged entries, so every entry fits its strip's
-  // range; the limit only keeps a bucket from spilling into its neighbour.
-  const int total = loff[TR - 1] + cnt[TR - 1];
-  for (int k = tid; k < total; k += kBinBlock) {
-    const uint64_t x = sorted[k];
-    const int strip = (uint32_t)x >> 16;
-    const int at = base[strip] + (k - loff[strip]);
-    if (at < lim[strip]) bucket[at] = x & 0xffffffff0000ffffull;
-  }
+  auto *out = (__attribute__((address_space(1))) uint64_t *)(D.chunks) + p0;
+  const int total = loff[TR];
+  for (int k = tid; k < total; k += kBinBlock) out[k] = sorted[k];
 }
 
 __device__ __forceinline__ StripSrc src_of(const FrameDescDev &D) {
-  return StripSrc{nullptr, D.bucket, D.bcount, D.boff, D.range_out};
+  return StripSrc{nullptr, D.chunks, D.blkoff, D.nblk, D.f.TR, D.range_out};
 }
 
 template <int TH, int TW>
@@ -265,7 +211,7 @@ __global__ void __launch_bounds__(kBlock, kStripWavesPerEU) k_batch_pred_grid(co
 }
 
 // Range image of a key frame's strip for the seed network: the strip's
-// bucket resolved in LDS (nearest point wins) and written out.
+// binned points resolved in LDS (nearest point wins) and written out.
 template <int TH, int TW>
 __global__ void __launch_bounds__(kBlock) k_batch_keyimage(const FrameDescDev *__restrict__ d,
                                                            const int2 *__restrict__ items) {
@@ -274,7 +220,8 @@ __global__ void __launch_bounds__(kBlock) k_batch_keyimage(const FrameDescDev *_
   const FrameDescDev &D = d[fi.x];
   StripSmem<TH, TW> sm;
   sm.r = reinterpret_cast<float *>(smem_raw);
-  load_source<TH, TW>(sm, StripSrc{nullptr, D.bucket, D.bcount, D.boff, D.net_range}, D.s, fi.y);
+  sm.scratch = reinterpret_cast<uint32_t *>(smem_raw + sizeof(float) * (size_t)(D.s.W / TW) * TH * TW);
+  load_source<TH, TW>(sm, StripSrc{nullptr, D.chunks, D.blkoff, D.nblk, D.f.TR, D.net_range}, D.s, fi.y);
 }
 
 __global__ void __launch_bounds__(256) k_batch_finish(const FrameDescDev *__restrict__ d) {
@@ -307,7 +254,8 @@ struct BatchPlan {
   int *d_counters = nullptr;     // queue counters (64), then the frames' strip counts
   int64_t ncounters = 0;
   int bin_blocks = 0;
-  size_t count_smem = 0;     // LDS of the binning pass's sensor tables (0: read from device memory)
+  size_t count_smem = 0;     // LDS of the binning pass: its sensor tables and then its grouped entries
+  int count_tab = 0;         // the sensor tables fit in LDS (else the walks read device memory)
   std::vector<Group> groups;
   int persistent = 1;
   // seed network (key frames with 4x8 tiles)
@@ -368,30 +316,19 @@ static hipError_t launch_group(BatchPlan &P, int gi, hipStream_t st) {
   return hipLaunchKernel(fn, dim3(g.count), dim3(kBlock), args, g.smem, st);
 }
 
-// Binning of one frame subset: count, offsets, scatter.
+// Binning of one frame subset.
 template <class Mark>
 static void bin_frames(BatchPlan &P, bool key, hipStream_t st, Mark mark) {
   const int nb = key ? P.bin_blocks_key : P.bin_blocks - P.bin_blocks_key;
   const int base = key ? 0 : P.bin_blocks_key;
-  const int nf = key ? P.nkey : P.npred;
-  if (!nf) return;
-  if (nb) {
-    if (P.count_smem)
-      hipLaunchKernelGGL(k_batch_count<true>, dim3(nb), dim3(kBinBlock), P.count_smem, st, P.d_desc, P.d_bin_owner,
-                         P.d_bin_first, base);
-    else
-      hipLaunchKernelGGL(k_batch_count<false>, dim3(nb), dim3(kBinBlock), 0, st, P.d_desc, P.d_bin_owner,
-                         P.d_bin_first, base);
-    mark(PC_LAUNCH_COUNT);
-  }
-  hipLaunchKernelGGL(k_batch_offsets, dim3((nf + 3) / 4), dim3(256), 0, st, P.d_desc,
-                     key ? P.d_key_frames : P.d_pred_frames, nf);
-  mark(PC_LAUNCH_OFFSETS);
-  if (nb) {
-    hipLaunchKernelGGL(k_batch_scatter, dim3(nb), dim3(kBinBlock), 0, st, P.d_desc, P.d_bin_owner, P.d_bin_first,
-                       base);
-    mark(PC_LAUNCH_SCATTER);
-  }
+  if (!nb) return;
+  if (P.count_tab)
+    hipLaunchKernelGGL(k_batch_bin<true>, dim3(nb), dim3(kBinBlock), P.count_smem, st, P.d_desc, P.d_bin_owner,
+                       P.d_bin_first, base);
+  else
+    hipLaunchKernelGGL(k_batch_bin<false>, dim3(nb), dim3(kBinBlock), P.count_smem, st, P.d_desc, P.d_bin_owner,
+                       P.d_bin_first, base);
+  mark(PC_LAUNCH_COUNT);
 }
 
 // All launches of one batch, in order; mark(kind) follows each (PC_LAUNCH_*).
@@ -484,8 +421,9 @@ static pc_status batch_sizes(const pc_frame_desc *frames, int32_t nframes, const
     int tr = F.sensor->H / (F.params->tile_h > 0 ? F.params->tile_h : 1);
     items += tr;
     strips += tr;
-    bb += (F.n + kBinChunk - 1) / kBinChunk;
-    buckets += 2 * a256(sizeof(uint2) * (size_t)F.n);
+    const int64_t nblk = (F.n + kBinChunk - 1) / kBinChunk;
+    bb += nblk;
+    buckets += a256(sizeof(uint2) * (size_t)nblk * kBinChunk) + a256(sizeof(int) * (size_t)nblk * (tr + 1));
     if (net_frame(F, i, opts)) {
       nnet++;
       net_items += tr;
@@ -503,7 +441,7 @@ static pc_status batch_sizes(const pc_frame_desc *frames, int32_t nframes, const
   B.desc = a256(sizeof(FrameDescDev) * (size_t)nframes);
   B.items = a256(sizeof(int2) * (size_t)items);
   B.bins = a256(sizeof(int) * ((size_t)bb + 2 * (size_t)nframes));     // owner, first, frame lists
-  B.counters = a256(sizeof(int) * (64 + 3 * (size_t)strips));
+  B.counters = a256(sizeof(int) * 64);
   B.buckets = buckets;
   B.net = net;
   B.total = B.desc + B.items + B.bins + B.counters + B.buckets + B.net;
@@ -534,7 +472,6 @@ pc_status pc_batch_create(pc_ctx *ctx, const pc_frame_desc *frames, int32_t nfra
   if (o.blocks_per_cu < 0) return set_error(PC_ERR_ARG, "blocks_per_cu must be >= 0");
   char *ws = (char *)workspace;
   int *counters = (int *)(ws + B.desc + B.items + B.bins);
-  int *strip_counts = counters + 64;
   char *bucket_ws = ws + B.desc + B.items + B.bins + B.counters;
   char *net_ws = bucket_ws + B.buckets;
   std::vector<FrameDescDev> desc((size_t)nframes);
@@ -559,7 +496,6 @@ pc_status pc_batch_create(pc_ctx *ctx, const pc_frame_desc *frames, int32_t nfra
     d_net_items = (int2 *)net_ws;
     net_ws += a256(sizeof(int2) * B.net_items);
   }
-  int64_t strip_at = 0;
   for (int i = 0; i < nframes; i++) {
     const pc_frame_desc &F = frames[i];
     if ((st = pcc_check_all(F.sensor, F.params))) return st;
@@ -590,15 +526,12 @@ pc_status pc_batch_create(pc_ctx *ctx, const pc_frame_desc *frames, int32_t nfra
     if (L.TR > 256) return set_error(PC_ERR_UNSUPPORTED, "frame %d: more than 256 tile-row strips", i);
     D.f = frame_dev(F.out, L);
     if (!o.records) D.f.tiles = nullptr;     // per-tile fit records are diagnostics only
-    D.bucket = (uint2 *)bucket_ws;
-    bucket_ws += a256(sizeof(uint2) * (size_t)F.n);
-    D.stage = (uint2 *)bucket_ws;
-    bucket_ws += a256(sizeof(uint2) * (size_t)F.n);
+    D.nblk = (int)((F.n + kBinChunk - 1) / kBinChunk);
+    D.chunks = (uint2 *)bucket_ws;
+    bucket_ws += a256(sizeof(uint2) * (size_t)D.nblk * kBinChunk);
+    D.blkoff = (int *)bucket_ws;
+    bucket_ws += a256(sizeof(int) * (size_t)D.nblk * (L.TR + 1));
     D.twl = __builtin_ctz((unsigned)F.params->tile_w);
-    D.bcount = strip_counts + strip_at;
-    D.boff = strip_counts + B.strips + strip_at;
-    D.bcur = strip_counts + 2 * B.strips + strip_at;
-    strip_at += L.TR;
     D.range_out = F.range;
     D.seed = F.seed;
     if (net_frame(F, i, &o)) {
@@ -636,7 +569,8 @@ pc_status pc_batch_create(pc_ctx *ctx, const pc_frame_desc *frames, int32_t nfra
     size_t tab = 0;
     for (int i = 0; i < nframes; i++)
       tab = std::max(tab, sizeof(float) * (size_t)(desc[i].s.H + 1 + 2 * desc[i].s.W));
-    P.count_smem = tab <= kCountTabMax ? tab : 0;
+    P.count_tab = tab <= kCountTabMax ? 1 : 0;
+    P.count_smem = std::max(P.count_tab ? tab : (size_t)0, sizeof(uint64_t) * (size_t)kBinChunk);
   }
   std::vector<int2> items;
   items.reserve(B.nitems);
@@ -679,7 +613,8 @@ pc_status pc_batch_create(pc_ctx *ctx, const pc_frame_desc *frames, int32_t nfra
     P.net_wpk = net_wpk;
     P.d_net_items = d_net_items;
     P.n_net_items = (int)net_items.size();
-    P.net_smem = sizeof(float) * (size_t)(net_maxW / 8) * StripSmem<4, 8>::N;
+    // the strip's ranges, then the binning offsets the loader gathers
+    P.net_smem = sizeof(float) * (size_t)(net_maxW / 8) * StripSmem<4, 8>::N + kSegBytes;
     P.d_net_in = d_net_in;
     P.d_net_conv = d_net_conv;
     P.net_hw[0] = net_hw[0];
@@ -718,7 +653,7 @@ pc_status pc_batch_create(pc_ctx *ctx, const pc_frame_desc *frames, int32_t nfra
   P.d_key_frames = P.d_bin_first + nframes;
   P.d_pred_frames = P.d_key_frames + P.nkey;
   P.d_counters = counters;
-  P.ncounters = 64 + B.strips;      // queue counters and the strip counts (offsets and cursors are rewritten)
+  P.ncounters = 64;                 // queue counters (binning rewrites its chunk offsets every pass)
   bool ok = hipMemcpy(P.d_desc, desc.data(), sizeof(FrameDescDev) * desc.size(), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(P.d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice) == hipSuccess &&
             (bin_owner.empty() || hipMemcpy(P.d_bin_owner, bin_owner.data(), sizeof(int) * bin_owner.size(), hipMemcpyHostToDevice) == hipSuccess) &&

@@ -8,7 +8,7 @@ template <int TH, int TW>
 __global__ void __launch_bounds__(kBlock, kStripWavesPerEU) k_encode_key(const float *__restrict__ range, SensorDev s, EncParams p,
                                                        const float *__restrict__ seed, FrameDev f) {
   extern __shared__ __align__(16) char smem_raw[];
-  StripSrc src{range, nullptr, nullptr, nullptr, nullptr};
+  StripSrc src{range, nullptr, nullptr, 0, 0, nullptr};
   key_strip<TH, TW>(smem_raw, src, s, p, seed, f, blockIdx.x);
 }
 
@@ -16,7 +16,7 @@ template <int TH, int TW>
 __global__ void __launch_bounds__(kBlock, kStripWavesPerEU) k_encode_pred(const float *__restrict__ range, SensorDev s, EncParams p,
                                                         FrameDev key, FrameDev f) {
   extern __shared__ __align__(16) char smem_raw[];
-  StripSrc src{range, nullptr, nullptr, nullptr, nullptr};
+  StripSrc src{range, nullptr, nullptr, 0, 0, nullptr};
   pred_strip<TH, TW>(smem_raw, key, src, s, p, f, blockIdx.x);
 }
 

@@ -42,6 +42,9 @@ __device__ __forceinline__ int strip_tid() {
 }
 
 constexpr int kReach = 6;     // tiles a fit measures its reach over before the walk continues it
+constexpr int kBinChunkPts = 2048;      // points per binning block (its chunk's capacity)
+constexpr int kSegMax = 512;            // chunk offsets the loader gathers at a time (two ints each)
+constexpr size_t kSegBytes = 2 * sizeof(int) * kSegMax;
 
 // ---------------------------------------------------------------- LDS layout
 // Ranges are stored tile-major, N = th*tw per tile with no padding; the
@@ -79,7 +82,7 @@ struct StripSmem {
   uint64_t *acc;     // [(TC + 63) / 64] tiles that may start a run (bit tc)
   int32_t *krun;     // [TC] key run slot, -1 if the key tile is not plane coded (predicted frames)
   uint32_t *scratch; // fits: cur (u64[TC]), two work lists and the FP64 list (i16[TC] each);
-                     // residuals: counts per (row, tile) (u32[TH * TC])
+                     // residuals: counts per (row, tile) (u32[TH * TC]); load: chunk offsets
   uint32_t *hist;    // [4 * 256] 16-bit counts, two per word (byte v of a stream in half v & 1)
   int32_t *misc;     // [32] counters
 
@@ -87,9 +90,12 @@ struct StripSmem {
   __device__ uint64_t *cur() const { return reinterpret_cast<uint64_t *>(scratch); }
   __device__ int16_t *list(int q, int TC) const { return reinterpret_cast<int16_t *>(cur() + TC) + q * TC; }
 
+  // fits: cur and three lists; residuals: counts; the load of binned
+  // points: the chunk offsets it gathers
   __host__ __device__ static size_t scratch_bytes(int TC) {
     size_t a = sizeof(uint32_t) * (size_t)TH * TC, b = sizeof(uint64_t) * (size_t)TC + 3 * sizeof(int16_t) * (size_t)TC;
-    return a > b ? a : b;
+    size_t m = a > b ? a : b;
+    return m > kSegBytes ? m : kSegBytes;
   }
   __host__ __device__ static size_t bytes(int W, int TC, bool pred) {
     auto a16 = [](size_t n) { return (n + 15) & ~(size_t)15; };
@@ -220,45 +226,69 @@ __device__ __forceinline__ void load_strip(StripSmem<TH, TW> &sm, const float *_
 }
 
 // Where a strip's ranges come from: a range image (0 = empty), or the
-// strip's bucket of (LDS slot, range bits) entries from the batched binning
-// pass (slots as strip_slot gives them), resolved here with LDS atomicMin:
-// the nearest point wins (Sec. III-D).  range_out, if set, receives the
-// strip's range image.
+// batched binning pass's chunks, one per binning block of the frame, each
+// holding its block's kept points as (LDS slot, range bits) entries grouped
+// by strip (slots as strip_slot gives them), resolved here with LDS
+// atomicMin: the nearest point wins (Sec. III-D).  range_out, if set,
+// receives the strip's range image.
 struct StripSrc {
   const float *range;
-  const uint2 *bucket;     // frame's bucket entries
-  const int *bcount;       // [TR] entries per strip
-  const int *boff;         // [TR] first entry of each strip
+  const uint2 *chunks;     // frame's chunks, block b's at b * kBinChunkPts
+  const int *blkoff;       // [nblk][TR + 1] first entry of each strip in each chunk
+  int nblk, TR;
   float *range_out;
 };
 
 template <int TH, int TW>
 __device__ __forceinline__ void load_source(StripSmem<TH, TW> &sm, const StripSrc &src, const SensorDev &s, int tr) {
-  constexpr int N = StripSmem<TH, TW>::N, U = 8;
+  constexpr int N = StripSmem<TH, TW>::N, NW = kBlock / 64;
   const int W = s.W, TC = W / TW, tid = strip_tid();
-  if (!src.bucket) {
+  if (!src.chunks) {
     load_strip<TH, TW>(sm, src.range, s, tr);
   } else {
     uint32_t *ri = reinterpret_cast<uint32_t *>(sm.r);
     for (int e = tid; e < TC * N; e += kBlock) ri[e] = 0x7f800000u;   // +inf: empty
-    __syncthreads();
-    const int n = src.bcount[tr];
-    // entry = slot | range bits << 32
-    const auto *b = (const __attribute__((address_space(1))) uint64_t *)(src.bucket + src.boff[tr]);
     const uint32_t lim = (uint32_t)(TC * N);
-    // U entries in flight per thread before their atomics
-    for (int q0 = tid; q0 < n; q0 += U * kBlock) {
-      uint64_t en[U];
-#pragma unroll
-      for (int u = 0; u < U; u++) {
-        const int q = q0 + u * kBlock;
-        en[u] = q < n ? (uint64_t)b[q] : ~0ull;
+    const int lane = tid & 63, wv = tid >> 6, stride = src.TR + 1;
+    int *sb = reinterpret_cast<int *>(sm.scratch), *sl = sb + kSegMax;     // segment start and length per chunk
+    const auto *ch = (const __attribute__((address_space(1))) uint64_t *)src.chunks;
+    for (int c0 = 0; c0 < src.nblk; c0 += kSegMax) {
+      const int nb = min(kSegMax, src.nblk - c0);
+      for (int b = tid; b < nb; b += kBlock) {
+        const int *o = src.blkoff + (int64_t)(c0 + b) * stride + tr;
+        const int a = o[0];
+        sb[b] = a;
+        sl[b] = o[1] - a;
       }
+      __syncthreads();
+      // a wavefront takes four chunks' segments at a time and reads them
+      // jointly, 128 entries of each per round (eight loads per lane in
+      // flight), as many rounds as the longest of the four needs
+      for (int b0 = wv; b0 < nb; b0 += 4 * NW) {
+        int len[4];
+        int64_t at[4];
+        int mx = 0;
 #pragma unroll
-      for (int u = 0; u < U; u++)
-        if ((uint32_t)en[u] < lim) atomicMin(&ri[(uint32_t)en[u]], (uint32_t)(en[u] >> 32));
+        for (int u = 0; u < 4; u++) {
+          const int b = b0 + u * NW;
+          len[u] = b < nb ? sl[b] : 0;
+          at[u] = (int64_t)(c0 + b) * kBinChunkPts + (b < nb ? sb[b] : 0);
+          mx = max(mx, len[u]);
+        }
+        for (int q0 = lane; q0 < mx; q0 += 128) {
+          uint64_t en[8];
+#pragma unroll
+          for (int u = 0; u < 4; u++) {
+            en[2 * u] = q0 < len[u] ? (uint64_t)ch[at[u] + q0] : ~0ull;
+            en[2 * u + 1] = q0 + 64 < len[u] ? (uint64_t)ch[at[u] + q0 + 64] : ~0ull;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; u++)
+            if ((uint32_t)en[u] < lim) atomicMin(&ri[(uint32_t)en[u]], (uint32_t)(en[u] >> 32));
+        }
+      }
+      __syncthreads();     // every segment read before the next offsets overwrite them
     }
-    __syncthreads();
     for (int e = tid; e < TC * N; e += kBlock)
       if (ri[e] == 0x7f800000u) ri[e] = 0u;
   }

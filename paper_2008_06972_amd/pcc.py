@@ -116,7 +116,7 @@ EXPORTED = ("pc_stream_layout", "pc_workspace_size", "pc_ctx_create", "pc_ctx_de
             "pc_decode_batch_workspace_size", "pc_decode_batch", "pc_unpack_batch_workspace_size", "pc_unpack_batch",
             "pc_project_noalloc")
 PC_NET_PARAMS = 15636
-LAUNCH_KINDS = {0: "reset", 1: "count", 2: "offsets", 3: "scatter", 4: "key", 5: "pred", 6: "finish",
+LAUNCH_KINDS = {0: "reset", 1: "bin", 2: "offsets", 3: "scatter", 4: "key", 5: "pred", 6: "finish",
                 7: "keyimage", 8: "net"}
 
 

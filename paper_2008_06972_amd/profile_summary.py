@@ -12,8 +12,8 @@ batched encoder's kernels and of a plain device copy of COPY_BYTES bytes
 units to bytes, which is applied to every kernel.  The result is JSON keyed
 by launch kind (count, scatter, keyimage, net, key, pred, finish, ...) with
 the hash of the kernel sources it was taken on: bytes per pass of the batch
-graph for its kinds (a pass launches the binning kernels twice, for key and
-for predicted frames), per dispatch for the others.
+graph for its kinds (a pass launches binning twice, for key and for
+predicted frames), per dispatch for the others.
 """
 from __future__ import annotations
 
@@ -25,14 +25,14 @@ import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
-KINDS = (("k_batch_count", "count"), ("k_batch_scatter", "scatter"), ("k_batch_keyimage", "keyimage"),
+KINDS = (("k_batch_bin", "bin"), ("k_batch_count", "count"), ("k_batch_scatter", "scatter"), ("k_batch_keyimage", "keyimage"),
          ("k_net_", "net"), ("k_batch_key", "key"),
          ("k_batch_pred", "pred"), ("k_batch_finish", "finish"), ("k_batch_offsets", "offsets"),
          ("k_batch_reset", "reset"), ("k_pack_", "pack"), ("k_decode", "decode"))
 
 
 # launch kinds of the batch graph: their traffic is given per pass
-PASS_KINDS = ("count", "scatter", "keyimage", "net", "key", "pred", "finish", "offsets", "reset")
+PASS_KINDS = ("bin", "count", "scatter", "keyimage", "net", "key", "pred", "finish", "offsets", "reset")
 
 
 def kernel_source_hash() -> str:

@@ -89,11 +89,16 @@ struct StripSmem {
   __device__ uint32_t *cnt() const { return scratch; }
   __device__ uint64_t *cur() const { return reinterpret_cast<uint64_t *>(scratch); }
   __device__ int16_t *list(int q, int TC) const { return reinterpret_cast<int16_t *>(cur() + TC) + q * TC; }
+  // growth: the masks the run tests found (over cur) and the start whose
+  // plane found each (after the three lists)
+  __device__ uint64_t *mcache() const { return cur(); }
+  __device__ int16_t *mstart(int TC) const { return list(3, TC); }
 
-  // fits: cur and three lists; residuals: counts; the load of binned
-  // points: the chunk offsets it gathers
+  // fits: cur and three lists; growth: the mask cache over cur, the
+  // lists, the masks' start tiles after them; residuals: counts; the load
+  // of binned points: the chunk offsets it gathers
   __host__ __device__ static size_t scratch_bytes(int TC) {
-    size_t a = sizeof(uint32_t) * (size_t)TH * TC, b = sizeof(uint64_t) * (size_t)TC + 3 * sizeof(int16_t) * (size_t)TC;
+    size_t a = sizeof(uint32_t) * (size_t)TH * TC, b = sizeof(uint64_t) * (size_t)TC + 4 * sizeof(int16_t) * (size_t)TC;
     size_t m = a > b ? a : b;
     return m > kSegBytes ? m : kSegBytes;
   }
@@ -653,7 +658,7 @@ __device__ __forceinline__ uint64_t inliers_at(const StripSmem<TH, TW> &sm, int 
 // 64 / (TH * TW) tiles from tile t on (lane = pixel); returns how many more
 // tiles join.
 template <int TH, int TW, class Allowed>
-__device__ __forceinline__ int extend_beyond(const StripSmem<TH, TW> &sm, const EncParams &p, const Plane &P, int s, int t, int TC,
+__device__ __forceinline__ int extend_beyond(StripSmem<TH, TW> &sm, const EncParams &p, const Plane &P, int s, int t, int TC,
                              Allowed allowed) {
   constexpr int N = TH * TW, TPW = 64 / N;
   const int lane = strip_tid() & 63, w = lane / N, j = lane % N, i = j / TW, k = j % TW;
@@ -673,6 +678,10 @@ __device__ __forceinline__ int extend_beyond(const StripSmem<TH, TW> &sm, const 
 #pragma unroll
     for (int q = 0; q < TPW; q++)
       if (((E >> (q * N)) & 1ull) && f == q) f = q + 1;
+    if (j == 0 && w < f) {          // tiles that join the run: their masks
+      sm.mcache()[tt] = m;
+      sm.mstart(TC)[tt] = (int16_t)s;
+    }
     added += f;
     t += f;
     if (f < TPW) break;
@@ -697,6 +706,10 @@ __device__ __forceinline__ void reach_pass(StripSmem<TH, TW> &sm, const EncParam
     const uint64_t m = inliers(T, plane_of(s), p.eps, Red{});
     if (sub != 0 || __popcll(m) < need_of(p, sm.nv[t])) continue;
     sm.reach[s] = (uint8_t)d;
+    // levels run in order of d, so the farthest start that reaches t keeps
+    // its mask here: the run's own start for a tile of a run's first kReach
+    sm.mcache()[t] = m;
+    sm.mstart(TC)[t] = (int16_t)s;
     if (d < kReach) list_push<TH, TW>(sm, q ^ 1, TC, s);
   }
 }
@@ -725,8 +738,10 @@ __device__ __forceinline__ int grow_runs(StripSmem<TH, TW> &sm, const EncParams 
       list_push<TH, TW>(sm, 0, TC, tc);
     }
   }
-  for (int tc = tid; tc < TC; tc += kBlock)
+  for (int tc = tid; tc < TC; tc += kBlock) {
     if (member(tc)) sm.runof[tc] = -1;
+    sm.mstart(TC)[tc] = -1;
+  }
   __syncthreads();
   // reach, level by level
   int n = sm.misc[M_LIST];
@@ -754,7 +769,7 @@ __device__ __forceinline__ int grow_runs(StripSmem<TH, TW> &sm, const EncParams 
   // successor (its run may go on), so the chain is cut there: that run is
   // continued by extend_beyond and the marking restarts after it.
   {
-    int16_t *ja = reinterpret_cast<int16_t *>(sm.cur()), *jb = ja + TC;
+    int16_t *ja = sm.list(0, TC), *jb = ja + TC;     // the lists are free now; the mask cache is kept
     uint8_t *on = reinterpret_cast<uint8_t *>(jb + TC);
     __shared__ int wcnt[kBlock / 64];
     const int lane = tid & 63, wv = tid >> 6;
@@ -841,7 +856,8 @@ __device__ __forceinline__ int grow_runs(StripSmem<TH, TW> &sm, const EncParams 
     const int ri = sm.runof[tc];
     if (ri < 0) continue;
     const int s = sm.rs[ri];
-    sm.fmask[tc] = s == tc ? own_mask(tc) : inliers_at<TH, TW>(sm, tc, plane_of(s), p.eps);
+    sm.fmask[tc] = s == tc ? own_mask(tc)
+                           : (sm.mstart(TC)[tc] == s ? sm.mcache()[tc] : inliers_at<TH, TW>(sm, tc, plane_of(s), p.eps));
   }
   return *nr_out;
 }

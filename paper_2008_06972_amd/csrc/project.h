@@ -86,6 +86,25 @@ __device__ __forceinline__ int row_of(const SensorDev &s, const Tab &tab, float 
   return -1;
 }
 
+// Row from an estimate qa of q known to within mg: the v with
+// cut[v] > q >= cut[v + 1] when qa decides it (both cuts farther than mg
+// from qa after one step from the beam nearest the elevation), else -1.
+// The caller has checked cut[0] > q >= cut[H].
+template <class Tab>
+__device__ __forceinline__ int row_near(const SensorDev &s, const Tab &tab, float qa, float mg) {
+  const int H = s.H;
+  const float e = fabsf(qa) <= 1.0f ? atan_unit_as(qa)
+                                     : copysignf(1.57079632679f, qa) - atan_unit_as(__builtin_amdgcn_rcpf(qa));
+  int v = (int)fmaf(s.elev0 - e, s.inv_de, 0.5f);
+  v = min(max(v, 0), H - 1);
+  {
+    const float above = tab.c(v), below = tab.c(v + 1);
+    v += (below > qa ? 1 : 0) - (above <= qa ? 1 : 0);
+  }
+  const float above = tab.c(v), below = tab.c(v + 1);
+  return (above > qa + mg && below <= qa - mg) ? v : -1;
+}
+
 template <class Tab>
 __device__ __forceinline__ float edge_side(const Tab &tab, int u, float x, float y) {
   float t = tab.ey(u) * x;
@@ -105,16 +124,17 @@ __device__ __forceinline__ int column_of(const SensorDev &s, const Tab &tab, flo
   u = u >= W ? u - W : u;
   u = u >= W ? u - W : u;
   u = min(max(u, 0), W - 1);
-  // one branch-free step, then the walk for the rare rest
+  // one branch-free step; its check needs only the one edge the step did
+  // not already evaluate (stepping back: the new leading edge; forward:
+  // the new trailing edge)
   {
     const int un = (u + 1 == W) ? 0 : u + 1;
     const float lead = edge_side(tab, u, x, y), next = edge_side(tab, un, x, y);
-    u = lead > 0.0f ? ((u == 0) ? W - 1 : u - 1) : (next <= 0.0f ? un : u);
-  }
-  {
-    const int un = (u + 1 == W) ? 0 : u + 1;
-    const float lead = edge_side(tab, u, x, y), next = edge_side(tab, un, x, y);
-    if (!(lead > 0.0f) && !(next <= 0.0f)) return u;
+    const bool back = lead > 0.0f, fwd = !back && next <= 0.0f;
+    const int ub = (u == 0) ? W - 1 : u - 1, un2 = (un + 1 == W) ? 0 : un + 1;
+    const float other = edge_side(tab, back ? ub : un2, x, y);
+    u = back ? ub : (fwd ? un : u);
+    if (back ? !(other > 0.0f) : (fwd ? other > 0.0f : true)) return u;
   }
   for (int step = 0; step <= W + 2; step++) {
     const int un = (u + 1 == W) ? 0 : u + 1;
@@ -148,9 +168,23 @@ __device__ __forceinline__ int project_point(const SensorDev &s, const Tab &tab,
   r = sqrtf(fmaf(x, x, fmaf(y, y, zz2)));
   if (!isfinite(r) || r == 0.0f) return PROJ_NONFINITE;
   if (rho2 < 1e-12f) return PROJ_FOV;
-  const float q = z / sqrtf(rho2);
-  if (!(q < tab.c(0)) || q < tab.c(s.H)) return PROJ_FOV;
-  v = row_of(s, tab, q);
+  // The row depends on q = z / sqrt(rho2) (correctly rounded square root
+  // and division) only through comparisons with the cut tangents.  The
+  // estimate z * rsq(rho2) is within 3e-7 |q| of q (one-ulp reciprocal
+  // square root, two roundings on each side), so a cut farther than
+  // 1e-6 |q| from it compares the same way with q; only a point that close
+  // to a cut (or to the field of view's edges) computes q itself.
+  const float qa = z * __builtin_amdgcn_rsqf(rho2);
+  const float mg = fmaf(fabsf(qa), 1e-6f, 1e-30f);
+  const float top = tab.c(0), bot = tab.c(s.H);
+  if (qa - mg >= top || qa + mg < bot) return PROJ_FOV;
+  v = -1;
+  if (qa + mg < top && qa - mg >= bot) v = row_near(s, tab, qa, mg);
+  if (v < 0) {
+    const float q = z / sqrtf(rho2);
+    if (!(q < top) || q < bot) return PROJ_FOV;
+    v = row_of(s, tab, q);
+  }
   u = column_of(s, tab, x, y);
   return (v < 0 || u < 0) ? PROJ_FOV : PROJ_KEPT;
 }

@@ -562,6 +562,7 @@ __device__ __forceinline__ void temporal_pass(StripSmem<TH, TW> &sm, const EncPa
   const int tid = strip_tid(), sub = tid & (LANES - 1);
   const int16_t *L = sm.list(q, TC);
   uint64_t *cur = sm.cur();
+  float *tsum = reinterpret_cast<float *>(sm.fmask);     // final masks are not in use yet
   for (int e = tid / LANES; e < n; e += kBlock / LANES) {
     const int tc = L[e];
     TileRows<TH, TW> T = tile_at<TH, TW>(sm, tc);
@@ -569,8 +570,11 @@ __device__ __forceinline__ void temporal_pass(StripSmem<TH, TW> &sm, const EncPa
     T.i1 = T.i0 + TH / LANES;
     Plane P = unpack_plane(sm.plane[tc]);
     const uint64_t S = cur[tc];
-    P.c = temporal_offset(T, P, S, Red{});
-    const uint64_t S2 = inliers(T, P, p.eps, Red{});
+    // the first iteration sums over the valid pixels; later ones take the
+    // sum the previous test accumulated over the pixels it kept
+    P.c = it == 1 ? temporal_offset(T, P, S, Red{}) : tsum[tc] / (float)__popcll(S);
+    float next_sum;
+    const uint64_t S2 = inliers_offset_sum(T, P, p.eps, next_sum, Red{});
     if (sub != 0) continue;
     sm.iters[tc] = (uint8_t)it;
     sm.plane[tc] = pack_plane(P);
@@ -581,6 +585,7 @@ __device__ __forceinline__ void temporal_pass(StripSmem<TH, TW> &sm, const EncPa
     sm.omask[tc] = S2;
     if (S2 != S && it < p.max_iter) {
       cur[tc] = S2;
+      tsum[tc] = next_sum;
       list_push<TH, TW>(sm, q ^ 1, TC, tc);
     } else {
       sm.stat[tc] = __popcll(S2) >= need_of(p, sm.nv[tc]) ? 2 : 1;

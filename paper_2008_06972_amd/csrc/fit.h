@@ -361,6 +361,56 @@ __device__ __forceinline__ uint64_t inliers(const Tile &T, const Plane &P, float
   return ((uint64_t)red.bor((uint32_t)(m >> 32)) << 32) | red.bor((uint32_t)m);
 }
 
+// inliers() with, in the same pass, the sum of r (d_k + a d_k1 + b d_k2)
+// over the pixels it keeps (the offset sum of the next temporal iteration),
+// accumulated in pixel order exactly as temporal_offset does; a pixel kept
+// only after the correctly rounded recheck makes the sum be taken again.
+template <class Tile, class Red = LaneOne>
+__device__ __forceinline__ uint64_t inliers_offset_sum(const Tile &T, const Plane &P, float eps, float &sum_out,
+                                                       Red red = Red{}) {
+  const bool isx = P.k == 0, isz = P.k == 2;
+  uint32_t lo = 0, hi = 0, ulo = 0, uhi = 0;
+  float sum = 0.f;
+  T.each([&](int j, float r, const Dir &d) {
+    const float dk = isz ? d.z : (isx ? d.x : d.y);
+    const float dk1 = isx ? d.y : d.x;
+    const float dk2 = isz ? d.y : d.z;
+    const float den = fmaf(P.b, dk2, fmaf(P.a, dk1, dk));
+    const float t0 = P.c * __builtin_amdgcn_rcpf(den);
+    const float diff = fabsf(t0 - r);
+    const float margin = fmaf(fabsf(t0), 1e-6f, 1e-7f);
+    const bool valid = r > 0.0f;
+    const bool sure_in = valid & (diff < eps - margin) & (t0 > 0.0f);
+    const bool unsure = valid & !(diff < eps - margin) & !(diff > eps + margin);
+    sum = fmaf(r * (sure_in ? 1.0f : 0.0f), den, sum);
+    if (j < 32) {
+      lo |= (uint32_t)sure_in << (j & 31);
+      ulo |= (uint32_t)unsure << (j & 31);
+    } else {
+      hi |= (uint32_t)sure_in << (j & 31);
+      uhi |= (uint32_t)unsure << (j & 31);
+    }
+  });
+  uint64_t m = ((uint64_t)hi << 32) | lo, u = ((uint64_t)uhi << 32) | ulo;
+  uint32_t late = 0;
+  while (u) {
+    const int j = __ffsll((long long)u) - 1;
+    u &= u - 1;
+    const int i = j / Tile::TWc, k = j % Tile::TWc;
+    if (reproduces_exact(P.c, plane_den(P, T.dir_at(i, k)), T.at(j), eps)) {
+      m |= 1ull << j;
+      late = 1;
+    }
+  }
+  m = ((uint64_t)red.bor((uint32_t)(m >> 32)) << 32) | red.bor((uint32_t)m);
+  if (red.bor(late)) {
+    sum = 0.f;
+    T.each([&](int j, float r, const Dir &d) { sum = fmaf(r * bitw(m, j), plane_den(P, d), sum); });
+  }
+  sum_out = red.sum(sum);
+  return m;
+}
+
 // FP64 least squares on the exact products r*d: two-pass centring, Jacobi.
 // Rare path (near-degenerate scatter).
 template <class Tile>

@@ -467,3 +467,40 @@ def test_decoded_points_back_in_frame_coordinates(orc):
     # a rotation keeps lengths: |q| for q = R^T (p - T) equals |p - T| (R is
     # orthogonal to the FP32 rounding of its entries, about 1e-7)
     assert np.allclose(np.linalg.norm(Pf[v], axis=1), np.linalg.norm(Pk[v] - M[:3, 3], axis=1), rtol=1e-6, atol=0)
+
+
+# ------------------------------------------------------ decision margins
+@pytest.mark.parametrize("normal,c", [((1.0, 0.0, 0.0), 10.0), ((0.2, 0.98, 0.0), 5.0)])
+def test_margin_diagnostics_on_a_noiseless_wall(orc, normal, c):
+    """The per-tile margins are diagnostics of how close the keep-or-drop
+    test |t - r| <= eps came to flipping.  On a noiseless plane every point is
+    reproduced with |t - r| at the level of FP32 rounding, so over a fully
+    visible tile: margin_abs = eps (to that rounding), margin_rel = eps /
+    max(r, 1) at the tile's farthest point, and margin_cond = the smallest
+    eps |n . d| / max(r, 1) over the tile's pixels, n . d being the cosine
+    between the pixel's ray and the wall's unit normal (face-on and oblique
+    walls)."""
+    sensor = synth.Sensor(4, 64, 3.0, -3.0, az0=0.4)
+    tb = orc.Tables.of(sensor)
+    n = np.asarray(normal, float)
+    n /= np.linalg.norm(n)
+    d = tb.directions().astype(np.float64)
+    nd = d @ n
+    img = _plane_image(sensor, tb, [(0, sensor.W, n, c)])
+    ok = np.all((nd > 0.1) & (img > 0) & (img < 60.0), axis=0)
+    img[:, ~ok] = 0
+    prm = orc.Params(eps=0.01, th=4, tw=4)
+    f = orc.encode_key(img, tb, prm)
+    r = img.astype(np.float64)
+    checked = 0
+    for t in range(sensor.W // 4):
+        cols = slice(4 * t, 4 * t + 4)
+        if not np.all(ok[cols]) or f.cls[t] != orc.CLS_SPATIAL:
+            continue
+        checked += 1
+        rt, ct = r[:, cols], np.abs(nd[:, cols])
+        assert abs(f.margin_abs[t] - prm.eps) <= 1e-4 * prm.eps * max(1.0, rt.max())
+        assert f.margin_abs[t] <= prm.eps
+        assert f.margin_rel[t] == pytest.approx(prm.eps / np.maximum(rt, 1).max(), rel=2e-3)
+        assert f.margin_cond[t] == pytest.approx((prm.eps * ct / np.maximum(rt, 1)).min(), rel=2e-3)
+    assert checked >= 3

@@ -9,11 +9,13 @@
 // products and sums are FP32.
 //
 // Forward: each convolution is an implicit GEMM on
-// v_mfma_f32_16x16x16_bf16: M = 16 output pixels per wavefront, N = the
-// output channels in blocks of 16, K = (ky, kx, input channel) with the
-// channel fastest, so a lane's four K values are four consecutive channels of
-// one input pixel (one 8-byte load from the NHWC activations).  Weights are
-// packed once per call into [out channel][K] bf16 rows padded to 16.
+// v_mfma_f32_16x16x16_bf16, taken transposed: A = the weights (16 output
+// channels per block), B = 16 output pixels per wavefront, K = (ky, kx,
+// input channel) with the channel fastest, so a lane's four K values are
+// four consecutive channels of one input pixel (one 8-byte load from the
+// NHWC activations) and its four results are four consecutive output
+// channels of one pixel (one 8-byte store).  Weights are packed once per
+// call into [out channel][K] bf16 rows padded to 16.
 // Backward (training only) runs on the vector ALUs in FP32.
 //
 // Parameters: one FP32 vector, per layer W[out][in][ky][kx] then b[out].
@@ -93,6 +95,30 @@ __global__ void k_net_input(NetInputJob job, const NetInputJob *__restrict__ job
   o[3] = bf16_rne((r * se) * 0.0625f);
 }
 
+// Epilogue of a convolution whose product was taken transposed (weights as
+// the A operand, pixels as B: each element is the same dot product of the
+// same bf16 values): the lane holds channels nb*16 + 4g .. + 3 of one pixel.
+// Hidden layers store bf16(ReLU(. + bias)) as one 8-byte word per nb, the
+// last layer (four channels) its FP32 values as one 16-byte word.
+template <int CO, int NB, bool LAST>
+__device__ __forceinline__ void store_channels(void *out, size_t pix, const f32x4 (&acc)[NB], const float (&bv)[NB][4],
+                                               int g) {
+  if (LAST) {
+    if (g == 0)
+      *reinterpret_cast<float4 *>(static_cast<float *>(out) + pix * 4) =
+          make_float4(acc[0][0] + bv[0][0], acc[0][1] + bv[0][1], acc[0][2] + bv[0][2], acc[0][3] + bv[0][3]);
+  } else {
+#pragma unroll
+    for (int nb = 0; nb < NB; nb++) {
+      if (nb * 16 + 4 * g >= CO) continue;
+      bf16x4 v;
+#pragma unroll
+      for (int i = 0; i < 4; i++) v[i] = (short)bf16_rne(fmaxf(acc[nb][i] + bv[nb][i], 0.0f));
+      *reinterpret_cast<bf16x4 *>(static_cast<uint16_t *>(out) + pix * CO + nb * 16 + 4 * g) = v;
+    }
+  }
+}
+
 // One wavefront: kMT groups of 16 consecutive output pixels x all output
 // channels.  The weights (B operands) are loaded once per wavefront and
 // reused for every pixel group; each group's input gathers (A operands) are
@@ -114,9 +140,11 @@ __global__ void __launch_bounds__(256) k_net_conv(ConvJob job, const ConvJob *__
 #pragma unroll
     for (int nb = 0; nb < NB; nb++)
       b[s][nb] = *reinterpret_cast<const bf16x4 *>(wpk + (size_t)(nb * 16 + m) * KPAD + 16 * s + 4 * g);
-  float bv[NB];
+  float bv[NB][4];      // bias of the four channels a lane's results hold
 #pragma unroll
-  for (int nb = 0; nb < NB; nb++) bv[nb] = nb * 16 + m < CO ? bias[nb * 16 + m] : 0.0f;
+  for (int nb = 0; nb < NB; nb++)
+#pragma unroll
+    for (int i = 0; i < 4; i++) bv[nb][i] = nb * 16 + 4 * g + i < CO ? bias[nb * 16 + 4 * g + i] : 0.0f;
   for (int t = 0; t < kMT; t++) {
     const int p0 = pw + 16 * t;
     if (p0 >= npx) break;
@@ -138,21 +166,10 @@ __global__ void __launch_bounds__(256) k_net_conv(ConvJob job, const ConvJob *__
 #pragma unroll
     for (int s = 0; s < KSTEPS; s++)
 #pragma unroll
-      for (int nb = 0; nb < NB; nb++) acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[s], b[s][nb], acc[nb], 0, 0, 0);
-    // lane holds D[pixel 4g + i][channel nb*16 + m]
-#pragma unroll
-    for (int nb = 0; nb < NB; nb++) {
-      const int ch = nb * 16 + m;
-      if (ch >= CO) continue;
-#pragma unroll
-      for (int i = 0; i < 4; i++) {
-        const int pix = p0 + 4 * g + i;
-        if (pix >= npx) continue;
-        const float v = acc[nb][i] + bv[nb];
-        if (LAST) static_cast<float *>(J.out)[(size_t)pix * 4 + ch] = v;
-        else static_cast<uint16_t *>(J.out)[(size_t)pix * CO + ch] = bf16_rne(fmaxf(v, 0.0f));
-      }
-    }
+      for (int nb = 0; nb < NB; nb++) acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b[s][nb], a[s], acc[nb], 0, 0, 0);
+    // lane holds D[channel nb*16 + 4g + i][pixel p]: four consecutive
+    // channels of one pixel, stored together
+    if (p < npx) store_channels<CO, NB, LAST>(J.out, (size_t)p, acc, bv, g);
   }
 }
 
@@ -231,9 +248,11 @@ __global__ void __launch_bounds__(256) k_net_conv_lds(ConvJob job, const ConvJob
 #pragma unroll
     for (int nb = 0; nb < NB; nb++)
       b[s][nb] = *reinterpret_cast<const bf16x4 *>(wpk + (size_t)(nb * 16 + m) * KPAD + 16 * s + 4 * g);
-  float bv[NB];
+  float bv[NB][4];      // bias of the four channels a lane's results hold
 #pragma unroll
-  for (int nb = 0; nb < NB; nb++) bv[nb] = nb * 16 + m < CO ? bias[nb * 16 + m] : 0.0f;
+  for (int nb = 0; nb < NB; nb++)
+#pragma unroll
+    for (int i = 0; i < 4; i++) bv[nb][i] = nb * 16 + 4 * g + i < CO ? bias[nb * 16 + 4 * g + i] : 0.0f;
   __syncthreads();
   for (int t = wave; t < R * (BW / 16); t += 4) {
     const int r = t / (BW / 16), tc = t - r * (BW / 16), oy = oy0 + r;
@@ -252,66 +271,10 @@ __global__ void __launch_bounds__(256) k_net_conv_lds(ConvJob job, const ConvJob
 #pragma unroll
     for (int s = 0; s < KSTEPS; s++)
 #pragma unroll
-      for (int nb = 0; nb < NB; nb++) acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[s], b[s][nb], acc[nb], 0, 0, 0);
-    // lane holds D[pixel 4g + i][channel nb*16 + m]
-#pragma unroll
-    for (int nb = 0; nb < NB; nb++) {
-      const int ch = nb * 16 + m;
-      if (ch >= CO) continue;
-#pragma unroll
-      for (int i = 0; i < 4; i++) {
-        const int ox = ox0 + 16 * tc + 4 * g + i;
-        if (ox >= J.Wo) continue;
-        const size_t pix = (size_t)oy * J.Wo + ox;
-        const float v = acc[nb][i] + bv[nb];
-        if (LAST) static_cast<float *>(J.out)[pix * 4 + ch] = v;
-        else static_cast<uint16_t *>(J.out)[pix * CO + ch] = bf16_rne(fmaxf(v, 0.0f));
-      }
-    }
-  }
-}
-
-// The first layer straight from the range image (batched forward only):
-// a lane's four K values are the four input channels of one pixel, computed
-// as k_net_input computes them, so the result equals input + first layer.
-__global__ void __launch_bounds__(256) k_net_conv1_range(const NetInputJob *__restrict__ in_jobs,
-                                                         const ConvJob *__restrict__ jobs,
-                                                         const uint16_t *__restrict__ wpk, const float *__restrict__ bias) {
-  constexpr int CI = 4, CO = 16, KPAD = net_kpad(CI), KSTEPS = KPAD / 16;
-  const NetInputJob I = in_jobs[blockIdx.y];
-  const ConvJob J = jobs[blockIdx.y];
-  const int lane = threadIdx.x & 63, g = lane >> 4, m = lane & 15;
-  const int npx = J.Ho * J.Wo;
-  const int p0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
-  if (p0 >= npx) return;
-  const int p = p0 + m;
-  const int oy = p / J.Wo, ox = p - oy * J.Wo;
-  bf16x4 a[KSTEPS], b[KSTEPS];
-#pragma unroll
-  for (int s = 0; s < KSTEPS; s++) {
-    const int pos = (16 * s + 4 * g) / CI;
-    const int iy = oy * 2 - 1 + pos / 3, ix = ox * 2 - 1 + pos % 3;
-    const bool ok = pos < 9 && p < npx && iy >= 0 && iy < I.H && ix >= 0 && ix < I.W;
-    const int cy = ok ? iy : 0, cx = ok ? ix : 0;
-    const float r = I.range[(size_t)cy * I.W + cx];
-    const float ce = I.ce[cy], se = I.se[cy], ca = I.ca[cx], sa = I.sa[cx];
-    const float dx = ce * ca, dy = ce * sa;
-    bf16x4 v;
-    v[0] = (short)bf16_rne(r * 0.0625f);
-    v[1] = (short)bf16_rne((r * dx) * 0.0625f);
-    v[2] = (short)bf16_rne((r * dy) * 0.0625f);
-    v[3] = (short)bf16_rne((r * se) * 0.0625f);
-    a[s] = ok ? v : bf16x4{0, 0, 0, 0};
-    b[s] = *reinterpret_cast<const bf16x4 *>(wpk + (size_t)m * KPAD + 16 * s + 4 * g);
-  }
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int s = 0; s < KSTEPS; s++) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[s], b[s], acc, 0, 0, 0);
-  const float bv = bias[m];
-#pragma unroll
-  for (int i = 0; i < 4; i++) {
-    const int pix = p0 + 4 * g + i;
-    if (pix < npx) static_cast<uint16_t *>(J.out)[(size_t)pix * CO + m] = bf16_rne(fmaxf(acc[i] + bv, 0.0f));
+      for (int nb = 0; nb < NB; nb++) acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b[s][nb], a[s], acc[nb], 0, 0, 0);
+    // lane holds D[channel nb*16 + 4g + i][pixel pl]
+    const int ox = ox0 + pl;
+    if (ox < J.Wo) store_channels<CO, NB, LAST>(J.out, (size_t)oy * J.Wo + ox, acc, bv, g);
   }
 }
 

@@ -16,7 +16,9 @@
 // NHWC activations) and its four results are four consecutive output
 // channels of one pixel (one 8-byte store).  Weights are packed once per
 // call into [out channel][K] bf16 rows padded to 16.
-// Backward (training only) runs on the vector ALUs in FP32.
+// Backward (training only) runs on the vector ALUs in FP32 with fixed-order
+// reductions (no floating-point atomics): a gradient is the same bits on
+// every run.
 //
 // Parameters: one FP32 vector, per layer W[out][in][ky][kx] then b[out].
 #include "seednet.h"
@@ -283,8 +285,23 @@ __global__ void __launch_bounds__(256) k_net_conv_lds(ConvJob job, const ConvJob
 struct NetWork {
   uint16_t *wpk, *a0, *a1, *a2, *a3;
   float *dz1, *dz2, *dz3;
+  float *part;            // per-chunk weight gradient sums of the layer in progress
   size_t bytes;
 };
+
+constexpr int kGradChunk = 4096;     // output pixels per weight-gradient block
+
+// Largest per-chunk partial-sum table of the four layers (floats).
+static size_t net_grad_part_elems(int H, int W) {
+  const int npx[4] = {(H / 2) * (W / 2), (H / 4) * (W / 4), (H / 4) * (W / 8), (H / 4) * (W / 8)};
+  size_t most = 0;
+  for (int l = 0; l < kNetLayers; l++) {
+    const NetLayerDesc d = net_layer(l);
+    const size_t n = (size_t)((npx[l] + kGradChunk - 1) / kGradChunk) * (d.co * d.ci * 9 + d.co);
+    most = n > most ? n : most;
+  }
+  return most;
+}
 
 static size_t a256n(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -300,6 +317,7 @@ static NetWork net_work(char *base, int H, int W) {
   w.dz1 = (float *)take(4 * 16 * (size_t)(H / 2) * (W / 2));
   w.dz2 = (float *)take(4 * 32 * (size_t)(H / 4) * (W / 4));
   w.dz3 = (float *)take(4 * 32 * (size_t)(H / 4) * (W / 8));
+  w.part = (float *)take(4 * net_grad_part_elems(H, W));
   w.bytes = at;
   return w;
 }
@@ -392,12 +410,14 @@ hipError_t net_forward(const float *params, const float *range, const SensorDev 
 
 // ----------------------------------------------------------------- backward
 // Weight and bias gradients of one layer: a block per (out channel, input
-// channel, pixel chunk); nine partial sums per thread, block reduction, one
-// atomic per weight and block.
+// channel, pixel chunk); nine partial sums per thread, block reduction in a
+// fixed tree, the block's sums written to its chunk's row of part
+// ([chunk][CO * CI * 9 weights, then CO biases]); k_net_grad_sum adds the
+// rows in chunk order, so the gradient does not depend on scheduling.
 template <int CI, int CO, int SY, int SX>
 __global__ void __launch_bounds__(256) k_net_wgrad(const uint16_t *__restrict__ ain, int Hi, int Wi,
-                                                   const float *__restrict__ dz, int Ho, int Wo, float *__restrict__ gW,
-                                                   float *__restrict__ gb, int chunk) {
+                                                   const float *__restrict__ dz, int Ho, int Wo, float *__restrict__ part,
+                                                   int chunk) {
   const int co = blockIdx.x / CI, ci = blockIdx.x % CI;
   const int p_begin = blockIdx.y * chunk, p_end = min(Ho * Wo, p_begin + chunk);
   float acc[10];
@@ -423,8 +443,21 @@ __global__ void __launch_bounds__(256) k_net_wgrad(const uint16_t *__restrict__ 
       for (int q = 0; q < 10; q++) red[q][threadIdx.x] += red[q][threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x < 9) atomicAdd(&gW[(co * CI + ci) * 9 + threadIdx.x], red[threadIdx.x][0]);
-  if (threadIdx.x == 9 && ci == 0) atomicAdd(&gb[co], red[9][0]);
+  float *row = part + (size_t)blockIdx.y * (CO * CI * 9 + CO);
+  if (threadIdx.x < 9) row[(co * CI + ci) * 9 + threadIdx.x] = red[threadIdx.x][0];
+  if (threadIdx.x == 9 && ci == 0) row[CO * CI * 9 + co] = red[9][0];
+}
+
+// grad[e] += sum over chunks c = 0, 1, ... of part[c][e] for the nw weight
+// and nb bias gradients of one layer (gW, gb).
+__global__ void __launch_bounds__(256) k_net_grad_sum(const float *__restrict__ part, int nchunk, int nw, int nb,
+                                                      float *__restrict__ gW, float *__restrict__ gb) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nw + nb) return;
+  float s = 0.0f;
+  for (int c = 0; c < nchunk; c++) s += part[(size_t)c * (nw + nb) + e];
+  if (e < nw) gW[e] += s;
+  else gb[e - nw] += s;
 }
 
 // Gradient of a layer's input through the convolution (bfloat16 weights)
@@ -452,40 +485,35 @@ __global__ void __launch_bounds__(256) k_net_dgrad(const uint16_t *__restrict__ 
   dzin[e] = s;
 }
 
+// Weight and bias gradients of layer l (its output grid npx pixels) from its
+// input activations and output gradient, added to grad in a fixed order.
+template <int CI, int CO, int SY, int SX>
+static void layer_wgrad(int l, const uint16_t *ain, int Hi, int Wi, const float *dz, int Ho, int Wo, float *part,
+                        float *grad, hipStream_t st) {
+  const NetLayerDesc d = net_layer(l);
+  const int nchunk = (Ho * Wo + kGradChunk - 1) / kGradChunk, nw = CO * CI * 9;
+  hipLaunchKernelGGL((k_net_wgrad<CI, CO, SY, SX>), dim3(CO * CI, nchunk), dim3(256), 0, st, ain, Hi, Wi, dz, Ho, Wo,
+                     part, kGradChunk);
+  hipLaunchKernelGGL(k_net_grad_sum, dim3((nw + CO + 255) / 256), dim3(256), 0, st, (const float *)part, nchunk, nw,
+                     CO, grad + d.woff, grad + d.boff);
+}
+
 hipError_t net_backward(const float *params, const SensorDev &s, char *work, const float *dseed, float *grad,
                         hipStream_t st) {
   const int H = s.H, W = s.W;
   NetWork w = net_work(work, H, W);
   const int H1 = H / 2, W1 = W / 2, H2 = H / 4, W2 = W / 4, H3 = H / 4, W3 = W / 8;
-  auto chunks = [](int npx, int chunk) { return (npx + chunk - 1) / chunk; };
-  const int C = 4096;
   // layer 4: dz = dseed
-  {
-    NetLayerDesc d = net_layer(3);
-    hipLaunchKernelGGL((k_net_wgrad<32, 4, 1, 1>), dim3(4 * 32, chunks(H3 * W3, C)), dim3(256), 0, st, w.a3, H3, W3,
-                       dseed, H3, W3, grad + d.woff, grad + d.boff, C);
-    hipLaunchKernelGGL((k_net_dgrad<32, 4, 1, 1>), dim3((H3 * W3 * 32 + 255) / 256), dim3(256), 0, st,
-                       w.wpk + d.poff, dseed, H3, W3, w.a3, H3, W3, w.dz3);
-  }
-  {
-    NetLayerDesc d = net_layer(2);
-    hipLaunchKernelGGL((k_net_wgrad<32, 32, 1, 2>), dim3(32 * 32, chunks(H3 * W3, C)), dim3(256), 0, st, w.a2, H2, W2,
-                       w.dz3, H3, W3, grad + d.woff, grad + d.boff, C);
-    hipLaunchKernelGGL((k_net_dgrad<32, 32, 1, 2>), dim3((H2 * W2 * 32 + 255) / 256), dim3(256), 0, st,
-                       w.wpk + d.poff, w.dz3, H3, W3, w.a2, H2, W2, w.dz2);
-  }
-  {
-    NetLayerDesc d = net_layer(1);
-    hipLaunchKernelGGL((k_net_wgrad<16, 32, 2, 2>), dim3(32 * 16, chunks(H2 * W2, C)), dim3(256), 0, st, w.a1, H1, W1,
-                       w.dz2, H2, W2, grad + d.woff, grad + d.boff, C);
-    hipLaunchKernelGGL((k_net_dgrad<16, 32, 2, 2>), dim3((H1 * W1 * 16 + 255) / 256), dim3(256), 0, st,
-                       w.wpk + d.poff, w.dz2, H2, W2, w.a1, H1, W1, w.dz1);
-  }
-  {
-    NetLayerDesc d = net_layer(0);
-    hipLaunchKernelGGL((k_net_wgrad<4, 16, 2, 2>), dim3(16 * 4, chunks(H1 * W1, C)), dim3(256), 0, st, w.a0, H, W,
-                       w.dz1, H1, W1, grad + d.woff, grad + d.boff, C);
-  }
+  layer_wgrad<32, 4, 1, 1>(3, w.a3, H3, W3, dseed, H3, W3, w.part, grad, st);
+  hipLaunchKernelGGL((k_net_dgrad<32, 4, 1, 1>), dim3((H3 * W3 * 32 + 255) / 256), dim3(256), 0, st,
+                     w.wpk + net_layer(3).poff, dseed, H3, W3, w.a3, H3, W3, w.dz3);
+  layer_wgrad<32, 32, 1, 2>(2, w.a2, H2, W2, w.dz3, H3, W3, w.part, grad, st);
+  hipLaunchKernelGGL((k_net_dgrad<32, 32, 1, 2>), dim3((H2 * W2 * 32 + 255) / 256), dim3(256), 0, st,
+                     w.wpk + net_layer(2).poff, w.dz3, H3, W3, w.a2, H2, W2, w.dz2);
+  layer_wgrad<16, 32, 2, 2>(1, w.a1, H1, W1, w.dz2, H2, W2, w.part, grad, st);
+  hipLaunchKernelGGL((k_net_dgrad<16, 32, 2, 2>), dim3((H1 * W1 * 16 + 255) / 256), dim3(256), 0, st,
+                     w.wpk + net_layer(1).poff, w.dz2, H2, W2, w.a1, H1, W1, w.dz1);
+  layer_wgrad<4, 16, 2, 2>(0, w.a0, H, W, w.dz1, H1, W1, w.part, grad, st);
   return hipGetLastError();
 }
 

@@ -109,6 +109,14 @@ def test_net_backward_matches_oracle(frame):
             say("layer", li + 1, name, "cos", cos, "rel", rel)
             assert cos >= 0.999 and rel <= 2e-2, (li, name, cos, rel)
             at += n
+    # the reductions have a fixed order: a second backward pass adds the
+    # same bits again (grad starts from the first result: 2 g exactly)
+    pcc.pc_net_backward(frame["ctx"].h, pt, frame["S"], work, torch.from_numpy(dseed).to(DEV), grad)
+    again = torch.zeros_like(grad)
+    pcc.pc_net_backward(frame["ctx"].h, pt, frame["S"], work, torch.from_numpy(dseed).to(DEV), again)
+    torch.cuda.synchronize()
+    assert np.array_equal(again.cpu().numpy(), g)
+    assert np.array_equal(grad.cpu().numpy(), 2 * g)
 
 
 def test_net_loss_and_adam_match_oracle(frame):

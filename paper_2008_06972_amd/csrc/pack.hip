@@ -43,6 +43,7 @@ constexpr int kMaxSub = 8192;              // decode subsequences per stream
 constexpr int kMinSubBits = 256;
 constexpr int kRunLds = 32768;             // run tables up to this size are parsed from LDS
 constexpr int kPayLds = 49152;             // stream payloads up to this size are decoded from LDS
+constexpr int kMaxRec = 4096;              // run records a frame's table is decoded in parallel up to
 
 struct PackPlan {
   uint32_t hist[4][256];
@@ -940,89 +941,228 @@ __device__ __forceinline__ void unpack_frame(UnpackPlan *up, const StreamPtrs &s
     f.run_of[t] = -1;
     f.mask[t] = 0;
   }
-  // runs of each tile row, in stream order (one thread: variable-length
-  // fields leave no index); a run table that fits is staged in LDS first
+  // Runs of each tile row, in stream order.  The table has no index
+  // (variable-length fields), so one thread first walks it to find where
+  // each tile row starts, reading only the bytes that give a record's
+  // length (the lead bytes of its two varints: a temporal record is gap,
+  // len and one FP32 value, a spatial one gap, len, an axis byte and three
+  // FP32 values); then one thread per tile row decodes its records.
+  // Counts, gaps and lengths are at most TC, so their varints take one or
+  // two bytes (a longer one is malformed).  A table that fits is staged in
+  // LDS first.
   __shared__ __align__(16) uint8_t runbuf[kRunLds];
+  __shared__ uint32_t rowstart[1025];
+  __shared__ uint32_t recp[kMaxRec], recid[kMaxRec];   // start and (spatial << 31 | row << 13 | k) of every record
+  __shared__ int nsr_s, npr_s, nrec;
   const uint64_t nrun = up->nbytes[S_RUN];
   const bool staged = nrun <= (uint64_t)kRunLds;
   if (staged)
     for (uint32_t i = tid; i < (uint32_t)nrun; i += kUnpackBlock) runbuf[i] = sp.p[S_RUN][i];
   __syncthreads();
-  if (tid == 0) {
-    const uint8_t *R = staged ? (const uint8_t *)runbuf : sp.p[S_RUN];
-    const uint64_t n = nrun;
-    uint64_t p = 0;
-    uint32_t bad = 0;
-    auto byte = [&]() -> uint32_t {
-      if (p >= n) {
-        bad = 1;
-        return 0u;
-      }
-      return R[p++];
+  // byte q of the table, zero past its end: from LDS when staged (a
+  // table larger than the LDS copy is only read from device memory), with
+  // typed pointers so that each path is a plain LDS or global load
+  typedef const __attribute__((address_space(3))) uint8_t lds_u8;
+  typedef const __attribute__((address_space(1))) uint8_t glb_u8;
+  const lds_u8 *RL = (lds_u8 *)runbuf;
+  const glb_u8 *RG = (glb_u8 *)sp.p[S_RUN];
+  const uint32_t n = (uint32_t)nrun;
+  auto rbyte = [&](uint32_t q) -> uint32_t {
+    const uint32_t v = staged ? (uint32_t)RL[min(q, (uint32_t)kRunLds - 1u)] : (uint32_t)RG[min(q, n - 1u)];
+    return q < n ? v : 0u;
+  };
+  if (nrun > 0xFFFFFFF0ull && tid == 0) err |= 4u;
+  if (tid < 64) {
+    // the walk, by wavefront 0: lane l holds byte wb + l of a 64-byte
+    // window and the length of the two varints that would start there
+    // (0 when one is longer than two bytes); a record then costs one
+    // readlane at the wave-uniform offset p - wb
+    const int lane = tid;
+    uint32_t wb = 0, b0 = 0, b1 = 0, lead = 0;
+    auto load = [&](uint32_t at) {
+      wb = at;
+      const uint32_t q = at + lane;
+      b0 = rbyte(q);
+      b1 = rbyte(q + 1);
+      const uint32_t b2 = rbyte(q + 2), b3 = rbyte(q + 3);
+      const int lg = (b0 & 128u) ? 2 : 1;
+      const uint32_t l0 = lg == 1 ? b1 : b2, l1 = lg == 1 ? b2 : b3;
+      const int ll = (l0 & 128u) ? 2 : 1;
+      lead = ((lg == 2 && (b1 & 128u)) || (ll == 2 && (l1 & 128u))) ? 0u : (uint32_t)(lg + ll);
     };
-    auto varint = [&]() -> uint32_t {
-      uint32_t v = 0;
-      for (int sh = 0; sh < 35; sh += 7) {
-        const uint32_t b = byte();
-        v |= (b & 127u) << sh;
-        if (!(b & 128u)) return v;
-      }
-      bad = 1;
-      return v;
+    auto at = [&](uint32_t v, uint32_t q) -> uint32_t {     // lane q - wb's v (q uniform, inside the window)
+      return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)(q - wb));
     };
-    auto f32 = [&]() -> float {
-      uint32_t u = byte();
-      u |= byte() << 8;
-      u |= byte() << 16;
-      u |= byte() << 24;
-      return __uint_as_float(u);
-    };
-    int nsr = 0, npr = 0;
+    load(0);
+    uint32_t p = 0, bad = 0, nr = 0;
+    if (lane == 0) nsr_s = npr_s = 0;
     for (int tr = 0; tr < TR && !bad; tr++) {
-      int np = 0;
-      if (kind) {
-        np = (int)varint();
-        if (np > TC) bad = 1;
-        int prev = 0;
-        for (int k = 0; k < np && !bad; k++) {
-          const uint32_t gap = varint(), len = varint();
-          const float c = f32();
-          if (gap > (uint32_t)TC || len < 1 || len > (uint32_t)TC || prev + (int)gap + (int)len > TC) {
-            bad = 1;
-            break;
+      if (lane == 0) rowstart[tr] = p;
+      for (int sec = kind ? 0 : 1; sec < 2 && !bad; sec++) {      // temporal runs, then spatial
+        if (p - wb >= 64) load(p);
+        const uint32_t c0 = at(b0, p), c1 = at(b1, p);
+        const uint32_t cnt = (c0 & 128u) ? ((c0 & 127u) | (c1 << 7)) : c0;
+        if (((c0 & 128u) && (c1 & 128u)) || cnt > (uint32_t)TC) bad = 1;
+        p += (c0 & 128u) ? 2 : 1;
+        const uint32_t fixed = sec == 0 ? 4 : 13;
+        for (uint32_t k = 0; k < cnt && !bad; k++) {
+          if (p - wb >= 64) load(p);
+          const uint32_t L = at(lead, p);
+          if (!L) bad = 1;
+          if (lane == 0 && nr < kMaxRec) {
+            recp[nr] = p;
+            recid[nr] = ((uint32_t)sec << 31) | ((uint32_t)tr << 13) | k;
           }
-          const int s = prev + (int)gap;
-          f.pruns[(int64_t)tr * TC + k] = pc_prun{s, (int)len, -1, c};      // key slot filled below
-          prev = s + (int)len;
+          nr++;
+          p += L + fixed;
+          if (p > n) bad = 1;
         }
+        if (lane == 0) (sec ? nsr_s : npr_s) += (int)cnt;
+        if (lane == 0) f.nruns[sec ? tr : TR + tr] = (int32_t)cnt;
       }
-      f.nruns[TR + tr] = np;
-      npr += np;
-      const int ns = (int)varint();
-      if (ns > TC) bad = 1;
+      if (!kind && lane == 0) f.nruns[TR + tr] = 0;
+    }
+    if (lane == 0) {
+      rowstart[TR] = p;
+      nrec = (int)nr;
+      if (bad || p != n) err |= 4u;
+    }
+  }
+  __syncthreads();
+  if (!err && nrec <= kMaxRec) {
+    // every record by its own thread: the fields follow the two varints at
+    // offset 2, 3 or 4 and are taken by selects on that offset; runs must
+    // lie inside the row in order (the previous record of the row gives
+    // where the previous run ended)
+    for (int e = tid; e < nrec; e += kUnpackBlock) {
+      const uint32_t q = recp[e], id = recid[e];
+      const int sp_ = (int)(id >> 31), tr = (int)((id >> 13) & 1023u), k = (int)(id & 8191u);
+      uint32_t b[17];
+#pragma unroll
+      for (int j = 0; j < 17; j++) b[j] = rbyte(q + j);
+      const bool g2 = (b[0] & 128u) != 0;
+      const uint32_t gap = g2 ? ((b[0] & 127u) | (b[1] << 7)) : b[0];
+      const uint32_t l0 = g2 ? b[2] : b[1], l1 = g2 ? b[3] : b[2];
+      const bool l2 = (l0 & 128u) != 0;
+      const uint32_t len = l2 ? ((l0 & 127u) | (l1 << 7)) : l0;
+      const int o = (g2 ? 2 : 1) + (l2 ? 2 : 1);
+      auto field = [&](int j) -> uint32_t { return o == 2 ? b[2 + j] : (o == 3 ? b[3 + j] : b[4 + j]); };
+      auto u32f = [&](int j) -> uint32_t {
+        return field(j) | (field(j + 1) << 8) | (field(j + 2) << 16) | (field(j + 3) << 24);
+      };
+      if (gap > (uint32_t)TC || len < 1 || len > (uint32_t)TC) atomicOr(&err, 4u);
+      if (sp_) {
+        const uint32_t axis = field(0);
+        if (axis > 2) atomicOr(&err, 4u);
+        f.sruns[(int64_t)tr * TC + k] = pc_run{(int)gap, (int)len, (int)axis, __uint_as_float(u32f(1)),
+                                             __uint_as_float(u32f(5)), __uint_as_float(u32f(9))};
+      } else {
+        f.pruns[(int64_t)tr * TC + k] = pc_prun{(int)gap, (int)len, -1, __uint_as_float(u32f(0))};   // key slot filled below
+      }
+    }
+    __syncthreads();
+    // gaps to starts, a row and kind per thread (runs in order, inside the row)
+    for (int e = tid; e < 2 * TR && !err; e += kUnpackBlock) {
+      const int tr = e >> 1, sp_ = e & 1;
+      const int cnt = f.nruns[sp_ ? tr : TR + tr];
       int prev = 0;
-      for (int k = 0; k < ns && !bad; k++) {
-        const uint32_t gap = varint(), len = varint(), axis = byte();
-        const float a = f32(), b = f32(), c = f32();
-        if (gap > (uint32_t)TC || len < 1 || len > (uint32_t)TC || prev + (int)gap + (int)len > TC || axis > 2) {
+      for (int k = 0; k < cnt; k++) {
+        const int64_t slot = (int64_t)tr * TC + k;
+        const int gap = sp_ ? f.sruns[slot].s : f.pruns[slot].s, len = sp_ ? f.sruns[slot].len : f.pruns[slot].len;
+        if (prev + gap + len > TC) {
+          atomicOr(&err, 4u);
+          break;
+        }
+        if (sp_) f.sruns[slot].s = prev + gap;
+        else f.pruns[slot].s = prev + gap;
+        prev += gap + len;
+      }
+    }
+  }
+  __syncthreads();
+  // (a table of more than kMaxRec records) the rows, a thread each: a
+  // record's bytes are fetched together and its fields, which follow the
+  // two varints at offset 2, 3 or 4, taken by selects on that offset
+  for (int tr = tid; tr < TR && !err && nrec > kMaxRec; tr += kUnpackBlock) {
+    uint32_t p = rowstart[tr];
+    const uint32_t end = rowstart[tr + 1];
+    uint32_t bad = 0;
+    auto count = [&]() -> uint32_t {
+      const uint32_t c0 = rbyte(p), c1 = rbyte(p + 1);
+      p += (c0 & 128u) ? 2 : 1;
+      return (c0 & 128u) ? ((c0 & 127u) | (c1 << 7)) : c0;
+    };
+    // gap and len of the record at p; o = their bytes
+    auto lead2 = [&](const uint32_t *b, uint32_t &gap, uint32_t &len, int &o) {
+      const bool g2 = (b[0] & 128u) != 0;
+      gap = g2 ? ((b[0] & 127u) | (b[1] << 7)) : b[0];
+      const uint32_t l0 = g2 ? b[2] : b[1], l1 = g2 ? b[3] : b[2];
+      const bool l2 = (l0 & 128u) != 0;
+      len = l2 ? ((l0 & 127u) | (l1 << 7)) : l0;
+      o = (g2 ? 2 : 1) + (l2 ? 2 : 1);
+    };
+    auto field = [&](const uint32_t *b, int o, int j) -> uint32_t {   // byte o + j, o in {2, 3, 4}
+      return o == 2 ? b[2 + j] : (o == 3 ? b[3 + j] : b[4 + j]);
+    };
+    auto u32f = [&](const uint32_t *b, int o, int j) -> uint32_t {
+      return field(b, o, j) | (field(b, o, j + 1) << 8) | (field(b, o, j + 2) << 16) | (field(b, o, j + 3) << 24);
+    };
+    int np = 0;
+    if (kind) {
+      np = (int)count();
+      int prev = 0;
+      for (int k = 0; k < np && !bad; k++) {
+        uint32_t b[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) b[j] = rbyte(p + j);
+        uint32_t gap, len;
+        int o;
+        lead2(b, gap, len, o);
+        const float c = __uint_as_float(u32f(b, o, 0));
+        p += o + 4;
+        if (p > end || gap > (uint32_t)TC || len < 1 || len > (uint32_t)TC || prev + (int)gap + (int)len > TC) {
           bad = 1;
           break;
         }
-        const int s = prev + (int)gap;
-        f.sruns[(int64_t)tr * TC + k] = pc_run{s, (int)len, (int)axis, a, b, c};
-        prev = s + (int)len;
+        const int s0 = prev + (int)gap;
+        f.pruns[(int64_t)tr * TC + k] = pc_prun{s0, (int)len, -1, c};      // key slot filled below
+        prev = s0 + (int)len;
       }
-      f.nruns[tr] = ns;
-      nsr += ns;
     }
-    if (p != n) bad = 1;
-    if (bad) err |= 4u;
+    f.nruns[TR + tr] = np;
+    const int ns = bad ? 0 : (int)count();
+    int prev = 0;
+    for (int k = 0; k < ns && !bad; k++) {
+      uint32_t b[17];
+#pragma unroll
+      for (int j = 0; j < 17; j++) b[j] = rbyte(p + j);
+      uint32_t gap, len;
+      int o;
+      lead2(b, gap, len, o);
+      const uint32_t axis = field(b, o, 0);
+      const float fa = __uint_as_float(u32f(b, o, 1)), fb = __uint_as_float(u32f(b, o, 5)),
+                  fc = __uint_as_float(u32f(b, o, 9));
+      p += o + 13;
+      if (p > end || gap > (uint32_t)TC || len < 1 || len > (uint32_t)TC || prev + (int)gap + (int)len > TC ||
+          axis > 2) {
+        bad = 1;
+        break;
+      }
+      const int s0 = prev + (int)gap;
+      f.sruns[(int64_t)tr * TC + k] = pc_run{s0, (int)len, (int)axis, fa, fb, fc};
+      prev = s0 + (int)len;
+    }
+    f.nruns[tr] = ns;
+    if (bad || p != end) atomicOr(&err, 4u);
+  }
+  __syncthreads();
+  if (tid == 0) {
     for (int i = 0; i < (int)sizeof(pc_frame_info); i++) ((uint8_t *)f.info)[i] = 0;
     f.info->kind = kind;
     f.info->status = 0;
     for (int e = 0; e < 12; e++) f.info->M[e] = up->M[e];
-    f.info->n_sruns = nsr;
-    f.info->n_pruns = npr;
+    f.info->n_sruns = nsr_s;
+    f.info->n_pruns = npr_s;
     for (int q = 0; q < 4; q++) f.info->stream_bytes[q] = up->nbytes[q];
   }
   __syncthreads();
@@ -1138,17 +1278,30 @@ __device__ __forceinline__ void unpack_frame(UnpackPlan *up, const StreamPtrs &s
     if (tid == 0) atomicOr(&up->err, err);
     return;
   }
+  // each row's codes are the prefix sums (mod 2^16) of its differences, so
+  // a wavefront rebuilds a row 64 codes at a time with a scan (additions
+  // mod 2^32 wrap consistently with mod 2^16)
   const uint8_t *Rb = sp.p[S_RES];
-  for (int h = tid; h < H; h += kUnpackBlock) {
+  const int lane = tid & 63;
+  for (int h = tid >> 6; h < H; h += kUnpackBlock / 64) {
     const int r = h / th;
     const uint32_t b = rowoff[h], c = rowcnt[h], in_strip = b - rowoff[r * th];
     uint16_t *dst = f.res + (int64_t)r * th * W + in_strip;
-    uint32_t prev = 0;
-    for (uint32_t j = 0; j < c; j++) {
-      const uint32_t z = Rb[2 * (b + j)] | ((uint32_t)Rb[2 * (b + j) + 1] << 8);
-      const uint32_t d = (z >> 1) ^ ((z & 1u) ? 0xFFFFu : 0u);
-      prev = (prev + d) & 0xFFFFu;
-      dst[j] = (uint16_t)prev;
+    uint32_t carry = 0;
+    for (uint32_t j0 = 0; j0 < c; j0 += 64) {
+      const uint32_t j = j0 + lane;
+      uint32_t x = 0;
+      if (j < c) {
+        const uint32_t z = Rb[2 * (b + j)] | ((uint32_t)Rb[2 * (b + j) + 1] << 8);
+        x = (z >> 1) ^ ((z & 1u) ? 0xFFFFu : 0u);
+      }
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+      }
+      if (j < c) dst[j] = (uint16_t)((carry + x) & 0xFFFFu);
+      carry += __shfl(x, 63, 64);
     }
   }
 }

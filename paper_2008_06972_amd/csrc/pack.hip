@@ -785,23 +785,53 @@ __device__ void unpack_plan(const uint8_t *in, uint64_t n_in, UnpackPlan *up, co
   }
 }
 
+constexpr int kFastBits = 10;               // code words this short decode with one table lookup
+
 struct DecTab {
   uint32_t limit[kMaxLen + 1], first[kMaxLen + 1], index[kMaxLen + 1];
   uint8_t sorted[256];
+  // by the first kFastBits bits of a code word: symbol | length << 8 when
+  // the word is at most kFastBits long, else 0
+  uint16_t fast[1 << kFastBits];
 };
 
-// The code word at payload bit p: 15 bits MSB first, zeros past the end.
-__device__ __forceinline__ uint32_t peek15(const uint8_t *pay, uint64_t nbytes, uint64_t p) {
-  const uint64_t B = p >> 3;
-  uint32_t x = 0;
+// Payload reads of one stream: from its LDS copy (whole little-endian
+// words, zero past the payload) or, for a payload too large to copy, from
+// device memory byte by byte (clamped loads, zero past the payload).
+template <bool LDS>
+struct PayRead {
+  const __attribute__((address_space(3))) uint32_t *w;
+  const __attribute__((address_space(1))) uint8_t *g;
+  uint32_t nbytes;
+  // the 15 bits from payload bit p, MSB first
+  __device__ __forceinline__ uint32_t peek15(uint32_t p) const {
+    const uint32_t B = p >> 3;
+    uint32_t x;
+    if (LDS) {
+      const uint32_t W0 = B >> 2;
+      const uint64_t v = ((uint64_t)w[W0 + 1] << 32) | w[W0];
+      x = __builtin_bswap32((uint32_t)(v >> (8 * (B & 3))));
+    } else {
+      x = 0;
 #pragma unroll
-  for (int j = 0; j < 3; j++) x = (x << 8) | (B + j < nbytes ? pay[B + j] : 0u);
-  return ((x << (p & 7)) >> 9) & 0x7fffu;
-}
+      for (int j = 0; j < 3; j++) {
+        const uint32_t i = B + j, b = g[min(i, nbytes - 1)];
+        x = (x << 8) | (i < nbytes ? b : 0u);
+      }
+      x <<= 8;
+    }
+    return ((x << (p & 7)) >> 17) & 0x7fffu;
+  }
+};
 
-__device__ __forceinline__ int code_len(const DecTab &t, uint32_t win, uint32_t *bad) {
+// Length of the code word at the head of win: canonical limits (left
+// justified to 15 bits) never decrease with the length, so the length is
+// one more than the number of limits at or below win.  lim: the stream's
+// limits in registers.
+__device__ __forceinline__ int code_len(const uint32_t (&lim)[kMaxLen + 1], uint32_t win, uint32_t *bad) {
   int L = 1;
-  while (L <= kMaxLen && win >= t.limit[L]) L++;
+#pragma unroll
+  for (int l = 1; l <= kMaxLen; l++) L += win >= lim[l] ? 1 : 0;
   if (L > kMaxLen) {
     *bad = 1;
     return 1;
@@ -811,16 +841,92 @@ __device__ __forceinline__ int code_len(const DecTab &t, uint32_t win, uint32_t 
 
 // Decodes subsequence j from payload bit `s`: code words starting before
 // min((j + 1) S, nbits).  Returns the end bit and the code word count.
-__device__ __forceinline__ void decode_sub(const DecTab &t, const uint8_t *pay, uint64_t pbytes, uint64_t lim, uint64_t s,
-                                           uint64_t *end, uint32_t *cnt, uint32_t *bad) {
-  uint64_t p = s;
-  uint32_t c = 0;
-  while (p < lim) {
-    p += code_len(t, peek15(pay, pbytes, p), bad);
+template <class Pay>
+__device__ __forceinline__ void decode_sub(const uint32_t (&lim)[kMaxLen + 1],
+                                           const __attribute__((address_space(3))) uint16_t *fast, const Pay &pay,
+                                           uint32_t lim_bit, uint32_t s, uint32_t *end, uint32_t *cnt, uint32_t *bad) {
+  uint32_t p = s, c = 0;
+  while (p < lim_bit) {
+    const uint32_t win = pay.peek15(p);
+    const uint32_t e = fast[win >> (kMaxLen - kFastBits)];
+    p += e ? (e >> 8) : code_len(lim, win, bad);
     c++;
   }
   *end = p;
   *cnt = c;
+}
+
+// The subsequences of one stream (the part of unpack_stream after its
+// payload and tables are in place): decode from guessed starts, redo those
+// whose start differs from the predecessor's end until none changes, then
+// write the symbols at the prefix of the counts.  st, en: subsequence
+// starts and ends (bits), cnt: code words.
+template <class Pay>
+__device__ __forceinline__ void decode_stream(const Pay &pay, const DecTab &t, uint32_t nbits, uint64_t n,
+                                              uint32_t *st, uint32_t *en, uint32_t *cnt, uint8_t *out, uint32_t *red,
+                                              int *any, uint32_t *err) {
+  const int tid = threadIdx.x;
+  uint32_t lim[kMaxLen + 1];
+#pragma unroll
+  for (int L = 0; L <= kMaxLen; L++) lim[L] = t.limit[L];
+  typedef const __attribute__((address_space(3))) uint16_t lds_u16;
+  lds_u16 *fast = (lds_u16 *)t.fast;
+  uint32_t S = (nbits + kMaxSub - 1) / kMaxSub;
+  S = S < kMinSubBits ? kMinSubBits : S;
+  const uint32_t m = (nbits + S - 1) / S;
+  const uint32_t per = (m + kUnpackBlock - 1) / kUnpackBlock;
+  const uint32_t j0 = min(m, tid * per), j1 = min(m, j0 + per);
+  uint32_t bad = 0;
+  for (uint32_t j = j0; j < j1; j++) {
+    st[j] = j * S;
+    decode_sub(lim, fast, pay, min((j + 1) * S, nbits), st[j], &en[j], &cnt[j], &bad);
+  }
+  // a start that differs from its predecessor's end is decoded again; the
+  // verified prefix grows by at least one thread's share per round
+  for (uint32_t round = 0; round <= kUnpackBlock; round++) {
+    __syncthreads();
+    const uint32_t snap = (j0 > 0 && j0 < j1) ? en[j0 - 1] : 0;
+    if (tid == 0) *any = 0;
+    __syncthreads();
+    int changed = 0;
+    for (uint32_t j = j0; j < j1; j++) {
+      const uint32_t s = j == 0 ? 0 : (j == j0 ? snap : en[j - 1]);
+      if (s != st[j]) {
+        st[j] = s;
+        decode_sub(lim, fast, pay, min((j + 1) * S, nbits), s, &en[j], &cnt[j], &bad);
+        changed = 1;
+      }
+    }
+    if (changed) *any = 1;
+    __syncthreads();
+    if (!*any) break;
+  }
+  uint32_t mine = 0;
+  for (uint32_t j = j0; j < j1; j++) mine += cnt[j];
+  uint32_t total;
+  uint64_t idx = block_excl_scan(mine, red, &total);
+  for (uint32_t j = j0; j < j1; j++) {
+    uint32_t p = st[j];
+    const uint32_t lim_bit = min((j + 1) * S, nbits);
+    while (p < lim_bit) {
+      const uint32_t win = pay.peek15(p);
+      const uint32_t e = fast[win >> (kMaxLen - kFastBits)];
+      int L;
+      uint32_t sym;
+      if (e) {
+        L = (int)(e >> 8);
+        sym = e & 255u;
+      } else {
+        L = code_len(lim, win, &bad);
+        sym = t.sorted[t.index[L] + ((win >> (kMaxLen - L)) - t.first[L])];
+      }
+      if (idx < n) out[idx] = (uint8_t)sym;
+      idx++;
+      p += L;
+    }
+  }
+  if (tid == 0 && total < n) bad = 1;
+  if (bad) atomicOr(err, 2u);
 }
 
 // Stream q of one container, by one work-group.
@@ -843,66 +949,40 @@ __device__ __forceinline__ void unpack_stream(int q, const uint8_t *in, UnpackPl
   }
   for (int s = tid; s < 256; s += kUnpackBlock) t.sorted[s] = up->sorted[q][s];
   __syncthreads();
+  for (int e = tid; e < (1 << kFastBits); e += kUnpackBlock) {
+    const uint32_t win = (uint32_t)e << (kMaxLen - kFastBits);
+    int L = 1;
+    while (L <= kMaxLen && win >= t.limit[L]) L++;
+    t.fast[e] = L <= kFastBits ? (uint16_t)(t.sorted[t.index[L] + ((win >> (kMaxLen - L)) - t.first[L])] | (L << 8))
+                               : (uint16_t)0;
+  }
+  __syncthreads();
   const uint8_t *gpay = in + up->bit0[q] / 8;
   const uint64_t pbytes = nbits / 8;
-  // a payload that fits is staged in LDS: every code word costs dependent
-  // reads of its bytes, which LDS serves several times faster
-  __shared__ __align__(16) uint8_t paybuf[kPayLds];
+  if (nbits > 0xFFFFFF00ull) {                 // positions are 32-bit
+    if (tid == 0) atomicOr(&up->err, 2u);
+    return;
+  }
+  // a payload that fits is staged in LDS (with eight zero bytes after it):
+  // every code word costs dependent reads of its bytes, which LDS serves
+  // several times faster
+  __shared__ __align__(16) uint8_t paybuf[kPayLds + 8];
   const bool staged = pbytes <= (uint64_t)kPayLds;
-  if (staged)
+  if (staged) {
     for (uint32_t i = tid; i < (uint32_t)pbytes; i += kUnpackBlock) paybuf[i] = gpay[i];
+    if (tid < 8) paybuf[pbytes + tid] = 0;
+  }
   __syncthreads();
-  const uint8_t *pay = staged ? (const uint8_t *)paybuf : gpay;
-  uint64_t S = (nbits + kMaxSub - 1) / kMaxSub;
-  S = S < kMinSubBits ? kMinSubBits : S;
-  const uint32_t m = (uint32_t)((nbits + S - 1) / S);
-  uint64_t *st = sub + (int64_t)q * 2 * kMaxSub, *en = st + kMaxSub;
+  uint32_t *st = reinterpret_cast<uint32_t *>(sub) + (int64_t)q * 2 * kMaxSub, *en = st + kMaxSub;
   uint32_t *cnt = subc + (int64_t)q * kMaxSub;
-  const uint32_t per = (m + kUnpackBlock - 1) / kUnpackBlock;
-  const uint32_t j0 = min(m, tid * per), j1 = min(m, j0 + per);
-  uint32_t bad = 0;
-  for (uint32_t j = j0; j < j1; j++) {
-    st[j] = (uint64_t)j * S;
-    decode_sub(t, pay, pbytes, min((uint64_t)(j + 1) * S, nbits), st[j], &en[j], &cnt[j], &bad);
-  }
-  // a start that differs from its predecessor's end is decoded again; the
-  // verified prefix grows by at least one thread's share per round
-  for (uint32_t round = 0; round <= kUnpackBlock; round++) {
-    __syncthreads();
-    const uint64_t snap = (j0 > 0 && j0 < j1) ? en[j0 - 1] : 0;
-    if (tid == 0) any = 0;
-    __syncthreads();
-    int changed = 0;
-    for (uint32_t j = j0; j < j1; j++) {
-      const uint64_t s = j == 0 ? 0 : (j == j0 ? snap : en[j - 1]);
-      if (s != st[j]) {
-        st[j] = s;
-        decode_sub(t, pay, pbytes, min((uint64_t)(j + 1) * S, nbits), s, &en[j], &cnt[j], &bad);
-        changed = 1;
-      }
-    }
-    if (changed) any = 1;
-    __syncthreads();
-    if (!any) break;
-  }
-  uint32_t mine = 0;
-  for (uint32_t j = j0; j < j1; j++) mine += cnt[j];
-  uint32_t total;
-  uint64_t idx = block_excl_scan(mine, red, &total);
-  uint8_t *out = outp.p[q];
-  for (uint32_t j = j0; j < j1; j++) {
-    uint64_t p = st[j];
-    const uint64_t lim = min((uint64_t)(j + 1) * S, nbits);
-    while (p < lim) {
-      const uint32_t win = peek15(pay, pbytes, p);
-      const int L = code_len(t, win, &bad);
-      if (idx < n) out[idx] = t.sorted[t.index[L] + ((win >> (kMaxLen - L)) - t.first[L])];
-      idx++;
-      p += L;
-    }
-  }
-  if (tid == 0 && total < n) bad = 1;
-  if (bad) atomicOr(&up->err, 2u);
+  typedef const __attribute__((address_space(3))) uint32_t lds_u32;
+  typedef const __attribute__((address_space(1))) uint8_t glb_u8;
+  if (staged)
+    decode_stream(PayRead<true>{(lds_u32 *)paybuf, (glb_u8 *)gpay, (uint32_t)pbytes}, t, (uint32_t)nbits, n, st, en, cnt,
+                  outp.p[q], red, &any, &up->err);
+  else
+    decode_stream(PayRead<false>{(lds_u32 *)paybuf, (glb_u8 *)gpay, (uint32_t)pbytes}, t, (uint32_t)nbits, n, st, en,
+                  cnt, outp.p[q], red, &any, &up->err);
 }
 
 // Streams back into a frame stream buffer: occupancy words, runs and tile

@@ -369,8 +369,8 @@ __device__ __forceinline__ void list_push(StripSmem<TH, TW> &sm, int q, int TC, 
 // one thread's latency).  Ends after a barrier with list q's and the FP64
 // list's counters cleared.
 template <int TH, int TW, int LANES, class OnDegenerate, class Keep>
-__device__ __forceinline__ void fit_pass(StripSmem<TH, TW> &sm, const EncParams &p, int q, int n, int TC, int &fits, int &fp64,
-                         OnDegenerate on_degenerate, Keep keep) {
+__device__ __forceinline__ void fit_pass(StripSmem<TH, TW> &sm, const EncParams &p, int q, int n, int TC, bool refit, int &fits,
+                         int &fp64, OnDegenerate on_degenerate, Keep keep) {
   typedef typename LaneGroup<LANES>::type Red;
   const int tid = strip_tid(), sub = tid & (LANES - 1);
   const int16_t *L = sm.list(q, TC);
@@ -381,7 +381,8 @@ __device__ __forceinline__ void fit_pass(StripSmem<TH, TW> &sm, const EncParams 
     Plane P{0, 0.f, 0.f, 0.f};
     T.i0 = sub * (TH / LANES);
     T.i1 = T.i0 + TH / LANES;
-    const bool ok = fit_plane_f32(T, cur[tc], P, Red{});
+    const bool ok = refit ? refit_plane_f32(T, cur[tc], unpack_plane(sm.plane[tc]), P, Red{})
+                          : fit_plane_f32(T, cur[tc], P, Red{});
     const uint64_t S2 = ok ? inliers(T, P, p.eps, Red{}) : 0ull;
     if (sub != 0) continue;
     fits++;
@@ -458,9 +459,11 @@ __device__ __forceinline__ void own_fits(StripSmem<TH, TW> &sm, const EncParams 
             sm.stat[tc] = __popcll(S2) >= need_of(p, sm.nv[tc]) ? ST_ACCEPTED : ST_REJECTED;
           }
     };
-    if (p.lanes >= 4 && n <= kBlock / 4) fit_pass<TH, TW, 4>(sm, p, q, n, TC, fits, fp64, degenerate, kept);
-    else if (p.lanes >= 2 && n <= kBlock / 2) fit_pass<TH, TW, 2>(sm, p, q, n, TC, fits, fp64, degenerate, kept);
-    else fit_pass<TH, TW, 1>(sm, p, q, n, TC, fits, fp64, degenerate, kept);
+    // from the second fit on, the previous fit's normal gives the frame
+    const bool refit = it > 1;
+    if (p.lanes >= 4 && n <= kBlock / 4) fit_pass<TH, TW, 4>(sm, p, q, n, TC, refit, fits, fp64, degenerate, kept);
+    else if (p.lanes >= 2 && n <= kBlock / 2) fit_pass<TH, TW, 2>(sm, p, q, n, TC, refit, fits, fp64, degenerate, kept);
+    else fit_pass<TH, TW, 1>(sm, p, q, n, TC, refit, fits, fp64, degenerate, kept);
     n = sm.misc[M_LIST + (q ^ 1)];
   }
   __syncthreads();
@@ -531,7 +534,7 @@ __device__ __forceinline__ void seeded_fits(StripSmem<TH, TW> &sm, const EncPara
   const int n = sm.misc[M_LIST];
   if (n > 0)
     fit_pass<TH, TW, 1>(
-        sm, p, 0, n, TC, fits, fp64, [&](int tc) { sm.elig[tc] = 2; },
+        sm, p, 0, n, TC, false, fits, fp64, [&](int tc) { sm.elig[tc] = 2; },
         [&](int tc, const Plane &P, uint64_t S2) {
           if (__popcll(S2) >= need_of(p, sm.nv[tc])) {
             sm.omask[tc] = S2;

@@ -442,6 +442,50 @@ __device__ __forceinline__ bool fit_plane_f64(const Tile &T, uint64_t S, Plane &
   return true;
 }
 
+// Steps 2-3 of the FP32 fit for the pixels in S (n of them): the scatter
+// about the point m with each deviation rotated into the orthonormal frame
+// (a, l x a, l), its first moments correcting for m not being the mean,
+// then Jacobi on the nearly diagonal result, rotated back, and the offset
+// through the mean.  False when FP32 cannot decide (the two smallest
+// eigenvalues within kNearDegenerate of the largest).
+template <class Tile, class Red>
+__device__ __forceinline__ bool fit_in_frame(const Tile &T, uint64_t S, float n, float mx, float my, float mz, float ax,
+                                             float ay, float az, float lx, float ly, float lz, Plane &P, Red red) {
+  const float in = frcp(n);
+  float bx = ly * az - lz * ay, by = lz * ax - lx * az, bz = lx * ay - ly * ax;   // a2 = a3 x a1
+  float q1 = 0.f, q2 = 0.f, q3 = 0.f;
+  float s11 = 0.f, s12 = 0.f, s13 = 0.f, s22 = 0.f, s23 = 0.f, s33 = 0.f;
+  T.each([&](int j, float r, const Dir &d) {
+    float w = bitw(S, j);
+    float ex = fmaf(r, d.x, -mx), ey = fmaf(r, d.y, -my), ez = fmaf(r, d.z, -mz);
+    float e1 = fmaf(ax, ex, fmaf(ay, ey, az * ez)) * w;
+    float e2 = fmaf(bx, ex, fmaf(by, ey, bz * ez)) * w;
+    float e3 = fmaf(lx, ex, fmaf(ly, ey, lz * ez)) * w;
+    q1 += e1; q2 += e2; q3 += e3;
+    s11 = fmaf(e1, e1, s11); s12 = fmaf(e1, e2, s12); s13 = fmaf(e1, e3, s13);
+    s22 = fmaf(e2, e2, s22); s23 = fmaf(e2, e3, s23); s33 = fmaf(e3, e3, s33);
+  });
+  q1 = red.sum(q1); q2 = red.sum(q2); q3 = red.sum(q3);
+  s11 = red.sum(s11); s12 = red.sum(s12); s13 = red.sum(s13);
+  s22 = red.sum(s22); s23 = red.sum(s23); s33 = red.sum(s33);
+  float u1 = q1 * in, u2 = q2 * in, u3 = q3 * in;    // rounding left in the mean
+  s11 -= q1 * u1; s12 -= q1 * u2; s13 -= q1 * u3;
+  s22 -= q2 * u2; s23 -= q2 * u3; s33 -= q3 * u3;
+  float w1, w2, w3, l1, l2, l3;
+  jacobi3_f32(s11, s12, s13, s22, s23, s33, 3, w1, w2, w3, l1, l2, l3);
+  if (!((l2 - l1) > kNearDegenerate * l3)) return false;
+  float nx = w1 * ax + w2 * bx + w3 * lx;
+  float ny = w1 * ay + w2 * by + w3 * ly;
+  float nz = w1 * az + w2 * bz + w3 * lz;
+  float nn = frsq(nx * nx + ny * ny + nz * nz);
+  nx *= nn; ny *= nn; nz *= nn;
+  // offset through the exact-product mean: n . mean + n . (mean of e)
+  float ux = u1 * ax + u2 * bx + u3 * lx, uy = u1 * ay + u2 * by + u3 * ly, uz = u1 * az + u2 * bz + u3 * lz;
+  float c = (nx * mx + ny * my + nz * mz) + (nx * ux + ny * uy + nz * uz);
+  P = stored_form_f32(nx, ny, nz, c);
+  return true;
+}
+
 // Least-squares plane through the pixels in S, FP32:
 //  1. sums of the deviations from one of the tile's points, p - p0 =
 //     fma(r, d, -p0) (one rounding), and of their products: the mean and an
@@ -481,38 +525,43 @@ __device__ __forceinline__ bool fit_plane_f32(const Tile &T, uint64_t S, Plane &
   const float mx = px + ux0, my = py + uy0, mz = pz + uz0;
   float ax, ay, az, lx, ly, lz;
   if (!eig3_frame_f32(cxx, cxy, cxz, cyy, cyz, czz, ax, ay, az, lx, ly, lz)) return false;
-  float bx = ly * az - lz * ay, by = lz * ax - lx * az, bz = lx * ay - ly * ax;   // a2 = a3 x a1
-  float q1 = 0.f, q2 = 0.f, q3 = 0.f;
-  float s11 = 0.f, s12 = 0.f, s13 = 0.f, s22 = 0.f, s23 = 0.f, s33 = 0.f;
-  T.each([&](int j, float r, const Dir &d) {
-    float w = bitw(S, j);
-    float ex = fmaf(r, d.x, -mx), ey = fmaf(r, d.y, -my), ez = fmaf(r, d.z, -mz);
-    float e1 = fmaf(ax, ex, fmaf(ay, ey, az * ez)) * w;
-    float e2 = fmaf(bx, ex, fmaf(by, ey, bz * ez)) * w;
-    float e3 = fmaf(lx, ex, fmaf(ly, ey, lz * ez)) * w;
-    q1 += e1; q2 += e2; q3 += e3;
-    s11 = fmaf(e1, e1, s11); s12 = fmaf(e1, e2, s12); s13 = fmaf(e1, e3, s13);
-    s22 = fmaf(e2, e2, s22); s23 = fmaf(e2, e3, s23); s33 = fmaf(e3, e3, s33);
-  });
-  q1 = red.sum(q1); q2 = red.sum(q2); q3 = red.sum(q3);
-  s11 = red.sum(s11); s12 = red.sum(s12); s13 = red.sum(s13);
-  s22 = red.sum(s22); s23 = red.sum(s23); s33 = red.sum(s33);
-  float u1 = q1 * in, u2 = q2 * in, u3 = q3 * in;    // rounding left in the mean
-  s11 -= q1 * u1; s12 -= q1 * u2; s13 -= q1 * u3;
-  s22 -= q2 * u2; s23 -= q2 * u3; s33 -= q3 * u3;
-  float w1, w2, w3, l1, l2, l3;
-  jacobi3_f32(s11, s12, s13, s22, s23, s33, 3, w1, w2, w3, l1, l2, l3);
-  if (!((l2 - l1) > kNearDegenerate * l3)) return false;
-  float nx = w1 * ax + w2 * bx + w3 * lx;
-  float ny = w1 * ay + w2 * by + w3 * ly;
-  float nz = w1 * az + w2 * bz + w3 * lz;
-  float nn = frsq(nx * nx + ny * ny + nz * nz);
-  nx *= nn; ny *= nn; nz *= nn;
-  // offset through the exact-product mean: n . mean + n . (mean of e)
-  float ux = u1 * ax + u2 * bx + u3 * lx, uy = u1 * ay + u2 * by + u3 * ly, uz = u1 * az + u2 * bz + u3 * lz;
-  float c = (nx * mx + ny * my + nz * mz) + (nx * ux + ny * uy + nz * uz);
-  P = stored_form_f32(nx, ny, nz, c);
-  return true;
+  return fit_in_frame(T, S, n, mx, my, mz, ax, ay, az, lx, ly, lz, P, red);
+}
+
+// The FP32 fit of a refit (iteration two on): the previous fit's normal
+// serves as the frame's first axis, the direction from the first to the
+// last pixel of S (made orthogonal to it) as its third, and the first
+// pixel as the point m, so the fit takes one pass over the tile (the first
+// moments in the frame carry the mean exactly).  When the pixels lie close
+// to a line, that direction is the line's, which the frame must carry for
+// the in-plane scatter to stay well resolved in FP32.
+template <class Tile, class Red = LaneOne>
+__device__ __forceinline__ bool refit_plane_f32(const Tile &T, uint64_t S, const Plane &prev, Plane &P, Red red = Red{}) {
+  const float n = (float)__popcll(S);
+  const int j0 = __ffsll((long long)S) - 1, j1 = 63 - __clzll((long long)S);
+  const Dir d0 = T.dir_at(j0 / Tile::TWc, j0 % Tile::TWc), d1 = T.dir_at(j1 / Tile::TWc, j1 % Tile::TWc);
+  const float r0 = T.at(j0), r1 = T.at(j1);
+  const float mx = r0 * d0.x, my = r0 * d0.y, mz = r0 * d0.z;
+  // unit normal of the previous stored form (1, a, b) on axes (k, k1, k2)
+  float ax = prev.k == 0 ? 1.0f : prev.a, ay = prev.k == 1 ? 1.0f : (prev.k == 0 ? prev.a : prev.b),
+        az = prev.k == 2 ? 1.0f : prev.b;
+  const float na = frsq(ax * ax + ay * ay + az * az);
+  ax *= na; ay *= na; az *= na;
+  // first-to-last pixel, orthogonal to the normal
+  float lx = fmaf(r1, d1.x, -mx), ly = fmaf(r1, d1.y, -my), lz = fmaf(r1, d1.z, -mz);
+  const float dp = lx * ax + ly * ay + lz * az;
+  lx -= dp * ax; ly -= dp * ay; lz -= dp * az;
+  float ll = lx * lx + ly * ly + lz * lz;
+  if (!(ll > 1e-12f)) {     // along the normal: any unit vector orthogonal to it
+    const float ux = fabsf(ax) <= fabsf(ay) && fabsf(ax) <= fabsf(az) ? 1.f : 0.f;
+    const float uy = ux == 0.f && fabsf(ay) <= fabsf(az) ? 1.f : 0.f;
+    const float uz = (ux == 0.f && uy == 0.f) ? 1.f : 0.f;
+    lx = ay * uz - az * uy; ly = az * ux - ax * uz; lz = ax * uy - ay * ux;
+    ll = lx * lx + ly * ly + lz * lz;
+  }
+  const float il = frsq(ll);
+  lx *= il; ly *= il; lz *= il;
+  return fit_in_frame(T, S, n, mx, my, mz, ax, ay, az, lx, ly, lz, P, red);
 }
 
 // Points a tile must keep on its plane: max(min(min_pts, n), ceil(rho n)),

@@ -44,6 +44,7 @@ __device__ __forceinline__ int strip_tid() {
 constexpr int kReach = 6;     // tiles a fit measures its reach over before the walk continues it
 constexpr int kBinChunkPts = 2048;      // points per binning block (its chunk's capacity)
 constexpr int kSegMax = 512;            // chunk offsets the loader gathers at a time (two ints each)
+constexpr int kSegJoint = 8;            // chunk segments a loader wavefront reads together
 constexpr size_t kSegBytes = 2 * sizeof(int) * kSegMax;
 
 // ---------------------------------------------------------------- LDS layout
@@ -266,29 +267,29 @@ __device__ __forceinline__ void load_source(StripSmem<TH, TW> &sm, const StripSr
         sl[b] = o[1] - a;
       }
       __syncthreads();
-      // a wavefront takes four chunks' segments at a time and reads them
-      // jointly, 128 entries of each per round (eight loads per lane in
-      // flight), as many rounds as the longest of the four needs
-      for (int b0 = wv; b0 < nb; b0 += 4 * NW) {
-        int len[4];
-        int64_t at[4];
+      // a wavefront takes kSegJoint chunks' segments at a time and reads
+      // them jointly, 128 entries of each per round (2 kSegJoint loads per
+      // lane in flight), as many rounds as the longest of them needs
+      for (int b0 = wv; b0 < nb; b0 += kSegJoint * NW) {
+        int len[kSegJoint];
+        int64_t at[kSegJoint];
         int mx = 0;
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
+        for (int u = 0; u < kSegJoint; u++) {
           const int b = b0 + u * NW;
           len[u] = b < nb ? sl[b] : 0;
           at[u] = (int64_t)(c0 + b) * kBinChunkPts + (b < nb ? sb[b] : 0);
           mx = max(mx, len[u]);
         }
         for (int q0 = lane; q0 < mx; q0 += 128) {
-          uint64_t en[8];
+          uint64_t en[2 * kSegJoint];
 #pragma unroll
-          for (int u = 0; u < 4; u++) {
+          for (int u = 0; u < kSegJoint; u++) {
             en[2 * u] = q0 < len[u] ? (uint64_t)ch[at[u] + q0] : ~0ull;
             en[2 * u + 1] = q0 + 64 < len[u] ? (uint64_t)ch[at[u] + q0 + 64] : ~0ull;
           }
 #pragma unroll
-          for (int u = 0; u < 8; u++)
+          for (int u = 0; u < 2 * kSegJoint; u++)
             if ((uint32_t)en[u] < lim) atomicMin(&ri[(uint32_t)en[u]], (uint32_t)(en[u] >> 32));
         }
       }

@@ -1037,8 +1037,10 @@ __device__ __forceinline__ void residuals_and_streams(StripSmem<TH, TW> &sm, con
         float r = sm.r[tile_elem(tc, j, N)];
         if (r > 0.0f && !((fm >> j) & 1ull)) {
           float q = rintf(r * p.inv);
-          double back = (double)(q * p.step);
-          if (q > 65535.0f || fabs(back - (double)r) > (double)p.eps) {
+          // the difference is exact in FP32 (back and r within a factor of
+          // two when q >= 1, back = 0 otherwise)
+          const float back = q * p.step;
+          if (q > 65535.0f || fabsf(back - r) > p.eps) {
             bad = 1;
             q = fminf(q, 65535.0f);
           }

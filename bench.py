@@ -146,6 +146,8 @@ def run_mixed(a, log, nseq=96):
         big = max(sens, key=lambda hw: hw[0] * hw[1])
         tuned = timed(plans, chosen[big].lanes if chosen[big] else 0)
         tuned["plans"] = {f"{hw[0]}x{hw[1]}": (c.key() if c else None) for hw, c in chosen.items()}
+        if a.plans:
+            autotune.save_plans(a.plans, {autotune.plan_key(hw[0], hw[1], eps): c for hw, c in chosen.items() if c})
         out[f"eps_{eps}"] = {"tiles_4x8": plain, "autotuned": tuned}
         log(f"mixed eps {eps}: 4x8 {plain['frames_per_s']:.0f} frames/s ratio {plain['compression_ratio']:.2f}; "
             f"autotuned {tuned['frames_per_s']:.0f} frames/s ratio {tuned['compression_ratio']:.2f}")
@@ -162,6 +164,7 @@ def main():
     ap.add_argument("--seqs", type=int, default=96)
     ap.add_argument("--forms", default="plain,batched,learned")
     ap.add_argument("--tune-seqs", type=int, default=8, help="sequences the autotuner times candidates on (0 = off)")
+    ap.add_argument("--plans", default="", metavar="JSON", help="keep the autotuner's chosen plans in this file")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2008_06972_amd", "weights", "seednet_c2.f32"),
                     help="seed-network parameters for the learned form")
     ap.add_argument("--plain-steps", type=int, default=5)
@@ -292,6 +295,8 @@ def main():
             best, cands, ref_ratio = autotune.tune(pcc, torch, ctx, S, EPS, sample, KEY_INDEX, net=use_net,
                                                    shapes=shapes, log=log)
             tuned[name] = best
+            if a.plans and best is not None:
+                autotune.save_plans(a.plans, {autotune.plan_key(s.H, s.W, EPS) + f" {name}": best})
             result.setdefault("autotune", {})[name] = {
                 "chosen": best.key() if best else None, "reference_ratio": ref_ratio,
                 "candidates": {c.key(): {"ms": round(c.ms, 4), "ratio": round(c.ratio, 4), "ok": c.ok} for c in cands}}

@@ -146,3 +146,51 @@ def tune_mixed(pcc, torch, ctx, eps, samples, key_index, shapes=SHAPES, lanes=(1
                 f"({best.ms if best else float('nan'):.3f} ms, ratio {best.ratio if best else float('nan'):.3f}, "
                 f"4x8 ratio {ref_ratio:.3f})")
     return out
+
+
+# ------------------------------------------------------------ plan cache
+# Chosen plans kept between runs: a JSON object keyed by "HxW eps" (sensor
+# rows and columns, error bound in metres), each value the candidate's
+# fields and its measurement.
+def plan_key(H: int, W: int, eps: float) -> str:
+    return f"{H}x{W} {eps:g}"
+
+
+def to_record(c: Candidate) -> dict:
+    return {"tile": list(c.tile), "persistent": c.persistent, "blocks_per_cu": c.blocks_per_cu, "seeded": c.seeded,
+            "lanes": c.lanes, "ms": c.ms, "ratio": c.ratio}
+
+
+def from_record(r: dict) -> Candidate:
+    c = Candidate(tuple(int(x) for x in r["tile"]), bool(r["persistent"]), int(r["blocks_per_cu"]), bool(r["seeded"]),
+                  int(r.get("lanes", 4)))
+    c.ms, c.ratio, c.ok = float(r.get("ms", float("nan"))), float(r.get("ratio", float("nan"))), True
+    if c.tile not in SHAPES or c.lanes not in (1, 2, 4) or c.blocks_per_cu < 0:
+        raise ValueError(f"not a valid plan: {r}")
+    return c
+
+
+def save_plans(path: str, plans: dict) -> None:
+    """plans: {plan_key: Candidate}; merged into the file's existing entries."""
+    import json
+    import os
+    data = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            data = json.load(f)
+    data.update({k: to_record(c) for k, c in plans.items()})
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def load_plans(path: str) -> dict:
+    """{plan_key: Candidate} from a file written by save_plans ({} if absent)."""
+    import json
+    import os
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        data = json.load(f)
+    return {k: from_record(r) for k, r in data.items()}

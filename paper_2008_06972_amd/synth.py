@@ -65,6 +65,30 @@ SENSORS = {
 }
 
 
+# The five workloads the encoder is measured and tested on, by name: the
+# sensors, the scene kind, tile shape, error bounds, frames per sequence
+# with the key frame's index, sequences, and the first seed.
+WORKLOADS = {
+    "single-16": dict(sensors=("c1",), scene="c1", tile=(4, 4), eps=(0.02,), frames=1, key=0, sequences=1, seed=1000),
+    "single-64": dict(sensors=("c2",), scene="c2", tile=(4, 8), eps=(0.02,), frames=1, key=0, sequences=1, seed=2000),
+    "sequence-16": dict(sensors=("c1",), scene="c1", tile=(4, 4), eps=(0.02,), frames=10, key=0, sequences=1,
+                        seed=3000),
+    "batch-uneven": dict(sensors=tuple(f"{b}x{w}" for b, w in ((16, 1024), (16, 2048), (32, 1024), (32, 2048),
+                                                                (64, 1024), (64, 2048), (128, 1024), (128, 2048))),
+                         scene="c1", tile=None, eps=(0.01, 0.02), frames=10, key=5, sequences=96, seed=4000),
+    "learned-128": dict(sensors=("c5",), scene="c2", tile=(4, 8), eps=(0.02,), frames=10, key=5, sequences=200,
+                        seed=900000),
+}
+
+
+def workload_sensor(name: str) -> Sensor:
+    """A WORKLOADS sensor name: a SENSORS key, or "BxW" for the uneven batch."""
+    if name in SENSORS:
+        return SENSORS[name]
+    b, w = name.split("x")
+    return mixed_sensor(int(b), int(w))
+
+
 def mixed_sensor(beams: int, width: int) -> Sensor:
     """Sensors of the uneven batch: 16 beams span +-15 deg, 64 beams the HDL-64E
     fan, 32 and 128 beams span +15..-25 deg."""

@@ -14,7 +14,9 @@ sizes and the rates of both are reported.
         --epochs 12 --eval-seqs 200 --out paper_2008_06972_amd/weights/seednet_c5.f32
 
 Weights are written as PC_NET_PARAMS little-endian FP32 values, with a JSON
-note beside them (training configuration and held-out results).
+note beside them (training configuration and held-out results); with
+--state the Adam moments and step count are kept too and training resumes
+from them.
 """
 from __future__ import annotations
 
@@ -128,6 +130,8 @@ def main():
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--procs", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--out", default=os.path.join(ROOT, "paper_2008_06972_amd", "weights", "seednet_c2.f32"))
+    ap.add_argument("--state", default="", metavar="NPZ",
+                    help="optimiser state (parameters, Adam moments, step): resumed from if present, written at the end")
     a = ap.parse_args()
 
     import torch
@@ -161,13 +165,21 @@ def main():
     params = torch.from_numpy(he_init(1, P)).to(dev)
     m = torch.zeros(P, device=dev)
     v = torch.zeros(P, device=dev)
+    step0 = 0
+    if a.state and os.path.exists(a.state):
+        st = np.load(a.state)                  # plain arrays (no pickle)
+        params = torch.from_numpy(st["params"].astype(np.float32)).to(dev)
+        m = torch.from_numpy(st["m"].astype(np.float32)).to(dev)
+        v = torch.from_numpy(st["v"].astype(np.float32)).to(dev)
+        step0 = int(st["step"])
+        print(f"resumed from {a.state} at step {step0}", flush=True)
     grad = torch.zeros(P, device=dev)
     work = torch.zeros(pcc.pc_net_workspace_size(S), dtype=torch.uint8, device=dev)
     seed = torch.zeros(s.H // 4, s.W // 8, 4, device=dev)
     dseed = torch.zeros_like(seed)
     loss = torch.zeros(1, device=dev)
     losses = []
-    step = 0
+    step = step0
     t0 = time.time()
     for ep in range(a.epochs):
         order = np.random.default_rng(ep).permutation(len(data))
@@ -197,6 +209,8 @@ def main():
 
     os.makedirs(os.path.dirname(a.out), exist_ok=True)
     params.cpu().numpy().astype("<f4").tofile(a.out)
+    if a.state:
+        np.savez(a.state, params=params.cpu().numpy(), m=m.cpu().numpy(), v=v.cpu().numpy(), step=np.int64(step))
     note = {"sensor": a.sensor, "sensor_shape": [s.H, s.W, s.top_deg, s.bot_deg], "scene": a.scene,
             "frames": a.frames, "seeds": [a.seed0, a.seed0 + a.frames - 1], "epochs": a.epochs,
             "lr": a.lr, "loss_per_epoch": losses, "held_out": res,

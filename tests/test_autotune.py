@@ -32,3 +32,26 @@ def test_candidate_space():
     assert sum(1 for c in cs if not c.persistent) == 4
     assert sorted({c.lanes for c in cs}) == [1, 2, 4]
     assert len({c.key() for c in cs}) == len(cs)
+
+
+def test_plan_cache_round_trip(tmp_path):
+    """Chosen plans survive a save and load; a second save merges entries;
+    a record naming a shape that is not compiled is refused."""
+    import pytest
+    autotune = at
+    p = str(tmp_path / "plans.json")
+    a = autotune.Candidate((4, 8), True, 4, False, 2)
+    a.ms, a.ratio = 1.25, 24.9
+    b = autotune.Candidate((8, 8), False, 0, False)
+    autotune.save_plans(p, {autotune.plan_key(64, 2048, 0.02): a})
+    autotune.save_plans(p, {autotune.plan_key(16, 1024, 0.01): b})
+    got = autotune.load_plans(p)
+    assert set(got) == {"64x2048 0.02", "16x1024 0.01"}
+    assert got["64x2048 0.02"].key() == a.key() and got["64x2048 0.02"].ms == 1.25
+    assert got["16x1024 0.01"].key() == b.key()
+    assert autotune.load_plans(str(tmp_path / "missing.json")) == {}
+    import json
+    bad = dict(autotune.to_record(a), tile=[3, 5])
+    json.dump({"x": bad}, open(p, "w"))
+    with pytest.raises(ValueError):
+        autotune.load_plans(p)

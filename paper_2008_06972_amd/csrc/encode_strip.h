@@ -524,6 +524,7 @@ __device__ __forceinline__ void seeded_fits(StripSmem<TH, TW> &sm, const EncPara
         state = 2;
         if (__popcll(S1) >= p.min_pts) {
           cur[tc] = S1;
+          sm.plane[tc] = pack_plane(Q);     // the seed's normal frames the refit
           list_push<TH, TW>(sm, 0, TC, tc);
           state = 3;
         }
@@ -535,7 +536,7 @@ __device__ __forceinline__ void seeded_fits(StripSmem<TH, TW> &sm, const EncPara
   const int n = sm.misc[M_LIST];
   if (n > 0)
     fit_pass<TH, TW, 1>(
-        sm, p, 0, n, TC, false, fits, fp64, [&](int tc) { sm.elig[tc] = 2; },
+        sm, p, 0, n, TC, true, fits, fp64, [&](int tc) { sm.elig[tc] = 2; },
         [&](int tc, const Plane &P, uint64_t S2) {
           if (__popcll(S2) >= need_of(p, sm.nv[tc])) {
             sm.omask[tc] = S2;

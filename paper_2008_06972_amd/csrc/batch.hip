@@ -4,7 +4,7 @@
 //   reset    zero the queue counters (a kernel, so the graph holds no memset
 //            node)
 //   bin      project every point (Eq. (1), (2), (6)); each work-group groups
-//            its 2048 points by tile-row strip in LDS and writes them as one
+//            its 4096 points by tile-row strip in LDS and writes them as one
 //            chunk of (LDS slot, range bits) entries, with the chunk's first
 //            entry of every strip
 //   keyimage (with a seed network) the key frames' range images, built per
@@ -35,7 +35,7 @@
 namespace pcc {
 
 constexpr int kBinPts = 8;                 // points per thread in the binning passes
-constexpr int kBinBlock = 256;
+constexpr int kBinBlock = 512;
 constexpr int kBinChunk = kBinPts * kBinBlock;
 static_assert(kBinChunk == kBinChunkPts, "chunk capacity as the strip loader reads it");
 constexpr size_t kCountTabMax = 32 * 1024;  // sensor tables up to this size go to LDS in the binning pass

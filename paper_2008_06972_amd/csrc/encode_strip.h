@@ -42,7 +42,7 @@ __device__ __forceinline__ int strip_tid() {
 }
 
 constexpr int kReach = 6;     // tiles a fit measures its reach over before the walk continues it
-constexpr int kBinChunkPts = 2048;      // points per binning block (its chunk's capacity)
+constexpr int kBinChunkPts = 4096;      // points per binning block (its chunk's capacity)
 constexpr int kSegMax = 512;            // chunk offsets the loader gathers at a time (two ints each)
 constexpr int kSegJoint = 8;            // chunk segments a loader wavefront reads together
 constexpr size_t kSegBytes = 2 * sizeof(int) * kSegMax;

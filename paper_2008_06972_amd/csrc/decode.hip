@@ -36,8 +36,10 @@ __device__ __forceinline__ void block_prefix(uint32_t *a, int n, uint32_t *wsum)
   __syncthreads();
 }
 
-// One work-group per (tile-row strip, frame); blockIdx.y picks the frame's
-// job from `jobs`, or j0 when jobs is NULL.  Phase 1 (a thread per tile):
+// One work-group per (frame, tile-row strip); blockIdx.x picks the frame's
+// job from `jobs` (or j0 when jobs is NULL) and blockIdx.y the strip, so
+// that consecutive work-groups, which go to different XCDs, hold different
+// frames and every XCD gets every strip row.  Phase 1 (a thread per tile):
 // the run planes of the strip's tiles and the residual count of every
 // (row, tile) segment, prefix-summed into each segment's first code.
 // Phase 2 (a thread per four consecutive pixels of a row): each pixel is
@@ -55,12 +57,12 @@ __global__ void __launch_bounds__(kBlock) k_decode(DecodeJob j0, const DecodeJob
   extern __shared__ __align__(16) char smem_raw[];
   __shared__ uint32_t wsum[kBlock / 64];
   __shared__ float Ms[12];
-  const DecodeJob *J = jobs ? jobs + blockIdx.y : &j0;
+  const DecodeJob *J = jobs ? jobs + blockIdx.x : &j0;
   const FrameDev f = J->f;
   const int has_key = J->has_key;
   float *__restrict__ out = J->out;
   float *__restrict__ xyz = J->xyz;
-  const int TC = f.TC, tr = blockIdx.x, tid = threadIdx.x, W = s.W;
+  const int TC = f.TC, tr = blockIdx.y, tid = threadIdx.x, W = s.W;
   float4 *pl = (float4 *)smem_raw;                          // [TC]
   uint8_t *has = (uint8_t *)(pl + TC);                      // [TC]: 0 none, 1 plane, 2 temporal without its key
   uint32_t *cnt = (uint32_t *)(has + ((TC + 15) & ~15));    // [TH * TC]
@@ -177,7 +179,7 @@ static hipError_t launch_decode_t(const DecodeJob &j0, const DecodeJob *jobs, in
   size_t sh = sizeof(float4) * TC + ((TC + 15) & ~15) + sizeof(uint32_t) * TH * TC + 64;
   hipError_t e = hipFuncSetAttribute((const void *)k_decode<TH, TW>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_decode<TH, TW>), dim3(TR, n), dim3(kBlock), sh, st, j0, jobs, s, p);
+  hipLaunchKernelGGL((k_decode<TH, TW>), dim3(n, TR), dim3(kBlock), sh, st, j0, jobs, s, p);
   return hipGetLastError();
 }
 

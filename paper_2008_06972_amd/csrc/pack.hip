@@ -488,9 +488,10 @@ __device__ void encode_bytes(const uint8_t *buf, uint32_t n, uint64_t bit0, uint
 
 // One work-group per tile-row strip: regenerate the strip's bytes of each
 // stream from the frame stream buffer, optionally copy them out, and code
-// them.
+// them.  blockIdx.x is the frame (job) and blockIdx.y the strip, so that
+// every XCD gets every strip row.
 __global__ void __launch_bounds__(kPackBlock) k_pack_frame(PackJob j0, const PackJob *jobs) {
-  const PackJob *J = jobs ? jobs + blockIdx.y : &j0;
+  const PackJob *J = jobs ? jobs + blockIdx.x : &j0;
   const FrameDev f = J->f;
   const int th = J->th, tw = J->tw, W = J->W, max_seg = J->max_seg;
   PackPlan *plan = J->plan;
@@ -503,7 +504,7 @@ __global__ void __launch_bounds__(kPackBlock) k_pack_frame(PackJob j0, const Pac
   uint32_t *red = code + 1024;                           // [16]
   uint8_t *buf = (uint8_t *)(red + 16);                  // the strip's bytes of one stream
   __shared__ int skip;
-  const int tid = threadIdx.x, tr = blockIdx.x, TC = f.TC, TR = f.TR;
+  const int tid = threadIdx.x, tr = blockIdx.y, TC = f.TC, TR = f.TR;
   // other strips may raise plan->err meanwhile: decide once for the group
   if (tid == 0) skip = (plan->err & 1u) || plan->total == 0;
   __syncthreads();
@@ -868,11 +869,15 @@ __device__ __forceinline__ void decode_stream(const Pay &pay, const DecTab &t, u
   const int tid = threadIdx.x;
   uint32_t lim[kMaxLen + 1];
 #pragma unroll
-  for (int L = 0; L <= kMaxLen; L++) lim[L] = t.limit[L];
+  for (int L = 0; L <= kMaxLen; L++) lim[L] = __builtin_amdgcn_readfirstlane(t.limit[L]);   // uniform: scalar registers
   typedef const __attribute__((address_space(3))) uint16_t lds_u16;
   lds_u16 *fast = (lds_u16 *)t.fast;
   uint32_t S = (nbits + kMaxSub - 1) / kMaxSub;
   S = S < kMinSubBits ? kMinSubBits : S;
+  // an odd number of 32-bit words per subsequence: neighbouring lanes then
+  // read the LDS payload an odd number of words apart, which spreads them
+  // over the banks (at 8 words apart, 16 lanes share a bank)
+  S = (((S + 31u) / 32u) | 1u) * 32u;
   const uint32_t m = (nbits + S - 1) / S;
   const uint32_t per = (m + kUnpackBlock - 1) / kUnpackBlock;
   const uint32_t j0 = min(m, tid * per), j1 = min(m, j0 + per);
@@ -905,6 +910,22 @@ __device__ __forceinline__ void decode_stream(const Pay &pay, const DecTab &t, u
   for (uint32_t j = j0; j < j1; j++) mine += cnt[j];
   uint32_t total;
   uint64_t idx = block_excl_scan(mine, red, &total);
+  // a lane's symbols are consecutive bytes of out: they are gathered into
+  // 32-bit words and stored whole where the lane owns the whole aligned word
+  // (within the n bytes), byte by byte at its two ends
+  const uint32_t a0 = (uint32_t)(reinterpret_cast<uintptr_t>(out) & 3u);
+  uint64_t wbeg = idx;
+  uint32_t acc = 0;
+  auto flush = [&](uint64_t e) {
+    if (((a0 + wbeg) & 3u) == 0 && e == wbeg + 4 && e <= n) {
+      *reinterpret_cast<uint32_t *>(out + wbeg) = acc;
+    } else {
+      for (uint64_t i = wbeg; i < e; i++)
+        if (i < n) out[i] = (uint8_t)(acc >> (8u * ((a0 + (uint32_t)i) & 3u)));
+    }
+    acc = 0;
+    wbeg = e;
+  };
   for (uint32_t j = j0; j < j1; j++) {
     uint32_t p = st[j];
     const uint32_t lim_bit = min((j + 1) * S, nbits);
@@ -920,11 +941,13 @@ __device__ __forceinline__ void decode_stream(const Pay &pay, const DecTab &t, u
         L = code_len(lim, win, &bad);
         sym = t.sorted[t.index[L] + ((win >> (kMaxLen - L)) - t.first[L])];
       }
-      if (idx < n) out[idx] = (uint8_t)sym;
+      acc |= sym << (8u * ((a0 + (uint32_t)idx) & 3u));
       idx++;
+      if (((a0 + (uint32_t)idx) & 3u) == 0) flush(idx);
       p += L;
     }
   }
+  if (idx > wbeg) flush(idx);
   if (tid == 0 && total < n) bad = 1;
   if (bad) atomicOr(err, 2u);
 }
@@ -1412,9 +1435,13 @@ __global__ void __launch_bounds__(kUnpackBlock) k_unpack_streams(const uint8_t *
                                                                 uint32_t *subc, StreamPtrs outp) {
   unpack_stream(blockIdx.x, in, up, sub, subc, outp);
 }
+// blockIdx.x is the container and 3 - blockIdx.y the stream: consecutive
+// work-groups go to different XCDs, so each XCD gets every stream kind
+// (with the stream as the fast index, the long residual streams all landed
+// on two of the eight), and the residual streams, the longest, start first.
 __global__ void __launch_bounds__(kUnpackBlock) k_unpack_streams_b(const UnpackJob *jobs) {
-  const UnpackJob &J = jobs[blockIdx.y];
-  unpack_stream(blockIdx.x, J.in, J.up, J.sub, J.subc, J.sp);
+  const UnpackJob &J = jobs[blockIdx.x];
+  unpack_stream(3 - (int)blockIdx.y, J.in, J.up, J.sub, J.subc, J.sp);
 }
 
 __global__ void __launch_bounds__(kUnpackBlock) k_unpack_frame(UnpackPlan *up, StreamPtrs sp, FrameDev f,
@@ -1554,7 +1581,7 @@ hipError_t launch_frame_jobs(const PackJob &j0, const PackJob *jobs, int n, cons
   const size_t sh = 1024 + 4 * 1024 + 64 + 2 * (size_t)L.th * L.W + 64;
   hipError_t e = hipFuncSetAttribute((const void *)k_pack_frame, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pack_frame, dim3(L.TR, n), dim3(kPackBlock), sh, st, j0, jobs);
+  hipLaunchKernelGGL(k_pack_frame, dim3(n, L.TR), dim3(kPackBlock), sh, st, j0, jobs);
   hipLaunchKernelGGL(k_pack_done, dim3((n + 255) / 256), dim3(256), 0, st, j0, jobs, n);
   return hipGetLastError();
 }
@@ -1788,7 +1815,7 @@ pc_status pc_unpack_batch(pc_ctx *ctx, int32_t n, const void *const *data, const
       hipStreamSynchronize(st) != hipSuccess)
     return set_error(PC_ERR_DEVICE, "job table upload failed");
   hipLaunchKernelGGL(k_unpack_plan_b, dim3(n), dim3(64), 0, st, (const UnpackJob *)dj);
-  hipLaunchKernelGGL(k_unpack_streams_b, dim3(4, n), dim3(kUnpackBlock), 0, st, (const UnpackJob *)dj);
+  hipLaunchKernelGGL(k_unpack_streams_b, dim3(n, 4), dim3(kUnpackBlock), 0, st, (const UnpackJob *)dj);
   for (int pass = 0; pass < 2; pass++)
     hipLaunchKernelGGL(k_unpack_frame_b, dim3(n), dim3(kUnpackBlock), 0, st, (const UnpackJob *)dj, pass, L.H, L.W,
                        L.th, L.tw);

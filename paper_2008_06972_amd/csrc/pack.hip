@@ -786,7 +786,7 @@ __device__ void unpack_plan(const uint8_t *in, uint64_t n_in, UnpackPlan *up, co
   }
 }
 
-constexpr int kFastBits = 10;               // code words this short decode with one table lookup
+constexpr int kFastBits = 13;               // code words this short decode with one table lookup (16 KB of LDS)
 
 struct DecTab {
   uint32_t limit[kMaxLen + 1], first[kMaxLen + 1], index[kMaxLen + 1];

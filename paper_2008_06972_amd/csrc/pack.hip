@@ -703,7 +703,7 @@ __device__ __forceinline__ uint32_t rd_u32(const uint8_t *p) {
 // table (a counting sort of the symbols by length).  Called by every thread
 // of the group.
 __device__ void unpack_plan(const uint8_t *in, uint64_t n_in, UnpackPlan *up, const uint64_t *caps) {
-  __shared__ uint8_t lens[4][256];
+  __shared__ __align__(4) uint8_t lens[4][256];
   __shared__ uint64_t tab_at[4];
   __shared__ int ok;
   const int tid = threadIdx.x;
@@ -754,34 +754,47 @@ __device__ void unpack_plan(const uint8_t *in, uint64_t n_in, UnpackPlan *up, co
     lens[q][sym] = up->nbytes[q] ? (uint8_t)((in[tab_at[q] + sym / 2] >> (4 * (sym & 1))) & 15) : (uint8_t)0;
   }
   __syncthreads();
-  if (tid < 4 && up->nbytes[tid]) {
-    const int q = tid;
-    uint32_t count[kMaxLen + 1] = {0};
+  // canonical code tables, one stream at a time by the wavefront: lane l
+  // holds the lengths of symbols 4l .. 4l + 3, and for each length in turn
+  // a wavefront scan of the lanes' counts places those symbols in symbol
+  // order after the shorter ones (the canonical order) and gives the count
+  // of the length, from which the first code, index and limit follow
+  const int lane = tid & 63;
+  for (int q = 0; q < 4 && tid < 64; q++) {
+    if (!up->nbytes[q]) continue;
+    const uint32_t l4 = reinterpret_cast<const uint32_t *>(lens[q])[lane];
+    uint32_t code = 0, idx = 0, used = 0, c1 = 0;
     uint64_t kraft = 0;
-    int used = 0;
-    for (int sym = 0; sym < 256; sym++) {
-      const int L = lens[q][sym];
-      count[L]++;
-      if (L) {
-        kraft += 1ull << (kMaxLen - L);
-        used++;
-      }
-    }
-    // a complete code, or one symbol coded with one bit
-    if (!(kraft == (1ull << kMaxLen) || (used == 1 && count[1] == 1))) atomicOr(&up->err, 1u);
-    uint32_t code = 0, idx = 0, pos[kMaxLen + 1];
     for (int L = 1; L <= kMaxLen; L++) {
-      up->first[q][L] = code;
-      up->index[q][L] = idx;
-      up->limit[q][L] = (code + count[L]) << (kMaxLen - L);
-      pos[L] = idx;
-      idx += count[L];
-      code = (code + count[L]) << 1;
+      uint32_t mine = 0;
+#pragma unroll
+      for (int j = 0; j < 4; j++) mine += ((l4 >> (8 * j)) & 255u) == (uint32_t)L ? 1u : 0u;
+      uint32_t x = mine;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)x, o, 64);
+        if (lane >= o) x += y;
+      }
+      const uint32_t total = (uint32_t)__shfl((int)x, 63, 64);
+      uint32_t at = idx + x - mine;
+#pragma unroll
+      for (int j = 0; j < 4; j++)
+        if (((l4 >> (8 * j)) & 255u) == (uint32_t)L) up->sorted[q][at++] = (uint8_t)(4 * lane + j);
+      if (lane == 0) {
+        up->first[q][L] = code;
+        up->index[q][L] = idx;
+        up->limit[q][L] = (code + total) << (kMaxLen - L);
+      }
+      kraft += (uint64_t)total << (kMaxLen - L);
+      used += total;
+      if (L == 1) c1 = total;
+      idx += total;
+      code = (code + total) << 1;
     }
-    up->limit[q][0] = 0;
-    for (int sym = 0; sym < 256; sym++) {
-      const int L = lens[q][sym];
-      if (L) up->sorted[q][pos[L]++] = (uint8_t)sym;
+    if (lane == 0) {
+      up->limit[q][0] = 0;
+      // a complete code, or one symbol coded with one bit
+      if (!(kraft == (1ull << kMaxLen) || (used == 1 && c1 == 1))) atomicOr(&up->err, 1u);
     }
   }
 }
